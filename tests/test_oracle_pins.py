@@ -1,0 +1,385 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+Each test names what fixes the expected value: a textbook closed form, a
+first-principles derivation from the P-SV equations of motion (matrix
+exponential propagators, an independent formulation), an algebraic identity,
+a physical limit, or an invariance.  A dropped term, a wrong sign or index, or
+a transposed block in the oracle fails at least one of them.
+"""
+import math
+
+import mpmath as mp
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import oracle as O
+import workloads as WL
+
+
+# ---------------------------------------------------------------------------
+# Independent references
+# ---------------------------------------------------------------------------
+def rayleigh_speed(alpha, beta):
+    """Rayleigh-wave speed of a homogeneous half-space: c = beta sqrt(xi), xi the
+    root in (0, 1) of the rationalised Rayleigh equation
+    xi^3 - 8 xi^2 + (24 - 16 b) xi - 16 (1 - b) = 0 with b = beta^2/alpha^2."""
+    b = (beta / alpha) ** 2
+    roots = np.roots([1.0, -8.0, 24.0 - 16.0 * b, -16.0 * (1.0 - b)])
+    real = [r.real for r in roots if abs(r.imag) < 1e-12 and 0.0 < r.real < 1.0]
+    assert len(real) == 1
+    return beta * math.sqrt(real[0])
+
+
+def psv_system(k, c, alpha, beta, rho):
+    """Real first-order P-SV system v' = A v, z positive down, for the state
+    (u_x, -i u_z, tau_xz, -i tau_zz) of a plane wave exp(i(k x - k c t))."""
+    mu = rho * beta ** 2
+    lam = rho * alpha ** 2 - 2.0 * mu
+    M = lam + 2.0 * mu
+    w2 = (k * c) ** 2
+    A = np.zeros((4, 4))
+    A[0, 1] = k
+    A[0, 2] = 1.0 / mu
+    A[1, 0] = -k * lam / M
+    A[1, 3] = 1.0 / M
+    A[2, 0] = -rho * w2 + k * k * 4.0 * mu * (lam + mu) / M
+    A[2, 3] = k * lam / M
+    A[3, 1] = -rho * w2
+    A[3, 2] = -k
+    return A
+
+
+def layer_stiffness_from_propagator(k, c, h, alpha, beta, rho):
+    """Loads on a layer's faces vs its face displacements, from the transfer
+    matrix exp(A h): top load = -traction(0), bottom load = +traction(h)."""
+    P = sla.expm(psv_system(k, c, alpha, beta, rho) * h)
+    Puu, Put, Ptu, Ptt = P[:2, :2], P[:2, 2:], P[2:, :2], P[2:, 2:]
+    iPut = np.linalg.inv(Put)
+    return np.block([[iPut @ Puu, -iPut], [Ptu - Ptt @ iPut @ Puu, Ptt @ iPut]])
+
+
+def halfspace_stiffness_from_eigvecs(k, c, alpha, beta, rho):
+    """Load on a half-space's top face vs its displacement, from the two
+    decaying eigen-solutions of A (valid for c < beta)."""
+    ev, V = np.linalg.eig(psv_system(k, c, alpha, beta, rho))
+    order = np.argsort(ev.real)[:2]
+    Vd = V[:, order].real
+    return -(Vd[2:, :] @ np.linalg.inv(Vd[:2, :]))
+
+
+# The oracle's vertical degree of freedom has the opposite sign to the
+# propagator's; the similarity diag(1, -1, ...) leaves every determinant unchanged.
+FLIP4 = np.diag([1.0, -1.0, 1.0, -1.0])
+FLIP2 = np.diag([1.0, -1.0])
+
+
+def mp_secular(k, c, model):
+    """Rayleigh secular function of a layered half-space from mpmath propagators:
+    det(P_tu + H P_uu) with P the surface-to-half-space transfer matrix applied
+    to traction-free surface states and H the half-space's load/displacement
+    matrix.  Independent of the stiffness-matrix formulas."""
+    def sysmat(alpha, beta, rho):
+        k_, c_, a_, b_, r_ = map(mp.mpf, (k, c, alpha, beta, rho))
+        mu = r_ * b_ ** 2
+        lam = r_ * a_ ** 2 - 2 * mu
+        M = lam + 2 * mu
+        w2 = (k_ * c_) ** 2
+        A = mp.zeros(4, 4)
+        A[0, 1] = k_
+        A[0, 2] = 1 / mu
+        A[1, 0] = -k_ * lam / M
+        A[1, 3] = 1 / M
+        A[2, 0] = -r_ * w2 + k_ * k_ * 4 * mu * (lam + mu) / M
+        A[2, 3] = k_ * lam / M
+        A[3, 1] = -r_ * w2
+        A[3, 2] = -k_
+        return A
+    N = model.n_layers
+    P = mp.eye(4)
+    for j in range(N):
+        P = mp.expm(sysmat(model.alpha[j], model.beta[j], model.rho[j]) * mp.mpf(model.h[j])) * P
+    ev, V = mp.eig(sysmat(model.alpha[N], model.beta[N], model.rho[N]))
+    order = sorted(range(4), key=lambda i: mp.re(ev[i]))[:2]
+    Vd = mp.matrix(4, 2)
+    for a, i in enumerate(order):
+        for r in range(4):
+            Vd[r, a] = mp.re(V[r, i])
+    H = -Vd[2:4, 0:2] * mp.inverse(Vd[0:2, 0:2])
+    return mp.det(P[2:4, 0:2] + H * P[0:2, 0:2])
+
+
+def mp_root(k, lo, hi, model, steps=34):
+    f_lo = mp_secular(k, lo, model)
+    lo, hi = mp.mpf(lo), mp.mpf(hi)
+    for _ in range(steps):
+        mid = (lo + hi) / 2
+        f_mid = mp_secular(k, mid, model)
+        if mp.sign(f_mid) == mp.sign(f_lo):
+            lo, f_lo = mid, f_mid
+        else:
+            hi = mid
+    return float((lo + hi) / 2)
+
+
+def halfspace_model(alpha, beta, rho):
+    return WL.Model(np.zeros(0), np.array([alpha]), np.array([beta]), np.array([rho]))
+
+
+# ---------------------------------------------------------------------------
+# P1: homogeneous half-space, closed-form Rayleigh root
+# ---------------------------------------------------------------------------
+def test_rayleigh_closed_form_at_quarter_poisson():
+    # nu = 0.25 (alpha = sqrt(3) beta): c_R = beta sqrt(2 - 2/sqrt(3)).
+    assert rayleigh_speed(math.sqrt(3.0), 1.0) == pytest.approx(math.sqrt(2 - 2 / math.sqrt(3)), rel=1e-13)
+    assert math.sqrt(2 - 2 / math.sqrt(3)) == pytest.approx(0.91940168, abs=1e-8)
+
+
+@pytest.mark.parametrize("beta,nu,lam", [(400.0, 0.25, 5.0), (400.0, 0.25, 0.3),
+                                         (150.0, 0.33, 12.0), (250.0, 0.40, 80.0)])
+def test_halfspace_root_matches_rayleigh_equation(beta, nu, lam):
+    alpha = float(WL.alpha_from_poisson(np.array([beta]), np.array([nu]))[0])
+    cR = rayleigh_speed(alpha, beta)
+    c_test = WL.uniform_grid(0.5 * beta, 0.01, int(0.6 * beta / 0.01))
+    p = O.dispersion_point(lam, c_test, halfspace_model(alpha, beta, 1900.0))
+    assert p.status == O.STATUS_FOUND
+    # the pick is the upper end of the grid bracket that holds the root
+    assert c_test[p.idx - 1] < cR <= c_test[p.idx]
+    assert p.c_t == c_test[p.idx]
+    assert abs(p.c_ref - cR) / cR <= 1e-9
+
+
+def test_halfspace_det_closed_form():
+    # det H = -(k mu)^2 [(1 + s^2)^2 - 4 r s] / (1 - r s) for real r, s.
+    k, alpha, beta, rho = 0.9, 700.0, 400.0, 2000.0
+    for c in (100.0, 250.0, 380.0):
+        r = math.sqrt(1 - (c / alpha) ** 2)
+        s = math.sqrt(1 - (c / beta) ** 2)
+        mu = rho * beta ** 2
+        want = -(k * mu) ** 2 * ((1 + s * s) ** 2 - 4 * r * s) / (1 - r * s)
+        got = np.linalg.det(O.halfspace_matrix(k, np.array(c), alpha, beta, rho))
+        assert abs(got.imag) == 0.0
+        assert got.real == pytest.approx(want, rel=1e-12)
+
+
+@pytest.mark.parametrize("c", [450.0, 520.0, 650.0, 800.0, 1000.0])
+def test_halfspace_det_and_sign_above_beta(c):
+    # Above beta s = i sqrt(c^2/beta^2 - 1) (and above alpha r = i sqrt(...)):
+    # det H is complex and the search uses the sign of its real part.
+    k, alpha, beta, rho = 1.3, 700.0, 400.0, 2000.0
+    def psqrt(x):
+        return complex(math.sqrt(x), 0.0) if x >= 0 else complex(0.0, math.sqrt(-x))
+    r, s = psqrt(1 - (c / alpha) ** 2), psqrt(1 - (c / beta) ** 2)
+    mu = rho * beta ** 2
+    want = -(k * mu) ** 2 * ((1 + s * s) ** 2 - 4 * r * s) / (1 - r * s)
+    if c < alpha:                      # beta < c < alpha: r real, s imaginary
+        assert abs(want.imag) > 1e-6 * abs(want)
+    got = np.linalg.det(O.halfspace_matrix(k, np.array(c), alpha, beta, rho))
+    assert abs(got - want) <= 1e-12 * abs(want)
+    m = halfspace_model(alpha, beta, rho)
+    assert int(O.det_sign(k, c, m)[0]) == int(np.sign(want.real))
+
+
+# ---------------------------------------------------------------------------
+# First principles: layer and half-space matrices from the P-SV equations
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("c", [60.0, 150.0, 199.0, 260.0, 410.0, 700.0])
+@pytest.mark.parametrize("lam,h", [(7.0, 3.0), (2.0, 0.7), (30.0, 1.5)])
+def test_layer_matrix_matches_propagator(c, lam, h):
+    # c spans c < beta, beta < c < alpha (s imaginary) and c > alpha (both imaginary)
+    k = 2 * math.pi / lam
+    alpha, beta, rho = 520.0, 200.0, 1900.0
+    Ko = O.layer_matrix(k, np.array(c), h, alpha, beta, rho)
+    assert np.all(Ko.imag == 0.0)
+    Kp = FLIP4 @ layer_stiffness_from_propagator(k, c, h, alpha, beta, rho) @ FLIP4
+    scale = np.max(np.abs(Kp))
+    assert np.max(np.abs(Ko.real - Kp)) <= 1e-9 * scale
+
+
+@pytest.mark.parametrize("c", [50.0, 200.0, 355.0])
+def test_halfspace_matrix_matches_eigensolutions(c):
+    k, alpha, beta, rho = 2 * math.pi / 9.0, 650.0, 360.0, 2100.0
+    Ho = O.halfspace_matrix(k, np.array(c), alpha, beta, rho)
+    Hp = FLIP2 @ halfspace_stiffness_from_eigvecs(k, c, alpha, beta, rho) @ FLIP2
+    assert np.max(np.abs(Ho - Hp)) <= 1e-10 * np.max(np.abs(Hp))
+
+
+# ---------------------------------------------------------------------------
+# P2: condensing a layer onto an identical half-space gives the half-space
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("c", [80.0, 300.0, 390.0, 450.0, 760.0])
+def test_condensation_identity(c):
+    # c > beta (=400) makes H complex; c > alpha (=692.8) makes r imaginary too.
+    k, h = 2 * math.pi / 6.0, 2.5
+    alpha, beta, rho = 400.0 * math.sqrt(3.0), 400.0, 2000.0
+    KL = O.layer_matrix(k, np.array(c), h, alpha, beta, rho)
+    H = O.halfspace_matrix(k, np.array(c), alpha, beta, rho)
+    P, Q, R = KL[:2, :2], KL[:2, 2:], KL[2:, 2:]
+    cond = P - Q @ np.linalg.solve(R + H, Q.T)
+    assert np.max(np.abs(cond - H)) <= 1e-9 * np.max(np.abs(H))
+
+
+# ---------------------------------------------------------------------------
+# P3: identical layers over an identical half-space behave as the half-space
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("lam", [1.0, 7.0, 50.0])
+def test_identical_layers_reduce_to_halfspace(lam):
+    beta, rho = 400.0, 2000.0
+    alpha = math.sqrt(3.0) * beta
+    N = 3
+    m = WL.Model(np.array([2.0, 0.7, 4.0]), np.full(N + 1, alpha), np.full(N + 1, beta), np.full(N + 1, rho))
+    c_test = WL.uniform_grid(300.0, 0.01, 8001)
+    p = O.dispersion_point(lam, c_test, m)
+    p0 = O.dispersion_point(lam, c_test, halfspace_model(alpha, beta, rho))
+    assert p.idx == p0.idx
+    assert abs(p.c_ref - rayleigh_speed(alpha, beta)) / p.c_ref < 1e-9
+
+
+# ---------------------------------------------------------------------------
+# P4 / P5: short- and long-wavelength limits of a layer over a half-space
+# ---------------------------------------------------------------------------
+def _layer_over_halfspace():
+    beta = np.array([150.0, 400.0])
+    return WL.Model(np.array([2.0]), math.sqrt(3.0) * beta, beta, np.array([1850.0, 2000.0]))
+
+
+@pytest.mark.parametrize("lam", [0.05, 0.1, 0.2])
+def test_short_wavelength_limit(lam):
+    m = _layer_over_halfspace()
+    c_top = rayleigh_speed(m.alpha[0], m.beta[0])
+    p = O.dispersion_point(lam, WL.uniform_grid(100.0, 0.01, 30001), m)
+    assert abs(p.c_ref - c_top) / c_top < 1e-8
+
+
+def test_long_wavelength_limit_is_monotone():
+    m = _layer_over_halfspace()
+    c_hs = rayleigh_speed(m.alpha[1], m.beta[1])
+    grid = WL.uniform_grid(100.0, 0.01, 30001)
+    errs = [c_hs - O.dispersion_point(lam, grid, m).c_ref for lam in (20.0, 200.0, 2000.0, 20000.0)]
+    assert all(e > 0 for e in errs)
+    assert all(a > b for a, b in zip(errs, errs[1:]))
+    assert errs[-1] / c_hs < 1e-3
+
+
+# ---------------------------------------------------------------------------
+# Roots against an independent propagator secular function (mpmath, 30 digits)
+# ---------------------------------------------------------------------------
+def test_roots_match_propagator_secular_function():
+    mp.mp.dps = 30
+    rng = np.random.Generator(np.random.PCG64(7))
+    m = WL.increasing_profile(rng, 4)
+    m_inv = WL.increasing_profile(rng, 3)
+    m_inv.beta[1] = 0.7 * m_inv.beta[0]          # a low-velocity layer
+    m_inv.alpha[1] = 1.9 * m_inv.beta[1]
+    c_test = WL.uniform_grid(50.0, 0.05, 20001)
+    for model, lam in ((m, 1.5), (m, 12.0), (m_inv, 4.0)):
+        p = O.dispersion_point(lam, c_test, model)
+        assert p.status == O.STATUS_FOUND
+        k = 2 * math.pi / lam
+        assert mp.sign(mp_secular(k, c_test[p.idx - 1], model)) != mp.sign(mp_secular(k, c_test[p.idx], model))
+        want = mp_root(k, c_test[p.idx - 1], c_test[p.idx], model)
+        assert abs(p.c_ref - want) / want < 2e-9
+
+
+# ---------------------------------------------------------------------------
+# P6: scaling invariances
+# ---------------------------------------------------------------------------
+def test_scaling_invariances():
+    wl = WL.two_layer_case()
+    m, lams, c = wl.models[0], wl.lambdas[0][::3], wl.c_test
+    base = [O.dispersion_point(l, c, m, refine=False).idx for l in lams]
+    g = 1.7
+    # lengths: (h, lambda) -> g (h, lambda)
+    mh = m.copy(); mh.h = g * m.h
+    assert [O.dispersion_point(g * l, c, mh, refine=False).idx for l in lams] == base
+    # velocities: (alpha, beta, c_test) -> g (...)
+    mv = m.copy(); mv.alpha = g * m.alpha; mv.beta = g * m.beta
+    assert [O.dispersion_point(l, g * c, mv, refine=False).idx for l in lams] == base
+    # density: rho -> g rho multiplies det by g^(2(N+1)) > 0
+    mr = m.copy(); mr.rho = g * m.rho
+    assert [O.dispersion_point(l, c, mr, refine=False).idx for l in lams] == base
+
+
+# ---------------------------------------------------------------------------
+# P8: structure of the assembled matrix
+# ---------------------------------------------------------------------------
+def test_structure_symmetric_real_heptadiagonal():
+    rng = np.random.Generator(np.random.PCG64(3))
+    m = WL.increasing_profile(rng, 6)
+    k = 2 * math.pi / 5.0
+    c = np.array([60.0, 120.0, 0.99 * m.beta[-1], 1.2 * m.beta[-1]])
+    K = O.stiffness_matrix(k, c, m.h, m.alpha, m.beta, m.rho)
+    n = 2 * (m.n_layers + 1)
+    assert K.shape == (4, n, n)
+    assert np.array_equal(K, np.swapaxes(K, -1, -2))
+    assert np.all(K[:3].imag == 0.0)            # c below the half-space beta
+    assert np.any(K[3].imag != 0.0)             # above it the half-space block is complex
+    i, j = np.indices((n, n))
+    assert np.all(K[:, np.abs(i - j) > 3] == 0.0)
+    assert np.any(K[:, np.abs(i - j) == 3] != 0.0)
+
+
+# ---------------------------------------------------------------------------
+# Removable singularities at c = beta_j on the grid
+# ---------------------------------------------------------------------------
+def test_removable_singularity_on_grid_is_finite_and_continuous():
+    wl = WL.two_layer_case()
+    m = wl.models[0]
+    k = 2 * math.pi / 10.0
+    for cs in (150.0, 250.0):
+        assert cs in wl.c_test
+        s0, _, l0 = O.det_sign_logabs(k, np.array([cs]), m)
+        sl, _, ll = O.det_sign_logabs(k, np.array([cs - 1e-6, cs + 1e-6]), m)
+        assert s0[0] == sl[0] == sl[1]
+        assert abs(l0[0] - ll[0]) < 1e-6 and abs(l0[0] - ll[1]) < 1e-6
+    # no false pick at the grid point c = 150 = beta_1 for long wavelengths
+    p = O.dispersion_point(20.0, wl.c_test, m, refine=False)
+    assert wl.c_test[p.idx] != 150.0
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 1's scan semantics, and its not-found case
+# ---------------------------------------------------------------------------
+def test_first_change_index_semantics():
+    f = O.first_change_index
+    assert f([1, 1, 1, -1, -1]) == 3
+    assert f([-1, -1, -1]) == -1
+    assert f([1, 0, 0, -1]) == 1           # a zero determinant differs from +1
+    assert f([0, 0, 1]) == 2
+    assert f([1, 1], prev=-1) == 0        # carry from the previous batch
+    assert f([]) == -1
+
+
+def test_batched_scan_equals_whole_grid_scan():
+    wl = WL.two_layer_case()
+    m = wl.models[0]
+    for lam in (1.0, 9.0, 40.0):
+        k = 2 * math.pi / lam
+        sig = O.det_sign(k, wl.c_test, m)
+        d = np.nonzero(sig[1:] != sig[:-1])[0]
+        want = int(d[0]) + 1
+        for batch in (1, 7, 64, 1000):
+            assert O.first_sign_change(k, wl.c_test, m, batch=batch)[0] == want
+
+
+def test_not_found_below_root():
+    wl = WL.two_layer_case()
+    p = O.dispersion_point(1.0, WL.uniform_grid(50.0, 0.5, 100), wl.models[0])
+    assert p.idx == -1 and p.status == O.STATUS_NOT_FOUND and math.isnan(p.c_t) and math.isnan(p.c_ref)
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 2 (misfit) and the FP64 noise band
+# ---------------------------------------------------------------------------
+def test_misfit_definition():
+    assert O.misfit(np.array([1.0, 2.0, 3.0]), np.array([2.0, 2.0, 4.0])) == pytest.approx((0.5 + 0.0 + 0.25) / 3)
+
+
+def test_noise_band_only_at_the_root():
+    beta = 400.0
+    alpha = math.sqrt(3.0) * beta
+    m = halfspace_model(alpha, beta, 2000.0)
+    cR = rayleigh_speed(alpha, beta)
+    assert O.in_noise_band(3.0, cR, m)
+    assert not O.in_noise_band(3.0, cR + 0.01, m)
+    assert not O.in_noise_band(3.0, cR - 0.01, m)

@@ -1,0 +1,213 @@
+"""Seeded synthetic inputs for the dispersion-curve workloads.
+
+This module only draws layered earth models, wavelength lists and test-velocity
+grids.  It holds none of the dispersion arithmetic (no stiffness entries, no
+determinants, no search), so both the CPU oracle and the HIP path may use it
+without sharing any of the method's computation.
+
+The paper's own datasets (a 40-wavelength "variable" experimental curve and a
+"uniform" curve, Section 3) are not available; these recipes stand in for them
+with the paper's scales: up to ~100 wavelengths and ~1000 test velocities per
+curve with N <= 10 layers typical (Section 2.1), 40-entry variable curves and
+1000-wavelength uniform curves (Section 3.2), grown to the fine-scale and batched
+sizes that one MI355X is sized for.
+
+Every generator uses numpy's PCG64 with a fixed seed and a fixed draw order.
+Units: thickness h and wavelength in m, velocities in m/s, density in kg/m^3.
+Layer arrays: h has N entries; alpha, beta, rho have N+1 entries, the last
+being the half-space.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List
+
+import numpy as np
+
+
+@dataclass
+class Model:
+    """One layered model: N finite layers over a half-space."""
+
+    h: np.ndarray      # [N]   thickness (m)
+    alpha: np.ndarray  # [N+1] P-wave velocity (m/s)
+    beta: np.ndarray   # [N+1] S-wave velocity (m/s)
+    rho: np.ndarray    # [N+1] density (kg/m^3)
+
+    @property
+    def n_layers(self) -> int:
+        return int(self.h.shape[0])
+
+    def copy(self) -> "Model":
+        return Model(self.h.copy(), self.alpha.copy(), self.beta.copy(), self.rho.copy())
+
+
+@dataclass
+class Workload:
+    """Models with their wavelengths and one shared test-velocity grid."""
+
+    name: str
+    models: List[Model]
+    lambdas: List[np.ndarray]      # per model, wavelengths (m)
+    c_test: np.ndarray             # ascending test velocities (m/s), FP64
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_lambda_total(self) -> int:
+        return int(sum(len(l) for l in self.lambdas))
+
+
+def uniform_grid(c_min: float, dc: float, n: int) -> np.ndarray:
+    """c_i = c_min + i*dc evaluated in FP64 per index (never accumulated)."""
+    return c_min + dc * np.arange(n, dtype=np.float64)
+
+
+def alpha_from_poisson(beta: np.ndarray, nu: np.ndarray) -> np.ndarray:
+    """P velocity of an isotropic solid with S velocity beta and Poisson ratio nu."""
+    return beta * np.sqrt((2.0 - 2.0 * nu) / (1.0 - 2.0 * nu))
+
+
+def log_spaced(lo: float, hi: float, n: int) -> np.ndarray:
+    if n == 1:
+        return np.array([lo], dtype=np.float64)
+    return lo * (hi / lo) ** (np.arange(n, dtype=np.float64) / (n - 1))
+
+
+# --------------------------------------------------------------------------
+# The two-layer model used for the small worked case.
+# --------------------------------------------------------------------------
+def two_layer_model() -> Model:
+    beta = np.array([150.0, 250.0, 400.0])
+    return Model(h=np.array([2.0, 4.0]),
+                 alpha=np.sqrt(3.0) * beta,
+                 beta=beta,
+                 rho=np.array([1850.0, 1900.0, 2000.0]))
+
+
+def two_layer_case() -> Workload:
+    """2 layers over a half-space, 30 wavelengths log-spaced 1-40 m,
+    c_test 50-450 m/s at 0.5 m/s (801 values)."""
+    return Workload("two_layer_30lam_801c", [two_layer_model()],
+                    [log_spaced(1.0, 40.0, 30)], uniform_grid(50.0, 0.5, 801))
+
+
+# --------------------------------------------------------------------------
+# Velocity-increasing profiles (the fine-scale and batched recipes).
+# --------------------------------------------------------------------------
+def increasing_profile(rng: np.random.Generator, n_layers: int,
+                       poisson: bool = True,
+                       rho_lo: float = 1700.0, rho_hi: float = 2200.0) -> Model:
+    """Draw order: h[N], beta0, N-1 increments, nu[N+1] (or none), rho[N+1].
+
+    beta_0 ~ U(100, 200); beta_{j+1} = beta_j + U(5, 40); half-space beta =
+    last layer beta + 100.  With poisson=True alpha comes from nu ~ U(0.25, 0.4)
+    per layer and for the half-space; otherwise alpha = sqrt(3) beta.
+    """
+    N = n_layers
+    h = rng.uniform(0.5, 3.0, size=N)
+    beta = np.empty(N + 1)
+    beta[0] = rng.uniform(100.0, 200.0)
+    inc = rng.uniform(5.0, 40.0, size=max(N - 1, 0))
+    for j in range(1, N):
+        beta[j] = beta[j - 1] + inc[j - 1]
+    beta[N] = (beta[N - 1] if N > 0 else beta[0]) + 100.0
+    if poisson:
+        nu = rng.uniform(0.25, 0.4, size=N + 1)
+        alpha = alpha_from_poisson(beta, nu)
+    else:
+        alpha = np.sqrt(3.0) * beta
+    rho = rng.uniform(rho_lo, rho_hi, size=N + 1)
+    return Model(h, alpha, beta, rho)
+
+
+def fine_scale_case(seed: int = 2) -> Workload:
+    """20 layers, 1000 wavelengths log-spaced 1-100 m, c 50-1200 m/s at 0.01
+    m/s (115,001 values), plain FP64."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    m = increasing_profile(rng, 20)
+    return Workload("fine_scale_N20_1000lam_115001c", [m],
+                    [log_spaced(1.0, 100.0, 1000)], uniform_grid(50.0, 0.01, 115001))
+
+
+def apply_inversion(rng: np.random.Generator, m: Model, prob: float = 0.15) -> bool:
+    """With probability prob, pick j ~ U{1..N-1} and make layer j slower than
+    the layer above it: beta_j = beta_{j-1} * U(0.6, 0.9), alpha_j keeping
+    layer j's alpha/beta ratio.  Draw order: one uniform, then j, then the
+    factor (the last two only when an inversion is applied)."""
+    u = rng.uniform()
+    N = m.n_layers
+    if u >= prob or N < 2:
+        return False
+    j = int(rng.integers(1, N))            # 1..N-1
+    f = rng.uniform(0.6, 0.9)
+    ratio = m.alpha[j] / m.beta[j]
+    m.beta[j] = m.beta[j - 1] * f
+    m.alpha[j] = ratio * m.beta[j]
+    return True
+
+
+def batch_case(n_models: int = 4096, seed: int = 4,
+               n_lo: int = 3, n_hi: int = 30,
+               w_lo: int = 50, w_hi: int = 500) -> Workload:
+    """Batch of seeded models of uneven sizes: N ~ U{3..30}, W ~ U{50..500}
+    wavelengths log-spaced 1-80 m, c 50-1000 m/s at 0.05 m/s (19,001 values),
+    about 15% with one low-velocity inversion layer."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    models, lams, inverted = [], [], []
+    for _ in range(n_models):
+        N = int(rng.integers(n_lo, n_hi + 1))
+        W = int(rng.integers(w_lo, w_hi + 1))
+        m = increasing_profile(rng, N)
+        inverted.append(apply_inversion(rng, m))
+        models.append(m)
+        lams.append(log_spaced(1.0, 80.0, W))
+    return Workload(f"batch_{n_models}models_19001c", models, lams,
+                    uniform_grid(50.0, 0.05, 19001), meta={"inverted": inverted})
+
+
+# --------------------------------------------------------------------------
+# Random-walk chains for the serving workload.
+# --------------------------------------------------------------------------
+@dataclass
+class Chain:
+    model: Model
+    lambdas: np.ndarray
+
+
+def chain_bases(n_chains: int = 64, seed: int = 5) -> List[Chain]:
+    """Chain start points: N ~ U{5..25}, W ~ U{30..300} wavelengths log-spaced
+    1-40 m, beta as in the velocity-increasing recipe, alpha = sqrt(3) beta,
+    rho ~ U(1850, 2000)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for _ in range(n_chains):
+        N = int(rng.integers(5, 26))
+        W = int(rng.integers(30, 301))
+        m = increasing_profile(rng, N, poisson=False, rho_lo=1850.0, rho_hi=2000.0)
+        out.append(Chain(m, log_spaced(1.0, 40.0, W)))
+    return out
+
+
+def chain_step(rng: np.random.Generator, m: Model, sd: float = 0.02) -> Model:
+    """One random-walk step: every beta_j and h_j times (1 + N(0, sd));
+    alpha = sqrt(3) beta is kept.  Draw order: beta[N+1] then h[N]."""
+    out = m.copy()
+    out.beta = m.beta * (1.0 + sd * rng.standard_normal(m.beta.shape[0]))
+    out.h = m.h * (1.0 + sd * rng.standard_normal(m.h.shape[0]))
+    out.beta = np.maximum(out.beta, 1.0)
+    out.h = np.maximum(out.h, 1e-3)
+    out.alpha = np.sqrt(3.0) * out.beta
+    return out
+
+
+def serving_grid() -> np.ndarray:
+    """Per-request grid: 50-1000 m/s at 0.1 m/s (9,501 values)."""
+    return uniform_grid(50.0, 0.1, 9501)
+
+
+def poisson_arrivals(rate: float, duration: float, seed: int = 55) -> np.ndarray:
+    """Arrival times (s) of a Poisson process with the given rate."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = int(rate * duration * 1.5) + 16
+    t = np.cumsum(rng.exponential(1.0 / rate, size=n))
+    return t[t < duration]
