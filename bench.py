@@ -1,0 +1,249 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the dispersion-curve hot path on one MI355X.
+
+A step is one whole dispersion-curve job through the C ABI: staging and
+precompute, work ordering, the early-exit sweep with its FP64 refinement, and
+the results in HBM.  Inputs are resident in HBM before timing starts.
+
+Default workload: the 20-layer fine-scale model, 1000 wavelengths log-spaced
+1-100 m, c 50-1200 m/s at 0.01 m/s (115,001 values), plain FP64.  The split
+path (FP32 sweep + FP64 re-check + FP64 refinement) is timed on the same
+inputs and reported beside it with its root error against the FP64 path.
+
+Headline: useful determinant evaluations per second, sum over wavelengths of
+(pick index + 1), the work Algorithm 1 needs whatever the implementation.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+                       [--workload fine_scale|two_layer|batch] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "det evals/s + dispersion curves/s vs plain FP64 at 1e-6 rel; p50/p99 latency"
+FP64_PEAK_TFLOPS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+FP32_PEAK_TFLOPS = 157.3   # published, packed FP32 (packed math is not used here)
+
+
+def flops_per_eval(n_layers: float) -> float:
+    """Algorithmic FP operations of one determinant sign (add/sub/mul = 1,
+    a fused multiply-add = 2, each sqrt/division/expm1/sincos = 1):
+    per layer 101 (element entries 67 incl. k h, block elimination 34), plus 48
+    for the half-space block and the final complex 2x2 determinant."""
+    return 101.0 * n_layers + 48.0
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------- workloads --
+def make_workload(name: str):
+    import workloads as WL
+    if name == "fine_scale":
+        return WL.fine_scale_case()
+    if name == "two_layer":
+        return WL.two_layer_case()
+    if name == "batch":
+        return WL.batch_case()
+    raise SystemExit(f"unknown workload {name}")
+
+
+class DeviceJob:
+    """Inputs and outputs of one workload resident on the GPU."""
+
+    def __init__(self, wl, torch, dev):
+        import paper_2003_02256_amd as M
+        self.M, self.torch, self.wl = M, torch, wl
+        arrs = M.flatten_models(wl.models, wl.lambdas)
+        self.arrs = [torch.as_tensor(a, device=dev) for a in arrs]
+        self.c = torch.as_tensor(wl.c_test, device=dev)
+        self.W = int(arrs[-1].shape[0])
+        self.single = len(wl.models) == 1
+        f64, i32 = torch.float64, torch.int32
+        self.out = {p: (torch.empty(self.W, dtype=f64, device=dev), torch.empty(self.W, dtype=i32, device=dev),
+                        torch.empty(self.W, dtype=i32, device=dev), torch.empty(self.W, dtype=f64, device=dev))
+                    for p in (M.MASW_PREC_FP64, M.MASW_PREC_SPLIT)}
+        self.n_layers = [m.n_layers for m in wl.models]
+        self.lam_model = np.repeat(np.arange(len(wl.models)), [len(l) for l in wl.lambdas])
+
+    def run(self, ctx, prec):
+        M, a = self.M, self.arrs
+        if self.single:
+            M.masw_dispersion_curve(ctx, self.c, a[6], a[1], a[2], a[3], a[4], prec, 0, None, *self.out[prec])
+        else:
+            M.masw_dispersion_batch(ctx, self.c, *a, prec, 0, None, *self.out[prec])
+
+    def results(self, prec):
+        return tuple(o.cpu().numpy() for o in self.out[prec])
+
+
+def time_path(job, ctx, prec, steps, warmup):
+    torch, M = job.torch, job.M
+    for _ in range(warmup):
+        job.run(ctx, prec)
+    torch.cuda.synchronize()
+    sweep_ms, total_ms, stats = [], [], None
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        job.run(ctx, prec)
+        stats = M.masw_get_stats(ctx)          # synchronises the stream: one job per step
+        sweep_ms.append(stats["sweep_ms"])
+        total_ms.append(stats["total_ms"])
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    return wall, float(np.mean(sweep_ms)), float(np.mean(total_ms)), stats
+
+
+# ------------------------------------------------------------- cpu baseline --
+def _oracle_point(args):
+    import oracle as O
+    lam, c, model = args
+    p = O.dispersion_point(lam, c, model, refine=True)
+    return p.evals
+
+
+def cpu_baseline(wl, target_s: float, workers: int):
+    """The oracle (dense complex LU per determinant, FP64) on a bounded,
+    evenly spaced sample of the workload's wavelengths, on `workers` host
+    processes; returns useful evals/s."""
+    import multiprocessing as mp
+    os.environ["OMP_NUM_THREADS"] = "1"
+    lam_all = [(float(l), mi) for mi, ls in enumerate(wl.lambdas) for l in ls]
+    # ~45 us per 42x42 determinant on one core: size the sample to target_s of work
+    per_eval_s = 45e-6 * (np.mean([m.n_layers for m in wl.models]) + 1) / 21.0
+    est_depth = 0.3 * wl.c_test.shape[0]
+    n = int(max(workers, min(len(lam_all), target_s / (per_eval_s * est_depth))))
+    pick = np.unique(np.linspace(0, len(lam_all) - 1, n).round().astype(int))
+    tasks = [(lam_all[i][0], wl.c_test, wl.models[lam_all[i][1]]) for i in pick]
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        evals = pool.map(_oracle_point, tasks, chunksize=1)
+    wall = time.perf_counter() - t0
+    cpu = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"value": float(sum(evals) / wall), "unit": "useful det evals/s", "cores": workers,
+            "kind": "oracle",
+            "sample": f"{len(tasks)} of {len(lam_all)} wavelengths evenly spaced, {sum(evals)} useful evals, "
+                      f"{wall:.1f} s wall on {workers} processes ({cpu})"}
+
+
+# ---------------------------------------------------------------------- main --
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="fine_scale", choices=["fine_scale", "two_layer", "batch"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target CPU work of the oracle sample")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported (the dispersion path has no "
+              f"cross-GPU exchange and this build runs on a single MI355X)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2003_02256_amd as M
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    M.library()
+    dev = torch.device("cuda:0")
+    wl = make_workload(a.workload)
+    log(f"workload {wl.name}: {len(wl.models)} model(s), {wl.n_lambda_total} wavelengths, {wl.c_test.shape[0]} c")
+    job = DeviceJob(wl, torch, dev)
+    ctx_obj = M.Context(0, 4 << 30)
+    ctx = ctx_obj.ctx
+
+    # first call (includes module load and first-touch of the arena) vs steady state
+    t0 = time.perf_counter()
+    job.run(ctx, M.MASW_PREC_FP64)
+    torch.cuda.synchronize()
+    first_call_ms = (time.perf_counter() - t0) * 1e3
+
+    log("timing FP64 path")
+    wall64, sweep64, total64, st64 = time_path(job, ctx, M.MASW_PREC_FP64, a.steps, a.warmup)
+    r64 = job.results(M.MASW_PREC_FP64)
+    log("timing split path")
+    wall32, sweep32, total32, st32 = time_path(job, ctx, M.MASW_PREC_SPLIT, a.steps, a.warmup)
+    r32 = job.results(M.MASW_PREC_SPLIT)
+
+    idx64, idx32 = r64[1], r32[1]
+    useful = int(np.where(idx64 >= 0, idx64 + 1, wl.c_test.shape[0]).sum())
+    assert useful == st64["useful_evals"], (useful, st64["useful_evals"])
+    both = (idx64 == idx32) & (idx64 >= 0)
+    root_rel = np.abs(r32[3][both] - r64[3][both]) / r64[3][both]
+
+    # algorithmic flops of one FP64 launch: performed evaluations x F(N)
+    n_lay = np.asarray(job.n_layers)[job.lam_model]
+    nbar = float(np.average(n_lay, weights=np.where(idx64 >= 0, idx64 + 1, wl.c_test.shape[0])))
+    performed64 = st64["sweep_evals"] + st64["check_evals"] + st64["refine_evals"]
+    flops64 = performed64 * flops_per_eval(nbar)
+    achieved = flops64 / (sweep64 * 1e-3) / 1e12
+    n_curves = len(wl.models)
+
+    res = {
+        "metric": METRIC,
+        "value": useful / wall64,
+        "unit": "det evals/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": wall64 * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "models": n_curves, "wavelengths": wl.n_lambda_total,
+                   "n_c": int(wl.c_test.shape[0]), "layers_mean": nbar, "path": "plain FP64"},
+        "curves_per_s": n_curves / wall64,
+        "wavelengths_per_s": wl.n_lambda_total / wall64,
+        "useful_evals": useful,
+        "performed_evals": performed64,
+        "first_call_ms": first_call_ms,
+        "device_ms_per_step": total64,
+        "split": {
+            "value": useful / wall32, "unit": "det evals/s", "ms_per_step": wall32 * 1e3,
+            "dtype": "f32 sweep + f64 re-check/refine", "speedup_vs_fp64": wall64 / wall32,
+            "curves_per_s": n_curves / wall32,
+            "sweep_evals": st32["sweep_evals"], "check_evals": st32["check_evals"],
+            "refine_evals": st32["refine_evals"], "sweep_kernel_ms": sweep32,
+            "idx_mismatch_vs_fp64": int(np.sum((idx64 != idx32))),
+            "root_rel_err_vs_fp64_max": float(root_rel.max()) if root_rel.size else None,
+            "root_rel_err_vs_fp64_mean": float(root_rel.mean()) if root_rel.size else None,
+        },
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "kernel": f"sweep_kernel<FP64,G={st64['waves_per_item']}>",
+                     "kernel_ms": sweep64, "flops_per_launch": flops64},
+    }
+    if not a.no_cpu_baseline:
+        log("timing the CPU oracle on a sample")
+        workers = min(os.cpu_count() or 1, 16)
+        res["cpu_baseline"] = cpu_baseline(wl, a.cpu_seconds, workers)
+    ctx_obj.close()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

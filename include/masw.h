@@ -1,0 +1,199 @@
+/*
+ * masw.h -- C ABI of the MI355X dispersion-curve library.
+ *
+ * The library computes theoretical Rayleigh-wave dispersion curves of layered
+ * elastic models: for every wavelength lambda (k = 2 pi / lambda) and every
+ * test phase velocity c of an ascending grid, the sign of the determinant of
+ * the layered stiffness matrix, and the first grid velocity at which that sign
+ * changes (the paper's Algorithm 1, Section 2.1).  It adds an FP64 refinement
+ * of the root inside the bracketing grid interval.
+ *
+ * Units: lambda and h in m, alpha (P velocity), beta (S velocity) and c in
+ * m/s, rho in kg/m^3.
+ *
+ * Pointers.  Array arguments are HOST pointers unless `flags` contains
+ * MASW_DEVICE_PTRS; then every array argument (inputs and outputs) is a HIP
+ * device pointer, read and written in stream order on `stream`.  The caller
+ * owns every buffer.  The library copies host inputs into its own device
+ * memory before it returns and keeps no caller pointer after the call,
+ * except that with MASW_DEVICE_PTRS the kernels may still run on `stream`
+ * after the call returns (synchronise `stream` before reading outputs or
+ * reusing inputs).  A NULL `stream` means the context's own stream.
+ *
+ * Errors.  Every function returning int returns MASW_OK (0) or a negative
+ * MASW_E* code; nothing aborts or throws across the ABI.  Argument checks
+ * (sizes, finiteness, ordering, physical bounds) run on the host before any
+ * HIP call for host pointers.  With MASW_DEVICE_PTRS the values are checked
+ * on the device and a failing model reports MASW_STATUS_INVALID in the
+ * per-wavelength status.  masw_last_error() describes the last failure of the
+ * calling thread.
+ *
+ * Threads.  A context may be used by one thread at a time; calls on one
+ * context are serialised by an internal mutex.
+ */
+#ifndef MASW_H
+#define MASW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- codes -- */
+enum {
+    MASW_OK = 0,
+    MASW_EINVAL = -1,   /* an argument failed validation                      */
+    MASW_ENOMEM = -2,   /* the request does not fit the context's HBM budget  */
+    MASW_EBUSY = -3,    /* serving: result not ready / no free slot           */
+    MASW_EDEVICE = -4,  /* a HIP call failed or no device is present          */
+    MASW_ETIMEOUT = -5, /* serving: wait timed out                            */
+    MASW_ENOENT = -6    /* serving: unknown ticket                            */
+};
+
+/* Per-wavelength status (low byte) and flag bits. */
+enum {
+    MASW_STATUS_FOUND = 0,      /* a sign change was found at idx              */
+    MASW_STATUS_NOT_FOUND = 1,  /* no sign change in c_test: idx = -1, C_t NaN */
+    MASW_STATUS_INVALID = 2,    /* the model or grid failed device validation  */
+    MASW_STATUS_NAN = 3,        /* a determinant evaluated to NaN at idx       */
+    MASW_FLAG_POLE = 0x100      /* some layer denominator D_j changes sign
+                                   between c_test[idx-1] and c_test[idx]: the
+                                   change is a pole of det K, not a zero      */
+};
+
+/* Arithmetic of the search.
+ * MASW_PREC_FP64:  every determinant sign in FP64.
+ * MASW_PREC_SPLIT: the c-grid sweep in FP32; the FP32 bracket is re-checked
+ *                  in FP64 over a window of grid points around it, and the
+ *                  refinement is FP64.  idx is the first FP64 sign change in
+ *                  the re-checked window.                                     */
+typedef enum { MASW_PREC_FP64 = 0, MASW_PREC_SPLIT = 1 } masw_precision;
+
+/* Flags. */
+#define MASW_DEVICE_PTRS 0x1u  /* array arguments are device pointers        */
+#define MASW_NO_REFINE   0x2u  /* skip the root refinement (c_ref = NaN)     */
+
+/* Limits. */
+#define MASW_MAX_LAYERS 1024   /* finite layers per model                    */
+
+typedef struct masw_ctx masw_ctx;
+
+/* One model: n_layers finite layers over a half-space (n_layers = 0 is a
+ * homogeneous half-space).  h has n_layers entries (> 0); alpha, beta, rho
+ * have n_layers + 1 entries, the last for the half-space, with
+ * alpha > beta > 0 and rho > 0, all finite. */
+typedef struct {
+    int32_t n_layers;
+    const double *h;
+    const double *alpha;
+    const double *beta;
+    const double *rho;
+} masw_model;
+
+/* A batch of models of uneven sizes, flattened.
+ * Model m has N_m = layer_off[m+1] - layer_off[m] layers; its h entries are
+ * h[layer_off[m] .. layer_off[m+1]-1] and its alpha/beta/rho entries are at
+ * [layer_off[m] + m .. layer_off[m+1] + m] (N_m + 1 values, half-space last).
+ * Its wavelengths are lambda[lambda_off[m] .. lambda_off[m+1]-1].  Outputs
+ * are indexed by the flattened wavelength index.  layer_off and lambda_off
+ * are non-decreasing with layer_off[0] = lambda_off[0] = 0. */
+typedef struct {
+    int32_t n_models;
+    const int32_t *layer_off;   /* [n_models + 1] */
+    const double *h;            /* [layer_off[n_models]] */
+    const double *alpha;        /* [layer_off[n_models] + n_models] */
+    const double *beta;         /* [layer_off[n_models] + n_models] */
+    const double *rho;          /* [layer_off[n_models] + n_models] */
+    const int32_t *lambda_off;  /* [n_models + 1] */
+    const double *lambda;       /* [lambda_off[n_models]] */
+} masw_batch;
+
+/* Per-wavelength results, each an array of the number of wavelengths.
+ * c_t = c_test[idx] (the upper end of the bracketing grid interval, as in
+ * Algorithm 1), idx = grid index (-1 if none), status = MASW_STATUS_* |
+ * flags, c_ref = FP64 root inside [c_test[idx-1], c_test[idx]] to a bracket
+ * width of 1e-9 c_test[idx] (NaN if not found or MASW_NO_REFINE).  c_ref may
+ * be NULL. */
+typedef struct {
+    double *c_t;
+    int32_t *idx;
+    int32_t *status;
+    double *c_ref;
+} masw_outputs;
+
+/* Work counters of the last completed call on a context. */
+typedef struct {
+    uint64_t useful_evals;  /* sum over wavelengths of idx + 1 (n_c if none)    */
+    uint64_t sweep_evals;   /* determinant signs evaluated by the grid sweep   */
+    uint64_t check_evals;   /* FP64 re-check evaluations (split precision)     */
+    uint64_t refine_evals;  /* FP64 refinement evaluations                     */
+    uint64_t n_lambda;      /* wavelengths processed                           */
+    int32_t waves_per_item; /* wavefronts that cooperated on one wavelength    */
+    int32_t workgroups;     /* persistent workgroups launched                  */
+    float sweep_ms;         /* device time of the sweep/re-check/refine kernel,
+                               from HIP events on the launch stream            */
+    float total_ms;         /* device time of staging + ordering + sweep       */
+} masw_stats;
+
+/* Create a context on HIP device `device` that may hold up to
+ * `hbm_budget_bytes` of device memory (0 = 256 MiB).  The budget is
+ * allocated once, here.  Returns MASW_EDEVICE if no such device exists. */
+int masw_create(int device, size_t hbm_budget_bytes, masw_ctx **out);
+
+/* Wait for outstanding work, free the context's memory and streams.  NULL is
+ * ignored. */
+void masw_destroy(masw_ctx *ctx);
+
+/* Dispersion curve of one model (Algorithm 1 plus refinement).
+ * c_test: [n_c], strictly increasing, finite, > 0, n_c >= 2.
+ * lambda: [n_lambda], finite, > 0 (n_lambda = 0 does nothing).
+ * Outputs C_t, idx, status, c_ref (c_ref may be NULL): [n_lambda].
+ * Synchronous for host pointers; stream-ordered with MASW_DEVICE_PTRS. */
+int masw_dispersion_curve(masw_ctx *ctx, const double *c_test, int32_t n_c,
+                          const double *lambda, int32_t n_lambda,
+                          const masw_model *model, masw_precision prec,
+                          uint32_t flags, void *stream,
+                          double *C_t, int32_t *idx, int32_t *status,
+                          double *c_ref);
+
+/* Dispersion curves of a batch of models sharing one c grid, in one
+ * persistent launch whose work queue hands out (model, wavelength) items
+ * longest-expected-first.  Same rules as masw_dispersion_curve. */
+int masw_dispersion_batch(masw_ctx *ctx, const double *c_test, int32_t n_c,
+                          const masw_batch *batch, masw_precision prec,
+                          uint32_t flags, void *stream,
+                          const masw_outputs *out);
+
+/* Full sign map of one model: for every wavelength w and grid point i, with
+ * no early exit, sigma[w * n_c + i] = sign(Re det K) in {-1, 0, +1} (2 if the
+ * determinant is NaN) and, if log_abs_det is not NULL,
+ * log_abs_det[w * n_c + i] = natural log of |det K| (the unscaled matrix).
+ * This is the GPU counterpart of evaluating every stiffness matrix of the
+ * (wavelength, velocity) grid (Section 2.3).  MASW_PREC_FP64 or
+ * MASW_PREC_SPLIT (the latter evaluates in FP32). */
+int masw_sign_map(masw_ctx *ctx, const double *c_test, int32_t n_c,
+                  const double *lambda, int32_t n_lambda,
+                  const masw_model *model, masw_precision prec,
+                  uint32_t flags, void *stream,
+                  int8_t *sigma, double *log_abs_det);
+
+/* Counters of the last completed call on ctx (for MASW_DEVICE_PTRS calls,
+ * after the stream has been synchronised; this function synchronises). */
+int masw_get_stats(masw_ctx *ctx, masw_stats *out);
+
+/* Static text for an error code. */
+const char *masw_strerror(int code);
+
+/* Description of the calling thread's last error ("" if none). */
+const char *masw_last_error(void);
+
+/* Library version string. */
+const char *masw_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MASW_H */

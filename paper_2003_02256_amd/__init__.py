@@ -1,0 +1,300 @@
+"""Python binding of the MI355X dispersion-curve library (libmasw.so).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI declared in include/masw.h.  The functions below
+carry the C names; numpy arrays are passed as host pointers and torch tensors
+on a GPU as device pointers (MASW_DEVICE_PTRS is added automatically).  If the
+library has not been built, importing works but every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmasw.so")
+
+# --------------------------------------------------------------- constants --
+MASW_OK = 0
+MASW_EINVAL = -1
+MASW_ENOMEM = -2
+MASW_EBUSY = -3
+MASW_EDEVICE = -4
+MASW_ETIMEOUT = -5
+MASW_ENOENT = -6
+
+MASW_STATUS_FOUND = 0
+MASW_STATUS_NOT_FOUND = 1
+MASW_STATUS_INVALID = 2
+MASW_STATUS_NAN = 3
+MASW_FLAG_POLE = 0x100
+
+MASW_PREC_FP64 = 0
+MASW_PREC_SPLIT = 1
+
+MASW_DEVICE_PTRS = 0x1
+MASW_NO_REFINE = 0x2
+MASW_MAX_LAYERS = 1024
+
+
+class MaswError(RuntimeError):
+    def __init__(self, code: int, where: str, detail: str):
+        super().__init__(f"{where}: {detail} (code {code})")
+        self.code = code
+
+
+# ------------------------------------------------------------------ structs --
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+
+
+class masw_model(ctypes.Structure):
+    _fields_ = [("n_layers", ctypes.c_int32), ("h", _dp), ("alpha", _dp),
+                ("beta", _dp), ("rho", _dp)]
+
+
+class masw_batch(ctypes.Structure):
+    _fields_ = [("n_models", ctypes.c_int32), ("layer_off", _ip), ("h", _dp),
+                ("alpha", _dp), ("beta", _dp), ("rho", _dp),
+                ("lambda_off", _ip), ("lambda_", _dp)]
+
+
+class masw_outputs(ctypes.Structure):
+    _fields_ = [("c_t", _dp), ("idx", _ip), ("status", _ip), ("c_ref", _dp)]
+
+
+class masw_stats(ctypes.Structure):
+    _fields_ = [("useful_evals", ctypes.c_uint64), ("sweep_evals", ctypes.c_uint64),
+                ("check_evals", ctypes.c_uint64), ("refine_evals", ctypes.c_uint64),
+                ("n_lambda", ctypes.c_uint64), ("waves_per_item", ctypes.c_int32),
+                ("workgroups", ctypes.c_int32), ("sweep_ms", ctypes.c_float), ("total_ms", ctypes.c_float)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+# ------------------------------------------------------------------ loading --
+_lib = None
+
+
+def library() -> ctypes.CDLL:
+    """The loaded libmasw.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise MaswError(MASW_EDEVICE, "libmasw.so",
+                            f"not built ({LIB_PATH}); run paper_2003_02256_amd.build")
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, i32, u32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_size_t
+        sig = {
+            "masw_create": (ctypes.c_int, [ctypes.c_int, sz, ctypes.POINTER(vp)]),
+            "masw_destroy": (None, [vp]),
+            "masw_dispersion_curve": (ctypes.c_int, [vp, vp, i32, vp, i32, ctypes.POINTER(masw_model),
+                                                     ctypes.c_int, u32, vp, vp, vp, vp, vp]),
+            "masw_dispersion_batch": (ctypes.c_int, [vp, vp, i32, ctypes.POINTER(masw_batch),
+                                                     ctypes.c_int, u32, vp, ctypes.POINTER(masw_outputs)]),
+            "masw_sign_map": (ctypes.c_int, [vp, vp, i32, vp, i32, ctypes.POINTER(masw_model),
+                                             ctypes.c_int, u32, vp, vp, vp]),
+            "masw_get_stats": (ctypes.c_int, [vp, ctypes.POINTER(masw_stats)]),
+            "masw_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+            "masw_last_error": (ctypes.c_char_p, []),
+            "masw_version": (ctypes.c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(rc: int, where: str) -> int:
+    if rc != MASW_OK:
+        lib = library()
+        raise MaswError(rc, where, f"{lib.masw_strerror(rc).decode()}: {lib.masw_last_error().decode()}")
+    return rc
+
+
+# -------------------------------------------------------------- marshalling --
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _ptr(x, dtype) -> Optional[int]:
+    """Address of a contiguous numpy array or torch tensor of `dtype`."""
+    if x is None:
+        return None
+    if _is_torch(x):
+        import torch
+        want = {np.float64: torch.float64, np.int32: torch.int32, np.int8: torch.int8}[dtype]
+        if x.dtype != want or not x.is_contiguous():
+            raise MaswError(MASW_EINVAL, "marshal", f"tensor must be contiguous {want}")
+        return x.data_ptr()
+    if not isinstance(x, np.ndarray) or x.dtype != dtype or not x.flags.c_contiguous:
+        raise MaswError(MASW_EINVAL, "marshal", f"array must be a contiguous {np.dtype(dtype)} ndarray")
+    return x.ctypes.data
+
+
+def _device_flag(*xs) -> int:
+    devs = [_is_torch(x) and x.is_cuda for x in xs if x is not None]
+    if any(devs) and not all(devs):
+        raise MaswError(MASW_EINVAL, "marshal", "mix of host and device buffers")
+    return MASW_DEVICE_PTRS if (devs and all(devs)) else 0
+
+
+def _stream(stream, device_flag: int):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    if device_flag:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return None
+
+
+def _model_struct(h, alpha, beta, rho) -> masw_model:
+    m = masw_model()
+    m.n_layers = int(alpha.shape[0]) - 1
+    m.h = ctypes.cast(_ptr(h, np.float64), _dp) if int(h.shape[0]) > 0 else ctypes.cast(None, _dp)
+    m.alpha = ctypes.cast(_ptr(alpha, np.float64), _dp)
+    m.beta = ctypes.cast(_ptr(beta, np.float64), _dp)
+    m.rho = ctypes.cast(_ptr(rho, np.float64), _dp)
+    return m
+
+
+# ------------------------------------------------------------------ C names --
+def masw_version() -> str:
+    return library().masw_version().decode()
+
+
+def masw_strerror(code: int) -> str:
+    return library().masw_strerror(code).decode()
+
+
+def masw_last_error() -> str:
+    return library().masw_last_error().decode()
+
+
+def masw_create(device: int = 0, hbm_budget_bytes: int = 0) -> ctypes.c_void_p:
+    ctx = ctypes.c_void_p()
+    _check(library().masw_create(device, hbm_budget_bytes, ctypes.byref(ctx)), "masw_create")
+    return ctx
+
+
+def masw_destroy(ctx) -> None:
+    if ctx:
+        library().masw_destroy(ctx)
+
+
+def masw_dispersion_curve(ctx, c_test, lam, h, alpha, beta, rho, prec: int, flags: int,
+                          stream, C_t, idx, status, c_ref=None) -> int:
+    """Marshals to the C function of the same name (see include/masw.h)."""
+    fl = flags | _device_flag(c_test, lam, h, alpha, beta, rho, C_t, idx, status, c_ref)
+    m = _model_struct(h, alpha, beta, rho)
+    return _check(library().masw_dispersion_curve(
+        ctx, _ptr(c_test, np.float64), int(c_test.shape[0]), _ptr(lam, np.float64), int(lam.shape[0]),
+        ctypes.byref(m), prec, fl, _stream(stream, fl & MASW_DEVICE_PTRS),
+        _ptr(C_t, np.float64), _ptr(idx, np.int32), _ptr(status, np.int32), _ptr(c_ref, np.float64)),
+        "masw_dispersion_curve")
+
+
+def masw_dispersion_batch(ctx, c_test, layer_off, h, alpha, beta, rho, lambda_off, lam,
+                          prec: int, flags: int, stream, C_t, idx, status, c_ref=None) -> int:
+    fl = flags | _device_flag(c_test, layer_off, h, alpha, beta, rho, lambda_off, lam, C_t, idx, status, c_ref)
+    b = masw_batch()
+    b.n_models = int(layer_off.shape[0]) - 1
+    b.layer_off = ctypes.cast(_ptr(layer_off, np.int32), _ip)
+    b.h = ctypes.cast(_ptr(h, np.float64), _dp)
+    b.alpha = ctypes.cast(_ptr(alpha, np.float64), _dp)
+    b.beta = ctypes.cast(_ptr(beta, np.float64), _dp)
+    b.rho = ctypes.cast(_ptr(rho, np.float64), _dp)
+    b.lambda_off = ctypes.cast(_ptr(lambda_off, np.int32), _ip)
+    b.lambda_ = ctypes.cast(_ptr(lam, np.float64), _dp)
+    o = masw_outputs()
+    o.c_t = ctypes.cast(_ptr(C_t, np.float64), _dp)
+    o.idx = ctypes.cast(_ptr(idx, np.int32), _ip)
+    o.status = ctypes.cast(_ptr(status, np.int32), _ip)
+    o.c_ref = ctypes.cast(_ptr(c_ref, np.float64), _dp)
+    return _check(library().masw_dispersion_batch(
+        ctx, _ptr(c_test, np.float64), int(c_test.shape[0]), ctypes.byref(b), prec, fl,
+        _stream(stream, fl & MASW_DEVICE_PTRS), ctypes.byref(o)), "masw_dispersion_batch")
+
+
+def masw_sign_map(ctx, c_test, lam, h, alpha, beta, rho, prec: int, flags: int, stream,
+                  sigma, log_abs_det=None) -> int:
+    fl = flags | _device_flag(c_test, lam, h, alpha, beta, rho, sigma, log_abs_det)
+    m = _model_struct(h, alpha, beta, rho)
+    return _check(library().masw_sign_map(
+        ctx, _ptr(c_test, np.float64), int(c_test.shape[0]), _ptr(lam, np.float64), int(lam.shape[0]),
+        ctypes.byref(m), prec, fl, _stream(stream, fl & MASW_DEVICE_PTRS),
+        _ptr(sigma, np.int8), _ptr(log_abs_det, np.float64)), "masw_sign_map")
+
+
+def masw_get_stats(ctx) -> dict:
+    s = masw_stats()
+    _check(library().masw_get_stats(ctx, ctypes.byref(s)), "masw_get_stats")
+    return s.as_dict()
+
+
+# ------------------------------------------------------------ convenience --
+def flatten_models(models, lambdas):
+    """CSR arrays (layer_off, h, alpha, beta, rho, lambda_off, lam) of a list of
+    models (objects with h, alpha, beta, rho arrays) and their wavelengths."""
+    n = [int(m.h.shape[0]) for m in models]
+    w = [int(np.asarray(l).shape[0]) for l in lambdas]
+    layer_off = np.zeros(len(models) + 1, np.int32)
+    layer_off[1:] = np.cumsum(n)
+    lambda_off = np.zeros(len(models) + 1, np.int32)
+    lambda_off[1:] = np.cumsum(w)
+    cat = lambda xs: np.ascontiguousarray(np.concatenate(xs) if xs else np.zeros(0), dtype=np.float64)
+    return (layer_off, cat([m.h for m in models]), cat([m.alpha for m in models]),
+            cat([m.beta for m in models]), cat([m.rho for m in models]), lambda_off,
+            cat([np.asarray(l, np.float64) for l in lambdas]))
+
+
+class Context:
+    """A masw_ctx on one device, with helpers that allocate outputs."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 1 << 30):
+        self.ctx = masw_create(device, hbm_budget_bytes)
+
+    def close(self) -> None:
+        masw_destroy(self.ctx)
+        self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def stats(self) -> dict:
+        return masw_get_stats(self.ctx)
+
+    def curve(self, c_test, lam, model, prec=MASW_PREC_FP64, flags=0):
+        """Host arrays in, host arrays out: (C_t, idx, status, c_ref)."""
+        W = int(np.asarray(lam).shape[0])
+        out = (np.empty(W), np.empty(W, np.int32), np.empty(W, np.int32), np.empty(W))
+        f64 = lambda x: np.ascontiguousarray(x, dtype=np.float64)
+        masw_dispersion_curve(self.ctx, f64(c_test), f64(lam), f64(model.h), f64(model.alpha),
+                              f64(model.beta), f64(model.rho), prec, flags, None, *out)
+        return out
+
+    def batch(self, c_test, models, lambdas, prec=MASW_PREC_SPLIT, flags=0):
+        """Host arrays in, host arrays out, outputs flattened over all wavelengths."""
+        arrs = flatten_models(models, lambdas)
+        W = int(arrs[-1].shape[0])
+        out = (np.empty(W), np.empty(W, np.int32), np.empty(W, np.int32), np.empty(W))
+        masw_dispersion_batch(self.ctx, np.ascontiguousarray(c_test, np.float64), *arrs, prec, flags, None, *out)
+        return out
+
+    def sign_map(self, c_test, lam, model, prec=MASW_PREC_FP64, want_log=True):
+        W, n_c = int(np.asarray(lam).shape[0]), int(np.asarray(c_test).shape[0])
+        sig = np.empty(W * n_c, np.int8)
+        la = np.empty(W * n_c) if want_log else None
+        f64 = lambda x: np.ascontiguousarray(x, dtype=np.float64)
+        masw_sign_map(self.ctx, f64(c_test), f64(lam), f64(model.h), f64(model.alpha), f64(model.beta),
+                      f64(model.rho), prec, 0, None, sig, la)
+        return sig.reshape(W, n_c), (la.reshape(W, n_c) if want_log else None)

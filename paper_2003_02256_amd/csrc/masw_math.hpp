@@ -1,0 +1,239 @@
+// Per-lane determinant sign of the layered stiffness matrix K(k, c).
+//
+// The global matrix (size 2(N+1), symmetric, heptadiagonal; Section 2.1 and
+// Section 3.1) is block tridiagonal in 2x2 blocks.  Layer j's 4x4 element
+// matrix [[P_j, Q_j], [Q_j^T, R_j]] adds P_j to diagonal block j, R_j to block
+// j+1 and Q_j to the off-diagonal block (j, j+1); the half-space's 2x2 matrix
+// adds to block N.  The determinant is the product of the determinants of the
+// block pivots of an unpivoted block LDL^T elimination,
+//     S_0 = A_0,   S_{j+1} = A_{j+1} - Q_j^T S_j^{-1} Q_j,   det K = prod det S_j,
+// which is the O(N) banded elimination that the paper runs instead of a dense
+// LU (Section 2.3, Section 3.1), carried out here in registers while the
+// element matrices are formed, so the matrix is never stored.  Only the sign
+// is needed by the search, so only the sign of each det S_j is kept (the
+// magnitude overflows FP64 beyond a few tens of layers).
+//
+// Entries are divided by k mu_ref (mu_ref = the half-space's rho beta^2), and
+// every hyperbolic function of a layer is multiplied by
+// E = exp(-t Re sqrt(x)) (t = k h); both are positive factors that cancel in
+// f * numerator / denominator, so every entry is computed with no overflow at
+// any k h, and the result is real for every real c below the half-space's S
+// velocity.  With q = sqrt(|x|) for x = r^2 = 1 - c^2/alpha^2 or
+// x = s^2 = 1 - c^2/beta^2:
+//     x > 0:  E = exp(-t q),  a = E (cosh tq - 1),  Sh = E sinh(tq)/q,  R = E q sinh(tq)
+//     x < 0:  E = 1,          a = cos tq - 1,       Sh = sin(tq)/q,      R = -q sin(tq)
+//     x = 0:  E = 1,          a = 0,                Sh = t,              R = 0
+// (the last row is the removable 0/0 at c = alpha or c = beta).  a and Sh are
+// formed from expm1 or from the half-angle sin/cos so that the long-wavelength
+// cancellation 1 - cosh cosh is never computed as a difference of O(1) terms.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "masw_internal.hpp"
+
+namespace masw {
+
+// ---------------------------------------------------------------- helpers --
+template <typename T>
+struct Fn;
+
+template <>
+struct Fn<double> {
+  static __device__ __forceinline__ double sqrt_(double x) { return __builtin_sqrt(x); }
+  static __device__ __forceinline__ double expm1_(double x) { return ::expm1(x); }
+  static __device__ __forceinline__ void sincos_(double x, double* s, double* c) { ::sincos(x, s, c); }
+};
+
+template <>
+struct Fn<float> {
+  static __device__ __forceinline__ float sqrt_(float x) { return __builtin_sqrtf(x); }
+  static __device__ __forceinline__ float expm1_(float x) { return ::expm1f(x); }
+  static __device__ __forceinline__ void sincos_(float x, float* s, float* c) { ::sincosf(x, s, c); }
+};
+
+// The four E-scaled functions of one potential (see the file comment).
+template <typename T>
+struct Terms {
+  T E, a, Sh, R;
+};
+
+template <typename T>
+__device__ __forceinline__ Terms<T> potential_terms(T x, T t) {
+  Terms<T> o;
+  if (x > T(0)) {
+    const T q = Fn<T>::sqrt_(x);
+    const T m = Fn<T>::expm1_(-t * q);       // E - 1
+    const T half_sh = T(-0.5) * m * (T(2) + m);  // E sinh(tq) = (1 - E^2) / 2
+    o.E = T(1) + m;
+    o.a = T(0.5) * m * m;                    // E cosh - E = (1 - E)^2 / 2
+    o.Sh = half_sh / q;
+    o.R = half_sh * q;
+  } else if (x < T(0)) {
+    const T q = Fn<T>::sqrt_(-x);
+    T hs, hc;
+    Fn<T>::sincos_(T(0.5) * t * q, &hs, &hc);
+    const T sn = T(2) * hs * hc;             // sin(tq)
+    o.E = T(1);
+    o.a = T(-2) * hs * hs;                   // cos(tq) - 1
+    o.Sh = sn / q;
+    o.R = -q * sn;
+  } else {
+    o.E = T(1);
+    o.a = T(0);
+    o.Sh = t;
+    o.R = T(0);
+  }
+  return o;
+}
+
+// Six distinct entries of one layer's scaled element matrix
+//     [[k11,  k12,  k13,  k14],
+//      [k12,  k22, -k14,  k24],
+//      [k13, -k14,  k11, -k12],
+//      [k14,  k24, -k12,  k22]]  / (k mu_ref)
+// and gD = E_r E_s D, whose sign is the sign of the layer's denominator D.
+template <typename T>
+struct LayerK {
+  T k11, k12, k13, k14, k22, k24, gD;
+};
+
+template <typename T>
+__device__ __forceinline__ LayerK<T> layer_entries(T c2, T t, T ia2, T ib2, T rh, T mh) {
+  const T xr = T(1) - c2 * ia2;  // r^2
+  const T xs = T(1) - c2 * ib2;  // s^2
+  const Terms<T> P = potential_terms(xr, t);
+  const Terms<T> S = potential_terms(xs, t);
+  const T Cr = P.E + P.a;        // E_r cosh(t r)
+  const T Cs = S.E + S.a;
+  const T u = P.E * S.a + P.a * S.E + P.a * S.a;  // E_r E_s (C_r C_s - 1)
+  LayerK<T> o;
+  o.gD = T(-2) * u + P.Sh * S.Sh + P.R * S.R;
+  const T F = rh * c2 / o.gD;    // f / (k mu_ref) with the E factors cancelled
+  o.k11 = F * (Cr * S.Sh - P.R * Cs);
+  o.k12 = F * (u - P.R * S.R) - mh * (T(1) + xs);
+  o.k13 = F * (P.R * S.E - S.Sh * P.E);
+  o.k14 = F * (S.a * P.E - P.a * S.E);
+  o.k22 = F * (P.Sh * Cs - S.R * Cr);
+  o.k24 = F * (S.R * P.E - P.Sh * S.E);
+  return o;
+}
+
+// Symmetric 2x2 block (s11, s12; s12, s22).
+template <typename T>
+struct Block2 {
+  T s11, s12, s22;
+};
+
+// One layer of the block elimination.  On entry S holds the part of diagonal
+// block j built so far (R_{j-1} - Q_{j-1}^T S_{j-1}^{-1} Q_{j-1}, or 0 for j = 0).
+// Adds P_j to complete S_j, returns det S_j, and leaves R_j - Q_j^T S_j^{-1} Q_j
+// (the start of block j+1) in S.
+template <typename T>
+__device__ __forceinline__ T schur_layer(Block2<T>& S, const LayerK<T>& K) {
+  const T s11 = S.s11 + K.k11;
+  const T s12 = S.s12 + K.k12;
+  const T s22 = S.s22 + K.k22;
+  const T d = s11 * s22 - s12 * s12;
+  const T id = T(1) / d;
+  // Q_j = [[k13, k14], [-k14, k24]];  W = adj(S_j) Q_j;  M = Q_j^T W
+  const T q11 = K.k13, q12 = K.k14, q21 = -K.k14, q22 = K.k24;
+  const T w11 = s22 * q11 - s12 * q21;
+  const T w12 = s22 * q12 - s12 * q22;
+  const T w21 = s11 * q21 - s12 * q11;
+  const T w22 = s11 * q22 - s12 * q12;
+  const T m11 = q11 * w11 + q21 * w21;
+  const T m12 = q11 * w12 + q21 * w22;
+  const T m22 = q12 * w12 + q22 * w22;
+  S.s11 = K.k11 - m11 * id;
+  S.s12 = -K.k12 - m12 * id;
+  S.s22 = K.k22 - m22 * id;
+  return d;
+}
+
+// Real and imaginary parts of det S_N, S_N = S + H with H the scaled
+// half-space matrix
+//     h11 = mh r (1 - s^2)/(1 - r s),  h22 = mh s (1 - s^2)/(1 - r s),
+//     h12 = mh ((1 - s^2)/(1 - r s) - 2),
+// where r and s are taken on the principal branch from their real squares
+// (x < 0 gives +i sqrt(-x)).  H is complex only above the half-space's S
+// velocity.
+template <typename T>
+__device__ __forceinline__ void halfspace_det(const Block2<T>& S, T c2, T ia2, T ib2, T mh,
+                                              T* re, T* im) {
+  const T xr = T(1) - c2 * ia2;
+  const T xs = T(1) - c2 * ib2;
+  const T qr = Fn<T>::sqrt_(xr < T(0) ? -xr : xr);
+  const T qs = Fn<T>::sqrt_(xs < T(0) ? -xs : xs);
+  const T rr = xr >= T(0) ? qr : T(0), ri = xr >= T(0) ? T(0) : qr;
+  const T sr = xs >= T(0) ? qs : T(0), si = xs >= T(0) ? T(0) : qs;
+  const T dr = T(1) - (rr * sr - ri * si);  // 1 - r s
+  const T di = -(rr * si + ri * sr);
+  const T inv = T(1) / (dr * dr + di * di);
+  const T zr = dr * inv, zi = -di * inv;    // 1 / (1 - r s)
+  const T mu = mh * (c2 * ib2);             // mh (1 - s^2)
+  const T h11r = mu * (rr * zr - ri * zi), h11i = mu * (rr * zi + ri * zr);
+  const T h22r = mu * (sr * zr - si * zi), h22i = mu * (sr * zi + si * zr);
+  const T h12r = mu * zr - T(2) * mh, h12i = mu * zi;
+  const T ar = S.s11 + h11r, ai = h11i;
+  const T br = S.s22 + h22r, bi = h22i;
+  const T er = S.s12 + h12r, ei = h12i;
+  *re = ar * br - ai * bi - (er * er - ei * ei);
+  *im = ar * bi + ai * br - T(2) * er * ei;
+}
+
+__device__ __forceinline__ int sign_code(bool negative, double v) {
+  if (v != v) return kNaNSign;
+  const int s = (v > 0.0) - (v < 0.0);
+  return negative ? -s : s;
+}
+
+// sign(Re det K(k, c)) in {-1, 0, +1}, or kNaNSign.  L points at the model's
+// N layer records followed by its half-space record (uniform across the
+// wavefront).  With kMask, *dmask receives bit (j mod 64) xor-folded for
+// every layer whose denominator D_j is negative.
+template <typename T, bool kMask>
+__device__ __forceinline__ int det_sign(T c, T k, const LayerRec<T>* __restrict__ L, int N,
+                                        uint64_t* dmask) {
+  const T c2 = c * c;
+  Block2<T> S{T(0), T(0), T(0)};
+  bool neg = false;
+  uint64_t mask = 0;
+  for (int j = 0; j < N; ++j) {
+    const LayerRec<T> rec = L[j];
+    const LayerK<T> K = layer_entries<T>(c2, k * rec.h, rec.ia2, rec.ib2, rec.rh, rec.mh);
+    if (kMask) mask ^= uint64_t(K.gD < T(0)) << (j & 63);
+    const T d = schur_layer<T>(S, K);
+    neg ^= (d < T(0));
+  }
+  const LayerRec<T> hs = L[N];
+  T re, im;
+  halfspace_det<T>(S, c2, hs.ia2, hs.ib2, hs.mh, &re, &im);
+  if (kMask) *dmask = mask;
+  return sign_code(neg, double(re));
+}
+
+// As det_sign, also returning ln|det K| of the unscaled matrix:
+// sum_j ln|det S_j| + ln|det S_N| + 2(N+1) ln(k mu_ref).
+template <typename T>
+__device__ __forceinline__ int det_sign_logabs(T c, T k, const LayerRec<T>* __restrict__ L, int N,
+                                               double mu_ref, double k64, double* logabs) {
+  const T c2 = c * c;
+  Block2<T> S{T(0), T(0), T(0)};
+  bool neg = false;
+  double acc = 0.0;
+  for (int j = 0; j < N; ++j) {
+    const LayerRec<T> rec = L[j];
+    const LayerK<T> K = layer_entries<T>(c2, k * rec.h, rec.ia2, rec.ib2, rec.rh, rec.mh);
+    const T d = schur_layer<T>(S, K);
+    neg ^= (d < T(0));
+    acc += ::log(::fabs(double(d)));
+  }
+  const LayerRec<T> hs = L[N];
+  T re, im;
+  halfspace_det<T>(S, c2, hs.ia2, hs.ib2, hs.mh, &re, &im);
+  acc += ::log(::hypot(double(re), double(im)));
+  *logabs = acc + 2.0 * double(N + 1) * ::log(k64 * mu_ref);
+  return sign_code(neg, double(re));
+}
+
+}  // namespace masw

@@ -1,0 +1,588 @@
+// Host runtime behind masw.h: context, HBM arena, argument validation,
+// staging of host inputs, launch configuration and the C ABI.
+//
+// The context allocates its whole HBM budget once (masw_create) and carves
+// every call's workspace from it with a bump allocator, so no call allocates
+// device memory.  A request whose workspace exceeds the budget fails with
+// MASW_ENOMEM before any work is queued.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "masw.h"
+#include "masw_internal.hpp"
+
+namespace masw {
+int sweep_blocks_per_cu(int mode, int G);
+hipError_t launch_sweep(int mode, int G, int blocks, hipStream_t s, const SweepArgs& a);
+hipError_t launch_prep(const PrepArgs& a, int single_N, int single_W, hipStream_t s);
+hipError_t launch_sign_map(bool fp32, const SignMapArgs& a, hipStream_t s);
+}  // namespace masw
+
+using namespace masw;
+
+// ------------------------------------------------------------ errors --
+static thread_local std::string g_last_error;
+
+static int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define MASW_HIP(call)                                                              \
+  do {                                                                              \
+    hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      return fail(MASW_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// ----------------------------------------------------------- context --
+struct masw_ctx {
+  int device = -1;
+  hipStream_t stream = nullptr;   // the context's own stream (default priority)
+  hipStream_t last_stream = nullptr;
+  char* arena = nullptr;
+  size_t arena_size = 0;
+  int cus = 0;
+  int blocks_per_cu[2][4] = {};   // [mode][log2 G]
+  std::mutex mu;
+  masw_stats last = {};
+  bool stats_pending = false;
+  Counters* counters = nullptr;   // arena offset 0
+  hipEvent_t ev[3] = {};          // start, sweep start, sweep end
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+struct Bump {
+  char* base;
+  size_t cap;
+  size_t off;
+  template <typename T>
+  T* take(size_t n) {
+    off = (off + kAlign - 1) & ~(kAlign - 1);
+    T* p = reinterpret_cast<T*>(base + off);
+    off += n * sizeof(T);
+    return p;
+  }
+  bool ok() const { return off <= cap; }
+};
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// Host-side checks of one model's values (host pointers only).
+int check_model_values(int32_t N, const double* h, const double* alpha, const double* beta,
+                       const double* rho, const char* what) {
+  if (N < 0 || N > MASW_MAX_LAYERS)
+    return fail(MASW_EINVAL, std::string(what) + ": n_layers out of range [0, MASW_MAX_LAYERS]");
+  if ((N > 0 && !h) || !alpha || !beta || !rho)
+    return fail(MASW_EINVAL, std::string(what) + ": null model array");
+  for (int j = 0; j < N; ++j)
+    if (!finite_pos(h[j])) return fail(MASW_EINVAL, std::string(what) + ": h must be finite and > 0");
+  for (int j = 0; j <= N; ++j) {
+    if (!finite_pos(beta[j]) || !finite_pos(alpha[j]) || !finite_pos(rho[j]))
+      return fail(MASW_EINVAL, std::string(what) + ": alpha, beta, rho must be finite and > 0");
+    if (!(alpha[j] > beta[j]))
+      return fail(MASW_EINVAL, std::string(what) + ": alpha must exceed beta in every layer");
+  }
+  return MASW_OK;
+}
+
+int check_grid(const double* c, int32_t n_c, bool values) {
+  if (n_c < 2) return fail(MASW_EINVAL, "c_test: n_c must be >= 2");
+  if (!c) return fail(MASW_EINVAL, "c_test: null pointer");
+  if (!values) return MASW_OK;
+  for (int i = 0; i < n_c; ++i) {
+    if (!finite_pos(c[i])) return fail(MASW_EINVAL, "c_test: values must be finite and > 0");
+    if (i > 0 && !(c[i] > c[i - 1])) return fail(MASW_EINVAL, "c_test: must be strictly increasing");
+  }
+  return MASW_OK;
+}
+
+int check_lambda(const double* lam, int32_t n, bool values) {
+  if (n < 0) return fail(MASW_EINVAL, "lambda: n_lambda must be >= 0");
+  if (n > 0 && !lam) return fail(MASW_EINVAL, "lambda: null pointer");
+  if (!values) return MASW_OK;
+  for (int i = 0; i < n; ++i)
+    if (!finite_pos(lam[i])) return fail(MASW_EINVAL, "lambda: values must be finite and > 0");
+  return MASW_OK;
+}
+
+// Flattened view of the inputs, host or device, with sizes.
+struct Inputs {
+  int32_t n_models = 0;
+  const int32_t* layer_off = nullptr;  // nullptr: single model
+  int32_t single_N = 0;
+  int32_t single_W = 0;
+  const double* h = nullptr;
+  const double* alpha = nullptr;
+  const double* beta = nullptr;
+  const double* rho = nullptr;
+  const int32_t* lambda_off = nullptr;
+  const double* lambda = nullptr;
+  const double* c = nullptr;
+  int32_t n_c = 0;
+  int64_t n_layers_total = 0;  // sum N_m
+  int64_t n_lam = 0;           // sum W_m
+};
+
+// Total device bytes of one call's workspace.
+size_t workspace_bytes(const Inputs& in, bool stage_inputs, bool stage_outputs) {
+  Bump b{nullptr, ~size_t(0), 0};
+  const size_t R = size_t(in.n_layers_total + in.n_models);
+  b.take<Counters>(1);
+  b.take<ModelDesc>(size_t(in.n_models));
+  b.take<LayerRec64>(R);
+  b.take<LayerRec32>(R);
+  b.take<double>(size_t(in.n_c));
+  b.take<float>(size_t(in.n_c));
+  b.take<double>(size_t(in.n_lam));
+  b.take<int32_t>(size_t(in.n_lam));
+  b.take<uint8_t>(size_t(in.n_lam));
+  b.take<int32_t>(size_t(in.n_lam));
+  if (stage_inputs) {
+    b.take<int32_t>(size_t(in.n_models) + 1);
+    b.take<int32_t>(size_t(in.n_models) + 1);
+    b.take<double>(size_t(in.n_layers_total));
+    b.take<double>(R * 3);
+    b.take<double>(size_t(in.n_lam));
+  }
+  if (stage_outputs) {
+    b.take<double>(size_t(in.n_lam) * 2);
+    b.take<int32_t>(size_t(in.n_lam) * 2);
+  }
+  return b.off + kAlign;
+}
+
+int pick_waves_per_item(masw_ctx* ctx, int mode, int64_t n_items, int* blocks) {
+  // One wavefront per item when items outnumber wavefront slots; otherwise
+  // split each item over G wavefronts so that items * G roughly fills them.
+  int G = 1;
+  for (int lg = 3; lg >= 0; --lg) {
+    const int g = 1 << lg;
+    const int64_t slots = int64_t(ctx->cus) * ctx->blocks_per_cu[mode][lg] * g;
+    if (n_items * g <= slots) {
+      G = g;
+      break;
+    }
+  }
+  const int lg = G == 1 ? 0 : G == 2 ? 1 : G == 4 ? 2 : 3;
+  const int64_t max_blocks = int64_t(ctx->cus) * std::max(1, ctx->blocks_per_cu[mode][lg]);
+  *blocks = int(std::max<int64_t>(1, std::min<int64_t>(n_items, max_blocks)));
+  return G;
+}
+
+// Shared body of the curve and batch calls.
+int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t flags, void* stream,
+               const masw_outputs* out) {
+  const bool dev = (flags & MASW_DEVICE_PTRS) != 0;
+  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : ctx->stream;
+  const size_t need = workspace_bytes(in, !dev, !dev);
+  if (need > ctx->arena_size)
+    return fail(MASW_ENOMEM, "request needs " + std::to_string(need) + " B of device memory, budget is " +
+                                 std::to_string(ctx->arena_size) + " B");
+  MASW_HIP(hipSetDevice(ctx->device));
+
+  Bump b{ctx->arena, ctx->arena_size, 0};
+  const size_t R = size_t(in.n_layers_total + in.n_models);
+  PrepArgs p{};
+  p.counters = b.take<Counters>(1);
+  p.models = b.take<ModelDesc>(size_t(in.n_models));
+  p.layers64 = b.take<LayerRec64>(R);
+  p.layers32 = b.take<LayerRec32>(R);
+  double* c_copy = b.take<double>(size_t(in.n_c));
+  p.c32 = b.take<float>(size_t(in.n_c));
+  p.lam_k = b.take<double>(size_t(in.n_lam));
+  p.lam_model = b.take<int32_t>(size_t(in.n_lam));
+  p.lam_bucket = b.take<uint8_t>(size_t(in.n_lam));
+  p.order = b.take<int32_t>(size_t(in.n_lam));
+  p.n_models = in.n_models;
+  p.n_c = in.n_c;
+  p.n_lam = int32_t(in.n_lam);
+
+  SweepArgs sw{};
+  if (dev) {
+    p.layer_off = in.layer_off;
+    p.lambda_off = in.lambda_off;
+    p.h = in.h;
+    p.alpha = in.alpha;
+    p.beta = in.beta;
+    p.rho = in.rho;
+    p.lambda = in.lambda;
+    p.c_in = in.c;
+    p.c64 = const_cast<double*>(in.c);  // the grid is read in place
+    sw.out_ct = out->c_t;
+    sw.out_idx = out->idx;
+    sw.out_status = out->status;
+    sw.out_cref = out->c_ref;
+  } else {
+    int32_t* loff = nullptr;
+    int32_t* woff = nullptr;
+    if (in.layer_off) {
+      loff = b.take<int32_t>(size_t(in.n_models) + 1);
+      woff = b.take<int32_t>(size_t(in.n_models) + 1);
+    } else {
+      b.take<int32_t>(size_t(in.n_models) + 1);
+      b.take<int32_t>(size_t(in.n_models) + 1);
+    }
+    double* hh = b.take<double>(size_t(in.n_layers_total));
+    double* abr = b.take<double>(R * 3);
+    double* ll = b.take<double>(size_t(in.n_lam));
+    if (loff) {
+      MASW_HIP(hipMemcpyAsync(loff, in.layer_off, sizeof(int32_t) * (in.n_models + 1), hipMemcpyHostToDevice, s));
+      MASW_HIP(hipMemcpyAsync(woff, in.lambda_off, sizeof(int32_t) * (in.n_models + 1), hipMemcpyHostToDevice, s));
+    }
+    if (in.n_layers_total)
+      MASW_HIP(hipMemcpyAsync(hh, in.h, sizeof(double) * in.n_layers_total, hipMemcpyHostToDevice, s));
+    MASW_HIP(hipMemcpyAsync(abr, in.alpha, sizeof(double) * R, hipMemcpyHostToDevice, s));
+    MASW_HIP(hipMemcpyAsync(abr + R, in.beta, sizeof(double) * R, hipMemcpyHostToDevice, s));
+    MASW_HIP(hipMemcpyAsync(abr + 2 * R, in.rho, sizeof(double) * R, hipMemcpyHostToDevice, s));
+    if (in.n_lam) MASW_HIP(hipMemcpyAsync(ll, in.lambda, sizeof(double) * in.n_lam, hipMemcpyHostToDevice, s));
+    MASW_HIP(hipMemcpyAsync(c_copy, in.c, sizeof(double) * in.n_c, hipMemcpyHostToDevice, s));
+    p.layer_off = loff;
+    p.lambda_off = woff;
+    p.h = hh;
+    p.alpha = abr;
+    p.beta = abr + R;
+    p.rho = abr + 2 * R;
+    p.lambda = ll;
+    p.c_in = c_copy;
+    p.c64 = c_copy;
+    sw.out_ct = b.take<double>(size_t(in.n_lam));
+    sw.out_cref = b.take<double>(size_t(in.n_lam));
+    sw.out_idx = b.take<int32_t>(size_t(in.n_lam));
+    sw.out_status = b.take<int32_t>(size_t(in.n_lam));
+  }
+  if (!b.ok()) return fail(MASW_ENOMEM, "workspace exceeds the HBM budget");
+
+  MASW_HIP(hipEventRecord(ctx->ev[0], s));
+  MASW_HIP(launch_prep(p, in.single_N, in.single_W, s));
+
+  const int mode = prec == MASW_PREC_SPLIT ? 1 : 0;
+  int blocks = 1;
+  const int G = pick_waves_per_item(ctx, mode, in.n_lam, &blocks);
+  sw.models = p.models;
+  sw.layers64 = p.layers64;
+  sw.layers32 = p.layers32;
+  sw.c64 = p.c64;
+  sw.c32 = p.c32;
+  sw.lam_k = p.lam_k;
+  sw.lam_model = p.lam_model;
+  sw.order = p.order;
+  sw.n_items = int32_t(in.n_lam);
+  sw.refine = (flags & MASW_NO_REFINE) ? 0 : 1;
+  sw.counters = p.counters;
+  MASW_HIP(hipEventRecord(ctx->ev[1], s));
+  if (in.n_lam > 0) MASW_HIP(launch_sweep(mode, G, blocks, s, sw));
+  MASW_HIP(hipEventRecord(ctx->ev[2], s));
+  ctx->last = masw_stats{};
+  ctx->last.n_lambda = uint64_t(in.n_lam);
+  ctx->last.waves_per_item = G;
+  ctx->last.workgroups = in.n_lam > 0 ? blocks : 0;
+  ctx->stats_pending = true;
+  ctx->last_stream = s;
+
+  if (!dev) {
+    const size_t W = size_t(in.n_lam);
+    if (W) {
+      MASW_HIP(hipMemcpyAsync(out->c_t, sw.out_ct, sizeof(double) * W, hipMemcpyDeviceToHost, s));
+      MASW_HIP(hipMemcpyAsync(out->idx, sw.out_idx, sizeof(int32_t) * W, hipMemcpyDeviceToHost, s));
+      MASW_HIP(hipMemcpyAsync(out->status, sw.out_status, sizeof(int32_t) * W, hipMemcpyDeviceToHost, s));
+      if (out->c_ref)
+        MASW_HIP(hipMemcpyAsync(out->c_ref, sw.out_cref, sizeof(double) * W, hipMemcpyDeviceToHost, s));
+    }
+    MASW_HIP(hipStreamSynchronize(s));
+  }
+  return MASW_OK;
+}
+
+int check_common(masw_ctx* ctx, masw_precision prec, uint32_t flags) {
+  if (prec != MASW_PREC_FP64 && prec != MASW_PREC_SPLIT) return fail(MASW_EINVAL, "prec: unknown precision");
+  if (flags & ~(MASW_DEVICE_PTRS | MASW_NO_REFINE)) return fail(MASW_EINVAL, "flags: unknown bits");
+  if (!ctx) return fail(MASW_EINVAL, "ctx: null context");
+  return MASW_OK;
+}
+
+}  // namespace
+
+// ================================================================ C ABI ==
+extern "C" {
+
+const char* masw_version(void) { return "maswx 0.1.0 (gfx950)"; }
+
+const char* masw_last_error(void) { return g_last_error.c_str(); }
+
+const char* masw_strerror(int code) {
+  switch (code) {
+    case MASW_OK: return "success";
+    case MASW_EINVAL: return "invalid argument";
+    case MASW_ENOMEM: return "request exceeds the HBM budget";
+    case MASW_EBUSY: return "busy / not ready";
+    case MASW_EDEVICE: return "HIP device error";
+    case MASW_ETIMEOUT: return "timed out";
+    case MASW_ENOENT: return "unknown ticket";
+    default: return "unknown error code";
+  }
+}
+
+int masw_create(int device, size_t hbm_budget_bytes, masw_ctx** out) {
+  if (!out) return fail(MASW_EINVAL, "out: null pointer");
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return fail(MASW_EDEVICE, "no HIP device present");
+  if (device < 0 || device >= n) return fail(MASW_EDEVICE, "device index out of range");
+  const size_t budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t(256) << 20);
+  masw_ctx* ctx = new masw_ctx();
+  ctx->device = device;
+  auto cleanup = [&](int code, const std::string& msg) {
+    if (ctx->arena) (void)hipFree(ctx->arena);
+    if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    for (auto& e : ctx->ev)
+      if (e) (void)hipEventDestroy(e);
+    delete ctx;
+    return fail(code, msg);
+  };
+  if (hipSetDevice(device) != hipSuccess) return cleanup(MASW_EDEVICE, "hipSetDevice failed");
+  if (hipDeviceGetAttribute(&ctx->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+    return cleanup(MASW_EDEVICE, "cannot query compute units");
+  if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess)
+    return cleanup(MASW_EDEVICE, "hipStreamCreate failed");
+  for (auto& e : ctx->ev)
+    if (hipEventCreate(&e) != hipSuccess) return cleanup(MASW_EDEVICE, "hipEventCreate failed");
+  if (hipMalloc(&ctx->arena, budget) != hipSuccess) return cleanup(MASW_ENOMEM, "cannot allocate the HBM budget");
+  ctx->arena_size = budget;
+  ctx->counters = reinterpret_cast<Counters*>(ctx->arena);
+  for (int mode = 0; mode < 2; ++mode)
+    for (int lg = 0; lg < 4; ++lg) ctx->blocks_per_cu[mode][lg] = sweep_blocks_per_cu(mode, 1 << lg);
+  *out = ctx;
+  return MASW_OK;
+}
+
+void masw_destroy(masw_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->last_stream && ctx->last_stream != ctx->stream) (void)hipStreamSynchronize(ctx->last_stream);
+  if (ctx->arena) (void)hipFree(ctx->arena);
+  if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  for (auto& e : ctx->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete ctx;
+}
+
+int masw_dispersion_curve(masw_ctx* ctx, const double* c_test, int32_t n_c, const double* lambda,
+                          int32_t n_lambda, const masw_model* model, masw_precision prec, uint32_t flags,
+                          void* stream, double* C_t, int32_t* idx, int32_t* status, double* c_ref) {
+  const bool dev = (flags & MASW_DEVICE_PTRS) != 0;
+  int rc;
+  if (!model) return fail(MASW_EINVAL, "model: null pointer");
+  if ((rc = check_grid(c_test, n_c, !dev))) return rc;
+  if ((rc = check_lambda(lambda, n_lambda, !dev))) return rc;
+  if (dev) {
+    if (model->n_layers < 0 || model->n_layers > MASW_MAX_LAYERS)
+      return fail(MASW_EINVAL, "model: n_layers out of range [0, MASW_MAX_LAYERS]");
+    if ((model->n_layers > 0 && !model->h) || !model->alpha || !model->beta || !model->rho)
+      return fail(MASW_EINVAL, "model: null model array");
+  } else if ((rc = check_model_values(model->n_layers, model->h, model->alpha, model->beta, model->rho,
+                                      "model"))) {
+    return rc;
+  }
+  if (n_lambda > 0 && (!C_t || !idx || !status)) return fail(MASW_EINVAL, "outputs: C_t, idx, status required");
+  if ((rc = check_common(ctx, prec, flags))) return rc;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  Inputs in;
+  in.n_models = 1;
+  in.single_N = model->n_layers;
+  in.single_W = n_lambda;
+  in.h = model->h;
+  in.alpha = model->alpha;
+  in.beta = model->beta;
+  in.rho = model->rho;
+  in.lambda = lambda;
+  in.c = c_test;
+  in.n_c = n_c;
+  in.n_layers_total = model->n_layers;
+  in.n_lam = n_lambda;
+  masw_outputs o{C_t, idx, status, c_ref};
+  return run_curves(ctx, in, prec, flags, stream, &o);
+}
+
+int masw_dispersion_batch(masw_ctx* ctx, const double* c_test, int32_t n_c, const masw_batch* batch,
+                          masw_precision prec, uint32_t flags, void* stream, const masw_outputs* out) {
+  const bool dev = (flags & MASW_DEVICE_PTRS) != 0;
+  int rc;
+  if (!batch) return fail(MASW_EINVAL, "batch: null pointer");
+  if (!out) return fail(MASW_EINVAL, "out: null pointer");
+  if ((rc = check_grid(c_test, n_c, !dev))) return rc;
+  if (batch->n_models < 1) return fail(MASW_EINVAL, "batch: n_models must be >= 1");
+  if (!batch->layer_off || !batch->lambda_off || !batch->alpha || !batch->beta || !batch->rho || !batch->lambda)
+    return fail(MASW_EINVAL, "batch: null array");
+  // Sizes come from the offset arrays, which are read on the host (for
+  // device pointers they are copied back; they are n_models + 1 ints).
+  std::vector<int32_t> loff(size_t(batch->n_models) + 1), woff(size_t(batch->n_models) + 1);
+  if (dev) {
+    if ((rc = check_common(ctx, prec, flags))) return rc;
+    MASW_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = stream ? static_cast<hipStream_t>(stream) : ctx->stream;
+    MASW_HIP(hipMemcpyAsync(loff.data(), batch->layer_off, sizeof(int32_t) * loff.size(), hipMemcpyDeviceToHost, s));
+    MASW_HIP(hipMemcpyAsync(woff.data(), batch->lambda_off, sizeof(int32_t) * woff.size(), hipMemcpyDeviceToHost, s));
+    MASW_HIP(hipStreamSynchronize(s));
+  } else {
+    std::memcpy(loff.data(), batch->layer_off, sizeof(int32_t) * loff.size());
+    std::memcpy(woff.data(), batch->lambda_off, sizeof(int32_t) * woff.size());
+  }
+  if (loff[0] != 0 || woff[0] != 0) return fail(MASW_EINVAL, "batch: offsets must start at 0");
+  for (int m = 0; m < batch->n_models; ++m) {
+    const int32_t N = loff[m + 1] - loff[m];
+    if (N < 0 || N > MASW_MAX_LAYERS) return fail(MASW_EINVAL, "batch: layer_off must be non-decreasing, N <= MASW_MAX_LAYERS");
+    if (woff[m + 1] < woff[m]) return fail(MASW_EINVAL, "batch: lambda_off must be non-decreasing");
+  }
+  const int64_t L = loff[batch->n_models];
+  const int64_t W = woff[batch->n_models];
+  if (L > 0 && !batch->h) return fail(MASW_EINVAL, "batch: null h");
+  if (W > 0 && (!out->c_t || !out->idx || !out->status)) return fail(MASW_EINVAL, "outputs: C_t, idx, status required");
+  if (!dev) {
+    for (int m = 0; m < batch->n_models; ++m) {
+      const int32_t N = loff[m + 1] - loff[m];
+      const int64_t r0 = int64_t(loff[m]) + m;
+      if ((rc = check_model_values(N, batch->h + loff[m], batch->alpha + r0, batch->beta + r0, batch->rho + r0,
+                                   ("batch model " + std::to_string(m)).c_str())))
+        return rc;
+    }
+    if ((rc = check_lambda(batch->lambda, int32_t(W), true))) return rc;
+    if ((rc = check_common(ctx, prec, flags))) return rc;
+  }
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  Inputs in;
+  in.n_models = batch->n_models;
+  in.layer_off = batch->layer_off;
+  in.lambda_off = batch->lambda_off;
+  in.h = batch->h;
+  in.alpha = batch->alpha;
+  in.beta = batch->beta;
+  in.rho = batch->rho;
+  in.lambda = batch->lambda;
+  in.c = c_test;
+  in.n_c = n_c;
+  in.n_layers_total = L;
+  in.n_lam = W;
+  return run_curves(ctx, in, prec, flags, stream, out);
+}
+
+int masw_sign_map(masw_ctx* ctx, const double* c_test, int32_t n_c, const double* lambda, int32_t n_lambda,
+                  const masw_model* model, masw_precision prec, uint32_t flags, void* stream, int8_t* sigma,
+                  double* log_abs_det) {
+  const bool dev = (flags & MASW_DEVICE_PTRS) != 0;
+  int rc;
+  if (!model) return fail(MASW_EINVAL, "model: null pointer");
+  if ((rc = check_grid(c_test, n_c, !dev))) return rc;
+  if ((rc = check_lambda(lambda, n_lambda, !dev))) return rc;
+  if (!dev && (rc = check_model_values(model->n_layers, model->h, model->alpha, model->beta, model->rho, "model")))
+    return rc;
+  if (n_lambda > 0 && !sigma) return fail(MASW_EINVAL, "sigma: null pointer");
+  if ((rc = check_common(ctx, prec, flags))) return rc;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : ctx->stream;
+  Inputs in;
+  in.n_models = 1;
+  in.single_N = model->n_layers;
+  in.single_W = n_lambda;
+  in.n_c = n_c;
+  in.n_layers_total = model->n_layers;
+  in.n_lam = n_lambda;
+  const size_t cells = size_t(n_lambda) * size_t(n_c);
+  size_t need = workspace_bytes(in, !dev, false);
+  if (!dev) need += cells * (sizeof(int8_t) + sizeof(double)) + 2 * kAlign;
+  if (need > ctx->arena_size) return fail(MASW_ENOMEM, "sign map exceeds the HBM budget");
+  MASW_HIP(hipSetDevice(ctx->device));
+  Bump b{ctx->arena, ctx->arena_size, 0};
+  const size_t R = size_t(model->n_layers + 1);
+  PrepArgs p{};
+  p.counters = b.take<Counters>(1);
+  p.models = b.take<ModelDesc>(1);
+  p.layers64 = b.take<LayerRec64>(R);
+  p.layers32 = b.take<LayerRec32>(R);
+  double* c_copy = b.take<double>(size_t(n_c));
+  p.c32 = b.take<float>(size_t(n_c));
+  p.lam_k = b.take<double>(size_t(n_lambda));
+  p.lam_model = b.take<int32_t>(size_t(n_lambda));
+  p.lam_bucket = b.take<uint8_t>(size_t(n_lambda));
+  p.order = b.take<int32_t>(size_t(n_lambda));
+  p.n_models = 1;
+  p.n_c = n_c;
+  p.n_lam = n_lambda;
+  int8_t* sig_dst = sigma;
+  double* log_dst = log_abs_det;
+  if (dev) {
+    p.h = model->h; p.alpha = model->alpha; p.beta = model->beta; p.rho = model->rho;
+    p.lambda = lambda; p.c_in = c_test; p.c64 = const_cast<double*>(c_test);
+  } else {
+    b.take<int32_t>(2); b.take<int32_t>(2);
+    double* hh = b.take<double>(size_t(model->n_layers));
+    double* abr = b.take<double>(R * 3);
+    double* ll = b.take<double>(size_t(n_lambda));
+    if (model->n_layers) MASW_HIP(hipMemcpyAsync(hh, model->h, sizeof(double) * model->n_layers, hipMemcpyHostToDevice, s));
+    MASW_HIP(hipMemcpyAsync(abr, model->alpha, sizeof(double) * R, hipMemcpyHostToDevice, s));
+    MASW_HIP(hipMemcpyAsync(abr + R, model->beta, sizeof(double) * R, hipMemcpyHostToDevice, s));
+    MASW_HIP(hipMemcpyAsync(abr + 2 * R, model->rho, sizeof(double) * R, hipMemcpyHostToDevice, s));
+    if (n_lambda) MASW_HIP(hipMemcpyAsync(ll, lambda, sizeof(double) * n_lambda, hipMemcpyHostToDevice, s));
+    MASW_HIP(hipMemcpyAsync(c_copy, c_test, sizeof(double) * n_c, hipMemcpyHostToDevice, s));
+    p.h = hh; p.alpha = abr; p.beta = abr + R; p.rho = abr + 2 * R; p.lambda = ll; p.c_in = c_copy; p.c64 = c_copy;
+    sig_dst = b.take<int8_t>(cells);
+    log_dst = log_abs_det ? b.take<double>(cells) : nullptr;
+  }
+  if (!b.ok()) return fail(MASW_ENOMEM, "sign map exceeds the HBM budget");
+  MASW_HIP(launch_prep(p, model->n_layers, n_lambda, s));
+  SignMapArgs a{};
+  a.models = p.models;
+  a.layers64 = p.layers64;
+  a.layers32 = p.layers32;
+  a.c64 = p.c64;
+  a.lam_k = p.lam_k;
+  a.n_lam = n_lambda;
+  a.n_c = n_c;
+  a.sigma = sig_dst;
+  a.logabs = log_dst;
+  MASW_HIP(launch_sign_map(prec == MASW_PREC_SPLIT, a, s));
+  ctx->stats_pending = false;
+  ctx->last = masw_stats{};
+  ctx->last_stream = s;
+  if (!dev) {
+    if (cells) {
+      MASW_HIP(hipMemcpyAsync(sigma, sig_dst, cells, hipMemcpyDeviceToHost, s));
+      if (log_abs_det) MASW_HIP(hipMemcpyAsync(log_abs_det, log_dst, cells * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    MASW_HIP(hipStreamSynchronize(s));
+  }
+  return MASW_OK;
+}
+
+int masw_get_stats(masw_ctx* ctx, masw_stats* out) {
+  if (!ctx || !out) return fail(MASW_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  if (ctx->stats_pending) {
+    MASW_HIP(hipSetDevice(ctx->device));
+    if (ctx->last_stream) MASW_HIP(hipStreamSynchronize(ctx->last_stream));
+    Counters c;
+    MASW_HIP(hipMemcpy(&c, ctx->counters, sizeof(Counters), hipMemcpyDeviceToHost));
+    ctx->last.useful_evals = c.useful;
+    ctx->last.sweep_evals = c.sweep;
+    ctx->last.check_evals = c.check;
+    ctx->last.refine_evals = c.refine;
+    MASW_HIP(hipEventElapsedTime(&ctx->last.sweep_ms, ctx->ev[1], ctx->ev[2]));
+    MASW_HIP(hipEventElapsedTime(&ctx->last.total_ms, ctx->ev[0], ctx->ev[2]));
+    ctx->stats_pending = false;
+  }
+  *out = ctx->last;
+  return MASW_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,139 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+declared in include/masw.h, and rejects bad arguments on the host (before any
+HIP call) with MASW_EINVAL and a message naming the failing argument."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2003_02256_amd as M
+import workloads as WL
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "masw.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(masw_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(M.LIB_PATH):
+        pytest.fail("libmasw.so is not built: run __graft_entry__.build()")
+    return M.library()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for want in ("masw_create", "masw_destroy", "masw_dispersion_curve", "masw_dispersion_batch",
+                 "masw_sign_map", "masw_get_stats", "masw_strerror", "masw_last_error"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_strerror_and_version(lib):
+    assert M.masw_strerror(M.MASW_OK) == "success"
+    assert M.masw_strerror(M.MASW_EINVAL) == "invalid argument"
+    assert M.masw_strerror(12345) == "unknown error code"
+    assert "gfx950" in M.masw_version()
+
+
+def _call_curve(c, lam, m, C=None, prec=M.MASW_PREC_FP64, flags=0, ctx=None):
+    W = lam.shape[0]
+    out = (np.empty(W), np.empty(W, np.int32), np.empty(W, np.int32), np.empty(W))
+    mod = M._model_struct(m.h, m.alpha, m.beta, m.rho)
+    rc = M.library().masw_dispersion_curve(ctx, M._ptr(c, np.float64), int(c.shape[0]), M._ptr(lam, np.float64),
+                                           W, ctypes.byref(mod), prec, flags, None,
+                                           *[M._ptr(o, o.dtype.type) for o in out])
+    return rc, M.masw_last_error()
+
+
+def _good():
+    wl = WL.two_layer_case()
+    return wl.c_test.copy(), wl.lambdas[0].copy(), wl.models[0].copy()
+
+
+def test_valid_arguments_reach_the_context_check(lib):
+    c, lam, m = _good()
+    rc, msg = _call_curve(c, lam, m)
+    assert rc == M.MASW_EINVAL and "ctx" in msg
+
+
+@pytest.mark.parametrize("mutate,needle", [
+    (lambda c, l, m: c.__setitem__(5, c[4]), "strictly increasing"),
+    (lambda c, l, m: c.__setitem__(0, np.nan), "finite"),
+    (lambda c, l, m: c.__setitem__(0, -1.0), "finite"),
+    (lambda c, l, m: l.__setitem__(3, 0.0), "lambda"),
+    (lambda c, l, m: l.__setitem__(3, np.inf), "lambda"),
+    (lambda c, l, m: m.h.__setitem__(0, -2.0), "h must"),
+    (lambda c, l, m: m.alpha.__setitem__(1, m.beta[1]), "alpha must exceed beta"),
+    (lambda c, l, m: m.beta.__setitem__(2, np.nan), "finite"),
+    (lambda c, l, m: m.rho.__setitem__(0, 0.0), "finite and > 0"),
+])
+def test_host_validation_rejects(lib, mutate, needle):
+    c, lam, m = _good()
+    mutate(c, lam, m)
+    rc, msg = _call_curve(c, lam, m)
+    assert rc == M.MASW_EINVAL
+    assert needle in msg
+
+
+def test_short_grid_rejected(lib):
+    c, lam, m = _good()
+    rc, msg = _call_curve(c[:1].copy(), lam, m)
+    assert rc == M.MASW_EINVAL and "n_c" in msg
+
+
+def test_bad_precision_and_flags(lib):
+    c, lam, m = _good()
+    rc, msg = _call_curve(c, lam, m, prec=7)
+    assert rc == M.MASW_EINVAL and "prec" in msg
+    rc, msg = _call_curve(c, lam, m, flags=0x80)
+    assert rc == M.MASW_EINVAL and "flags" in msg
+
+
+def test_create_without_device_reports_edevice(lib):
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is present")
+    except Exception:
+        pass
+    ctx = ctypes.c_void_p()
+    rc = lib.masw_create(0, 0, ctypes.byref(ctx))
+    assert rc == M.MASW_EDEVICE and not ctx.value
+
+
+def test_batch_offsets_validated(lib):
+    wl = WL.batch_case(n_models=3, seed=11)
+    arrs = list(M.flatten_models(wl.models, wl.lambdas))
+    arrs[0] = arrs[0].copy()
+    arrs[0][1], arrs[0][2] = arrs[0][2], arrs[0][1]   # layer_off no longer non-decreasing
+    W = arrs[-1].shape[0]
+    out = (np.empty(W), np.empty(W, np.int32), np.empty(W, np.int32), np.empty(W))
+    with pytest.raises(M.MaswError) as e:
+        M.masw_dispersion_batch(None, wl.c_test, *arrs, M.MASW_PREC_SPLIT, 0, None, *out)
+    assert e.value.code == M.MASW_EINVAL
+
+
+def test_sign_map_validates_on_host(lib):
+    c, lam, m = _good()
+    m.alpha[0] = 10.0
+    sig = np.empty(lam.shape[0] * c.shape[0], np.int8)
+    with pytest.raises(M.MaswError) as e:
+        M.masw_sign_map(None, c, lam, m.h, m.alpha, m.beta, m.rho, M.MASW_PREC_FP64, 0, None, sig)
+    assert e.value.code == M.MASW_EINVAL and "alpha" in str(e.value)
+
+
+def test_marshal_rejects_wrong_dtype(lib):
+    c, lam, m = _good()
+    with pytest.raises(M.MaswError):
+        M._ptr(c.astype(np.float32), np.float64)

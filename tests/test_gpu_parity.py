@@ -1,0 +1,311 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Picks must equal the oracle's grid index exactly, unless one of the bracket
+points of either pick lies in the FP64 noise band (cond_2(K) 2(N+1) 2^-53 >=
+1e-2); such wavelengths are counted as NOISE and reported, not compared.
+Refined roots must agree to 1e-6 relative (both sides bisect to a bracket of
+1e-9 c, so the observed gap is far smaller).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2003_02256_amd as M
+import workloads as WL
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+REL_TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def torch_dev(gpu):
+    import torch
+    return torch, torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu):
+    c = M.Context(0, 2 << 30)
+    yield c
+    c.close()
+
+
+def dev_curve(torch_dev, ctx, c_test, lam, model, prec, flags=0):
+    torch, dev = torch_dev
+    t = lambda x: torch.as_tensor(np.ascontiguousarray(x, np.float64), device=dev)
+    W = len(lam)
+    out = (torch.empty(W, dtype=torch.float64, device=dev), torch.empty(W, dtype=torch.int32, device=dev),
+           torch.empty(W, dtype=torch.int32, device=dev), torch.empty(W, dtype=torch.float64, device=dev))
+    M.masw_dispersion_curve(ctx.ctx, t(c_test), t(lam), t(model.h), t(model.alpha), t(model.beta),
+                            t(model.rho), prec, flags, None, *out)
+    torch.cuda.synchronize()
+    return tuple(o.cpu().numpy() for o in out)
+
+
+def dev_batch(torch_dev, ctx, c_test, models, lambdas, prec, flags=0):
+    torch, dev = torch_dev
+    arrs = M.flatten_models(models, lambdas)
+    td = [torch.as_tensor(a, device=dev) for a in arrs]
+    W = int(arrs[-1].shape[0])
+    out = (torch.empty(W, dtype=torch.float64, device=dev), torch.empty(W, dtype=torch.int32, device=dev),
+           torch.empty(W, dtype=torch.int32, device=dev), torch.empty(W, dtype=torch.float64, device=dev))
+    M.masw_dispersion_batch(ctx.ctx, torch.as_tensor(c_test, device=dev), *td, prec, flags, None, *out)
+    torch.cuda.synchronize()
+    return tuple(o.cpu().numpy() for o in out)
+
+
+def compare(name, got, want_idx, want_status, want_cref, lambdas, c_test, model):
+    """Assert parity; return (n_compared, n_noise, max_rel_root_err)."""
+    ct, idx, st, cr = got
+    noise, errs, bad = [], [], []
+    for w in range(len(want_idx)):
+        wi = int(want_idx[w])
+        if idx[w] != wi:
+            pts = {p for i in (int(idx[w]), wi) if i > 0 for p in (i - 1, i)}
+            if any(O.in_noise_band(float(lambdas[w]), float(c_test[p]), model) for p in pts):
+                noise.append(w)
+            else:
+                bad.append((w, int(idx[w]), wi))
+            continue
+        assert st[w] == want_status[w], (name, w, st[w], want_status[w])
+        if wi < 0:
+            assert math.isnan(ct[w]) and math.isnan(cr[w])
+            continue
+        assert ct[w] == c_test[wi]
+        errs.append(abs(cr[w] - want_cref[w]) / want_cref[w])
+    assert not bad, f"{name}: index mismatches outside the noise band (w, gpu, oracle): {bad[:10]}"
+    mx = max(errs) if errs else 0.0
+    print(f"{name}: {len(errs)} compared, {len(noise)} noise, max rel root err {mx:.3e}", flush=True)
+    assert mx <= REL_TOL
+    return len(errs), len(noise), mx
+
+
+def oracle_curve(lambdas, c_test, model):
+    pts = O.dispersion_curve(lambdas, c_test, model)
+    return ([p.idx for p in pts], [p.status for p in pts], [p.c_ref for p in pts])
+
+
+# ------------------------------------------------------------ two-layer case --
+@pytest.mark.parametrize("prec", [M.MASW_PREC_FP64, M.MASW_PREC_SPLIT])
+def test_two_layer_case_matches_oracle(torch_dev, ctx, prec):
+    wl = WL.two_layer_case()
+    m, lam, c = wl.models[0], wl.lambdas[0], wl.c_test
+    got = dev_curve(torch_dev, ctx, c, lam, m, prec)
+    n, n_noise, _ = compare(f"two-layer prec={prec}", got, *oracle_curve(lam, c, m), lam, c, m)
+    assert n == 30 and n_noise == 0
+    s = ctx.stats()
+    assert s["useful_evals"] == 8951
+    assert s["n_lambda"] == 30
+
+
+def test_host_and_device_pointer_paths_agree(torch_dev, ctx):
+    wl = WL.two_layer_case()
+    m, lam, c = wl.models[0], wl.lambdas[0], wl.c_test
+    for prec in (M.MASW_PREC_FP64, M.MASW_PREC_SPLIT):
+        a = ctx.curve(c, lam, m, prec)
+        b = dev_curve(torch_dev, ctx, c, lam, m, prec)
+        for x, y in zip(a, b):
+            np.testing.assert_array_equal(x, y)
+
+
+# ------------------------------------------------------------------ sign map --
+def test_sign_map_fp64_matches_dense_lu(gpu, ctx):
+    wl = WL.two_layer_case()
+    m, lam, c = wl.models[0], wl.lambdas[0], wl.c_test
+    sig, la = ctx.sign_map(c, lam, m, M.MASW_PREC_FP64)
+    osig, ola = O.sign_map(lam, c, m)
+    assert np.array_equal(sig, osig)
+    # away from sign changes log|det| agrees to a relative 1e-10 of det
+    near = np.zeros_like(osig, bool)
+    ch = np.nonzero(osig[:, 1:] != osig[:, :-1])
+    for w, i in zip(*ch):
+        near[w, max(0, i - 2):i + 4] = True
+    d = np.abs(la - ola)[~near]
+    print(f"sign map two-layer: max |d ln|det|| = {d.max():.3e}", flush=True)
+    assert d.max() < 1e-9
+
+
+def test_sign_map_fp64_twenty_layers(gpu, ctx):
+    wl = WL.fine_scale_case()
+    m = wl.models[0]
+    lam = wl.lambdas[0][::100].copy()
+    c = wl.c_test[::97].copy()                      # 1186 points over 50-1200 m/s
+    sig, la = ctx.sign_map(c, lam, m, M.MASW_PREC_FP64)
+    osig, ola = O.sign_map(lam, c, m)
+    mism = np.argwhere(sig != osig)
+    for w, i in mism:
+        assert O.in_noise_band(float(lam[w]), float(c[i]), m), (w, i, sig[w, i], osig[w, i])
+    fin = np.isfinite(ola) & (sig == osig)
+    rel = np.abs(la - ola)[fin]
+    print(f"sign map N=20: {len(mism)} sign mismatches (all in noise band), "
+          f"median |d ln|det|| {np.median(rel):.2e}", flush=True)
+    assert np.median(rel) < 1e-8
+
+
+def test_sign_map_fp32_close_to_fp64(gpu, ctx):
+    wl = WL.two_layer_case()
+    m, lam, c = wl.models[0], wl.lambdas[0], wl.c_test
+    s64, _ = ctx.sign_map(c, lam, m, M.MASW_PREC_FP64, want_log=False)
+    s32, _ = ctx.sign_map(c, lam, m, M.MASW_PREC_SPLIT, want_log=False)
+    bad = np.argwhere(s32 != s64)
+    print(f"FP32 sign map: {len(bad)} of {s64.size} signs differ from FP64", flush=True)
+    assert len(bad) <= s64.size // 1000
+
+
+# ------------------------------------------------------------------ edge cases --
+def test_homogeneous_halfspace_root(torch_dev, ctx):
+    beta = 400.0
+    m = WL.Model(np.zeros(0), np.array([math.sqrt(3) * beta]), np.array([beta]), np.array([2000.0]))
+    c = WL.uniform_grid(300.0, 0.01, 10001)
+    lam = np.array([0.5, 5.0, 50.0])
+    cR = beta * math.sqrt(2 - 2 / math.sqrt(3))
+    for prec in (M.MASW_PREC_FP64, M.MASW_PREC_SPLIT):
+        ct, idx, st, cr = dev_curve(torch_dev, ctx, c, lam, m, prec)
+        assert np.all(st == 0)
+        assert np.all(c[idx - 1] < cR) and np.all(cR <= c[idx])
+        assert np.max(np.abs(cr - cR) / cR) < 1e-8
+
+
+def test_not_found_and_tiny_grids(torch_dev, ctx):
+    wl = WL.two_layer_case()
+    m = wl.models[0]
+    lam = np.array([1.0, 40.0])
+    for prec in (M.MASW_PREC_FP64, M.MASW_PREC_SPLIT):
+        c = WL.uniform_grid(50.0, 0.5, 100)     # entirely below every root
+        ct, idx, st, cr = dev_curve(torch_dev, ctx, c, lam, m, prec)
+        assert np.all(idx == -1) and np.all(st == M.MASW_STATUS_NOT_FOUND)
+        assert np.all(np.isnan(ct)) and np.all(np.isnan(cr))
+        c2 = np.array([137.0, 139.0])           # n_c = 2, root of lambda = 1 inside
+        ct, idx, st, cr = dev_curve(torch_dev, ctx, c2, np.array([1.0]), m, prec)
+        p = O.dispersion_point(1.0, c2, m)
+        assert idx[0] == p.idx == 1 and abs(cr[0] - p.c_ref) < 1e-6 * p.c_ref
+
+
+@pytest.mark.parametrize("n_c", [65, 127, 129, 300, 513, 1000, 1537])
+def test_ragged_grid_lengths(torch_dev, ctx, n_c):
+    # grid lengths around multiples of 64 and of the multi-wavefront rounds
+    wl = WL.two_layer_case()
+    m = wl.models[0]
+    c = WL.uniform_grid(130.0, 190.0 / n_c, n_c)
+    lam = wl.lambdas[0]
+    want = oracle_curve(lam, c, m)
+    for prec in (M.MASW_PREC_FP64, M.MASW_PREC_SPLIT):
+        compare(f"ragged n_c={n_c} prec={prec}", dev_curve(torch_dev, ctx, c, lam, m, prec), *want, lam, c, m)
+
+
+def test_empty_wavelength_list(torch_dev, ctx):
+    wl = WL.two_layer_case()
+    got = dev_curve(torch_dev, ctx, wl.c_test, np.zeros(0), wl.models[0], M.MASW_PREC_FP64)
+    assert all(g.shape == (0,) for g in got)
+
+
+def test_device_side_validation_marks_invalid(torch_dev, ctx):
+    wl = WL.two_layer_case()
+    m = wl.models[0].copy()
+    m.alpha[1] = 0.5 * m.beta[1]                  # alpha < beta: invalid
+    ct, idx, st, cr = dev_curve(torch_dev, ctx, wl.c_test, wl.lambdas[0], m, M.MASW_PREC_FP64)
+    assert np.all(st == M.MASW_STATUS_INVALID) and np.all(idx == -1)
+    c = wl.c_test.copy()
+    c[10] = c[9]                                  # grid not strictly increasing
+    ct, idx, st, cr = dev_curve(torch_dev, ctx, c, wl.lambdas[0], wl.models[0], M.MASW_PREC_SPLIT)
+    assert np.all(st == M.MASW_STATUS_INVALID)
+    lam = wl.lambdas[0].copy()
+    lam[3] = -1.0                                 # one bad wavelength only
+    ct, idx, st, cr = dev_curve(torch_dev, ctx, wl.c_test, lam, wl.models[0], M.MASW_PREC_FP64)
+    assert st[3] == M.MASW_STATUS_INVALID and np.all(np.delete(st, 3) == 0)
+
+
+def test_many_layers(torch_dev, ctx):
+    rng = np.random.Generator(np.random.PCG64(21))
+    m = WL.increasing_profile(rng, 120)
+    c = WL.uniform_grid(100.0, 0.25, 1200)
+    lam = np.array([1.0, 3.0, 9.0])
+    want = oracle_curve(lam, c, m)
+    for prec in (M.MASW_PREC_FP64, M.MASW_PREC_SPLIT):
+        compare(f"N=120 prec={prec}", dev_curve(torch_dev, ctx, c, lam, m, prec), *want, lam, c, m)
+
+
+def test_low_velocity_layer_models(torch_dev, ctx):
+    rng = np.random.Generator(np.random.PCG64(33))
+    c = WL.uniform_grid(50.0, 0.05, 8001)
+    for trial in range(4):
+        m = WL.increasing_profile(rng, 6)
+        m.beta[2] = 0.7 * m.beta[1]
+        m.alpha[2] = 2.0 * m.beta[2]
+        lam = WL.log_spaced(1.0, 60.0, 12)
+        want = oracle_curve(lam, c, m)
+        for prec in (M.MASW_PREC_FP64, M.MASW_PREC_SPLIT):
+            compare(f"inversion trial {trial} prec={prec}", dev_curve(torch_dev, ctx, c, lam, m, prec),
+                    *want, lam, c, m)
+
+
+def test_repeat_runs_bitwise_identical(torch_dev, ctx):
+    wl = WL.fine_scale_case()
+    lam = wl.lambdas[0][::10].copy()
+    a = dev_curve(torch_dev, ctx, wl.c_test, lam, wl.models[0], M.MASW_PREC_SPLIT)
+    b = dev_curve(torch_dev, ctx, wl.c_test, lam, wl.models[0], M.MASW_PREC_SPLIT)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+
+
+# ---------------------------------------------------- full-size fine-scale case --
+def _golden(name):
+    path = os.path.join(HERE, "golden", name)
+    if not os.path.exists(path):
+        pytest.fail(f"missing {path}: run tests/golden/make_golden.py")
+    return json.load(open(path))
+
+
+@pytest.mark.parametrize("prec", [M.MASW_PREC_FP64, M.MASW_PREC_SPLIT])
+def test_fine_scale_full_size(torch_dev, ctx, prec):
+    g = _golden("fine_scale.json")
+    wl = WL.fine_scale_case()
+    m, lam, c = wl.models[0], wl.lambdas[0], wl.c_test
+    got = dev_curve(torch_dev, ctx, c, lam, m, prec)
+    compare(f"fine-scale prec={prec}", got, g["idx"], g["status"], [float(x) for x in g["c_ref"]], lam, c, m)
+    s = ctx.stats()
+    useful = int(np.sum(np.asarray(g["idx"]) + 1))
+    assert s["useful_evals"] == useful
+    print(f"fine-scale prec={prec}: stats {s}", flush=True)
+
+
+# ------------------------------------------------------------ batched launch --
+def test_batch_sample_and_split_vs_fp64(torch_dev, ctx):
+    g = _golden("batch_sample.json")
+    wl = WL.batch_case()
+    arrs = M.flatten_models(wl.models, wl.lambdas)
+    lam_off = arrs[5]
+    split = dev_batch(torch_dev, ctx, wl.c_test, wl.models, wl.lambdas, M.MASW_PREC_SPLIT)
+    s_split = ctx.stats()
+    fp64 = dev_batch(torch_dev, ctx, wl.c_test, wl.models, wl.lambdas, M.MASW_PREC_FP64)
+    print(f"batch split stats {s_split}; fp64 stats {ctx.stats()}", flush=True)
+    for entry in g["models"]:
+        mi = entry["model"]
+        sl = slice(int(lam_off[mi]), int(lam_off[mi + 1]))
+        for name, res in (("split", split), ("fp64", fp64)):
+            compare(f"batch model {mi} {name}", tuple(r[sl] for r in res), entry["idx"], entry["status"],
+                    [float(x) for x in entry["c_ref"]], wl.lambdas[mi], wl.c_test, wl.models[mi])
+    # every wavelength of the batch: the split path equals the FP64 path
+    diff = np.nonzero(split[1] != fp64[1])[0]
+    print(f"batch: {len(diff)} of {len(split[1])} split picks differ from FP64 picks", flush=True)
+    assert len(diff) <= len(split[1]) // 100000
+    ok = (split[1] == fp64[1]) & (split[1] >= 0)
+    rel = np.abs(split[3] - fp64[3])[ok] / fp64[3][ok]
+    assert rel.max() <= REL_TOL
+
+
+def test_batch_equals_single_model_runs(torch_dev, ctx):
+    # a model's curve is the same alone and inside a batch (bitwise)
+    wl = WL.batch_case(n_models=24, seed=9)
+    res = dev_batch(torch_dev, ctx, wl.c_test, wl.models, wl.lambdas, M.MASW_PREC_SPLIT)
+    off = 0
+    for m, lam in zip(wl.models, wl.lambdas):
+        alone = dev_curve(torch_dev, ctx, wl.c_test, lam, m, M.MASW_PREC_SPLIT)
+        for x, y in zip(alone, res):
+            np.testing.assert_array_equal(x, y[off:off + len(lam)])
+        off += len(lam)
