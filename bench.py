@@ -43,6 +43,27 @@ def flops_per_eval(n_layers: float) -> float:
     return 101.0 * n_layers + 48.0
 
 
+# HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs each scaled by the same counter's reading for a plain copy of
+# known size (FETCH x 2.000, WRITE x 1.000); see profiles/.  Keyed by the hash
+# of the kernel sources the counters were taken on, the workload and the
+# launch, so a changed kernel reports null until it is measured again.
+MEASURED_TRAFFIC = {
+    ("445b2599ee6b6ce2", "fine_scale_N20_1000lam_115001c", "sweep_kernel<FP64,G=8>"):
+        1362.3 * 1024 * 2.000 + 141.8 * 1024 * 1.000,
+}
+KERNEL_SOURCES = ["masw_internal.hpp", "masw_math.hpp", "masw_special.hpp", "masw_kernels.hip"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2003_02256_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
@@ -155,6 +176,9 @@ def main():
     ap.add_argument("--workload", default="fine_scale", choices=["fine_scale", "two_layer", "batch"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target CPU work of the oracle sample")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB three times (the reference "
+                         "for scaling HBM counter readings) and exit")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported (the dispersion path has no "
@@ -166,6 +190,15 @@ def main():
     import paper_2003_02256_amd as M
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
+    if a.calibrate_copy:
+        n = a.calibrate_copy << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "copies": 3}), flush=True)
+        return
     M.library()
     dev = torch.device("cuda:0")
     wl = make_workload(a.workload)
@@ -200,6 +233,8 @@ def main():
     flops64 = performed64 * flops_per_eval(nbar)
     achieved = flops64 / (sweep64 * 1e-3) / 1e12
     n_curves = len(wl.models)
+    kname = f"sweep_kernel<FP64,G={st64['waves_per_item']}>"
+    traffic = MEASURED_TRAFFIC.get((kernel_source_hash(), wl.name, kname))
 
     res = {
         "metric": METRIC,
@@ -233,8 +268,8 @@ def main():
             "root_rel_err_vs_fp64_mean": float(root_rel.mean()) if root_rel.size else None,
         },
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-                     "kernel": f"sweep_kernel<FP64,G={st64['waves_per_item']}>",
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
+                     "kernel": kname,
                      "kernel_ms": sweep64, "flops_per_launch": flops64},
     }
     if not a.no_cpu_baseline:

@@ -10,7 +10,7 @@
 // LDS, so the first sign change is known after the round and the item stops
 // (Algorithm 1's early exit; the paper's GPU design evaluated every (lambda, c)
 // instead, Section 2.3).  G is chosen by the host: 1 when there are many more
-// items than wavefront slots, up to 8 when a few deep items must fill the chip.
+// items than wavefront slots, up to 16 when a few deep items must fill the chip.
 #include <hip/hip_runtime.h>
 
 #include "masw_internal.hpp"
@@ -256,8 +256,10 @@ __global__ __launch_bounds__(64 * G) void sweep_kernel(SweepArgs a) {
   __shared__ int s_last[G];
   __shared__ int s_first[G];
   __shared__ int s_pair[2];
+  __shared__ int s_check[4];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
+  const int wave = tid >> 6;
   unsigned long long n_sweep = 0, n_check = 0, n_refine = 0, n_useful = 0;
 
   for (;;) {
@@ -319,15 +321,29 @@ __global__ __launch_bounds__(64 * G) void sweep_kernel(SweepArgs a) {
         }
         if (cand < 0) break;
         // FP64 re-check of the 64 positions ws-1 .. ws+62 around the
-        // candidate (48 before it, 15 after), one per lane.  Each wavefront of
-        // the group evaluates the same window, so the outcome does not depend
-        // on how many wavefronts share the item.
+        // candidate (48 before it, 15 after), one per lane of wavefront 0;
+        // the other wavefronts wait.  The window does not depend on the
+        // group size, so neither does the outcome.
         const int ws = max(1, cand - 48);
-        const int i = ws - 1 + lane;
-        const int sg = (i < n_c) ? det_sign<double, false>(c64[i], k64, L64, N, nullptr) : kNoSign;
-        int last;
-        const int f = wave_first_change(sg, &sig_f, &prev_f, &last);
-        n_check += (unsigned long long)(G * min(64, n_c - (ws - 1)));
+        if (wave == 0) {
+          const int i = ws - 1 + lane;
+          const int sg = (i < n_c) ? det_sign<double, false>(c64[i], k64, L64, N, nullptr) : kNoSign;
+          int last, s_c = 0, p_c = 0;
+          const int f = wave_first_change(sg, &s_c, &p_c, &last);
+          if (lane == 0) {
+            s_check[0] = f;
+            s_check[1] = last;
+            s_check[2] = s_c;
+            s_check[3] = p_c;
+          }
+        }
+        __syncthreads();
+        const int f = s_check[0];
+        const int last = s_check[1];
+        sig_f = s_check[2];
+        prev_f = s_check[3];
+        __syncthreads();
+        n_check += (unsigned long long)min(64, n_c - (ws - 1));
         if (f >= 0) {
           found = ws - 1 + f;
         } else {
@@ -351,41 +367,44 @@ __global__ __launch_bounds__(64 * G) void sweep_kernel(SweepArgs a) {
     }
     n_useful += (unsigned long long)(found + 1);
 
-    int status = MASW_STATUS_FOUND;
-    if (sig_f == kNaNSign || prev_f == kNaNSign) status = MASW_STATUS_NAN;
-    double c_ref = __builtin_nan("");
-
-    if (status == MASW_STATUS_FOUND) {
-      // FP64 multisection of [c[found-1], c[found]]: 64 points per round,
-      // both ends included, one per lane; the new bracket is the first sign
-      // change.  Each wavefront of the group runs the same rounds (the result
-      // is independent of the group size).  The first round also yields the
-      // layer-denominator sign masks at the two grid points (pole flag).
-      double lo = c64[found - 1], hi = c64[found];
-      const double tol = kRefineRel * hi;
-      for (int r = 0; r < 24; ++r) {
-        const double w = hi - lo;
-        const double c = (lane == 63) ? hi : lo + w * (double(lane) / 63.0);
-        uint64_t dm = 0;
-        const int sg = det_sign<double, true>(c, k64, L64, N, &dm);
-        if (r == 0 && __shfl(dm, 0, 64) != __shfl(dm, 63, 64)) status |= MASW_FLAG_POLE;
-        int s_c = 0, p_c = 0, unused;
-        const int f = wave_first_change(sg, &s_c, &p_c, &unused);
-        n_refine += (unsigned long long)(64 * G);
-        if (f < 0 || s_c == kNaNSign || p_c == kNaNSign) break;
-        const double nhi = (f == 63) ? hi : lo + w * (double(f) / 63.0);
-        const double nlo = lo + w * (double(f - 1) / 63.0);
-        lo = nlo;
-        hi = nhi;
-        if (!a.refine || hi - lo <= tol) break;
+    // Refinement and output by wavefront 0 alone; the others go on to the
+    // next item's queue barrier.  One wavefront at a time on a SIMD finishes
+    // these few rounds sooner than the whole group sharing the SIMDs would.
+    if (wave == 0) {
+      int status = MASW_STATUS_FOUND;
+      if (sig_f == kNaNSign || prev_f == kNaNSign) status = MASW_STATUS_NAN;
+      double c_ref = __builtin_nan("");
+      if (status == MASW_STATUS_FOUND) {
+        // FP64 multisection of [c[found-1], c[found]]: 64 points per round,
+        // both ends included, one per lane; the new bracket is the first
+        // sign change.  The first round also yields the layer-denominator
+        // sign masks at the two grid points (pole flag).
+        double lo = c64[found - 1], hi = c64[found];
+        const double tol = kRefineRel * hi;
+        for (int r = 0; r < 24; ++r) {
+          const double w = hi - lo;
+          const double c = (lane == 63) ? hi : lo + w * (double(lane) / 63.0);
+          uint64_t dm = 0;
+          const int sg = det_sign<double, true>(c, k64, L64, N, &dm);
+          if (r == 0 && __shfl(dm, 0, 64) != __shfl(dm, 63, 64)) status |= MASW_FLAG_POLE;
+          int s_c = 0, p_c = 0, unused;
+          const int f = wave_first_change(sg, &s_c, &p_c, &unused);
+          n_refine += 64ull;
+          if (f < 0 || s_c == kNaNSign || p_c == kNaNSign) break;
+          const double nhi = (f == 63) ? hi : lo + w * (double(f) / 63.0);
+          const double nlo = lo + w * (double(f - 1) / 63.0);
+          lo = nlo;
+          hi = nhi;
+          if (!a.refine || hi - lo <= tol) break;
+        }
+        if (a.refine) c_ref = 0.5 * (lo + hi);
       }
-      if (a.refine) c_ref = 0.5 * (lo + hi);
-    }
-    if (tid == 0) {
-      a.out_idx[g] = found;
-      a.out_status[g] = status;
-      a.out_ct[g] = c64[found];
-      if (a.out_cref) a.out_cref[g] = c_ref;
+      if (tid == 0) {
+        a.out_idx[g] = found;
+        a.out_status[g] = status;
+        a.out_ct[g] = c64[found];
+        if (a.out_cref) a.out_cref[g] = c_ref;
+      }
     }
   }
   if (tid == 0) {
@@ -439,23 +458,20 @@ __global__ __launch_bounds__(256) void sign_map_kernel(SignMapArgs a) {
 }
 
 // --------------------------------------------------------- host launchers --
-static const void* sweep_symbol(int mode, int G) {
-  if (mode == kModeFP64) {
-    switch (G) {
-      case 1: return reinterpret_cast<const void*>(&sweep_kernel<kModeFP64, 1>);
-      case 2: return reinterpret_cast<const void*>(&sweep_kernel<kModeFP64, 2>);
-      case 4: return reinterpret_cast<const void*>(&sweep_kernel<kModeFP64, 4>);
-      case 8: return reinterpret_cast<const void*>(&sweep_kernel<kModeFP64, 8>);
-    }
-  } else {
-    switch (G) {
-      case 1: return reinterpret_cast<const void*>(&sweep_kernel<kModeSplit, 1>);
-      case 2: return reinterpret_cast<const void*>(&sweep_kernel<kModeSplit, 2>);
-      case 4: return reinterpret_cast<const void*>(&sweep_kernel<kModeSplit, 4>);
-      case 8: return reinterpret_cast<const void*>(&sweep_kernel<kModeSplit, 8>);
-    }
+template <int MODE>
+static const void* sweep_symbol_mode(int G) {
+  switch (G) {
+    case 1: return reinterpret_cast<const void*>(&sweep_kernel<MODE, 1>);
+    case 2: return reinterpret_cast<const void*>(&sweep_kernel<MODE, 2>);
+    case 4: return reinterpret_cast<const void*>(&sweep_kernel<MODE, 4>);
+    case 8: return reinterpret_cast<const void*>(&sweep_kernel<MODE, 8>);
+    case 16: return reinterpret_cast<const void*>(&sweep_kernel<MODE, 16>);
   }
   return nullptr;
+}
+
+static const void* sweep_symbol(int mode, int G) {
+  return mode == kModeFP64 ? sweep_symbol_mode<kModeFP64>(G) : sweep_symbol_mode<kModeSplit>(G);
 }
 
 int sweep_blocks_per_cu(int mode, int G) {

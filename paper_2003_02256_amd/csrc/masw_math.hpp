@@ -26,32 +26,31 @@
 // (the last row is the removable 0/0 at c = alpha or c = beta).  a and Sh are
 // formed from expm1 or from the half-angle sin/cos so that the long-wavelength
 // cancellation 1 - cosh cosh is never computed as a difference of O(1) terms.
+// Divisions are reciprocals refined to about 1 ulp (masw_special.hpp): only the
+// sign of the determinant is used, and a last-bit difference in a quotient is
+// far below the rounding of the elimination itself.
 #pragma once
 #include <hip/hip_runtime.h>
 
 #include "masw_internal.hpp"
+#include "masw_special.hpp"
 
 namespace masw {
 
 // ---------------------------------------------------------------- helpers --
 template <typename T>
-struct Fn;
-
+__device__ __forceinline__ T sqrt_(T x) {
+  return __builtin_sqrt(x);
+}
 template <>
-struct Fn<double> {
-  static __device__ __forceinline__ double sqrt_(double x) { return __builtin_sqrt(x); }
-  static __device__ __forceinline__ double expm1_(double x) { return ::expm1(x); }
-  static __device__ __forceinline__ void sincos_(double x, double* s, double* c) { ::sincos(x, s, c); }
-};
+__device__ __forceinline__ float sqrt_(float x) {
+  return __builtin_sqrtf(x);
+}
 
-template <>
-struct Fn<float> {
-  static __device__ __forceinline__ float sqrt_(float x) { return __builtin_sqrtf(x); }
-  static __device__ __forceinline__ float expm1_(float x) { return ::expm1f(x); }
-  static __device__ __forceinline__ void sincos_(float x, float* s, float* c) { ::sincosf(x, s, c); }
-};
-
-// The four E-scaled functions of one potential (see the file comment).
+// The four E-scaled functions of one potential (see the file comment).  One
+// reciprocal square root gives both q and 1/q; the half-angle form
+// cos(tq) - 1 = -2 sin^2(tq/2), sin(tq) = 2 sin(tq/2) cos(tq/2) keeps the
+// small-angle end exact.
 template <typename T>
 struct Terms {
   T E, a, Sh, R;
@@ -61,21 +60,23 @@ template <typename T>
 __device__ __forceinline__ Terms<T> potential_terms(T x, T t) {
   Terms<T> o;
   if (x > T(0)) {
-    const T q = Fn<T>::sqrt_(x);
-    const T m = Fn<T>::expm1_(-t * q);       // E - 1
+    const T iq = special::rsqrt(x);
+    const T q = x * iq;
+    const T m = special::expm1_neg(t * q);       // E - 1
     const T half_sh = T(-0.5) * m * (T(2) + m);  // E sinh(tq) = (1 - E^2) / 2
     o.E = T(1) + m;
-    o.a = T(0.5) * m * m;                    // E cosh - E = (1 - E)^2 / 2
-    o.Sh = half_sh / q;
+    o.a = T(0.5) * m * m;                        // E cosh - E = (1 - E)^2 / 2
+    o.Sh = half_sh * iq;
     o.R = half_sh * q;
   } else if (x < T(0)) {
-    const T q = Fn<T>::sqrt_(-x);
-    T hs, hc;
-    Fn<T>::sincos_(T(0.5) * t * q, &hs, &hc);
-    const T sn = T(2) * hs * hc;             // sin(tq)
+    const T iq = special::rsqrt(-x);
+    const T q = -x * iq;
+    T s2, sc;
+    special::sin2_sincos(T(0.5) * t * q, &s2, &sc);
+    const T sn = T(2) * sc;                      // sin(tq)
     o.E = T(1);
-    o.a = T(-2) * hs * hs;                   // cos(tq) - 1
-    o.Sh = sn / q;
+    o.a = T(-2) * s2;                            // cos(tq) - 1
+    o.Sh = sn * iq;
     o.R = -q * sn;
   } else {
     o.E = T(1);
@@ -108,7 +109,7 @@ __device__ __forceinline__ LayerK<T> layer_entries(T c2, T t, T ia2, T ib2, T rh
   const T u = P.E * S.a + P.a * S.E + P.a * S.a;  // E_r E_s (C_r C_s - 1)
   LayerK<T> o;
   o.gD = T(-2) * u + P.Sh * S.Sh + P.R * S.R;
-  const T F = rh * c2 / o.gD;    // f / (k mu_ref) with the E factors cancelled
+  const T F = rh * c2 * special::rcp(o.gD);  // f / (k mu_ref), E factors cancelled
   o.k11 = F * (Cr * S.Sh - P.R * Cs);
   o.k12 = F * (u - P.R * S.R) - mh * (T(1) + xs);
   o.k13 = F * (P.R * S.E - S.Sh * P.E);
@@ -134,7 +135,7 @@ __device__ __forceinline__ T schur_layer(Block2<T>& S, const LayerK<T>& K) {
   const T s12 = S.s12 + K.k12;
   const T s22 = S.s22 + K.k22;
   const T d = s11 * s22 - s12 * s12;
-  const T id = T(1) / d;
+  const T id = special::rcp(d);
   // Q_j = [[k13, k14], [-k14, k24]];  W = adj(S_j) Q_j;  M = Q_j^T W
   const T q11 = K.k13, q12 = K.k14, q21 = -K.k14, q22 = K.k24;
   const T w11 = s22 * q11 - s12 * q21;
@@ -162,13 +163,13 @@ __device__ __forceinline__ void halfspace_det(const Block2<T>& S, T c2, T ia2, T
                                               T* re, T* im) {
   const T xr = T(1) - c2 * ia2;
   const T xs = T(1) - c2 * ib2;
-  const T qr = Fn<T>::sqrt_(xr < T(0) ? -xr : xr);
-  const T qs = Fn<T>::sqrt_(xs < T(0) ? -xs : xs);
+  const T qr = sqrt_<T>(xr < T(0) ? -xr : xr);  // may be exactly 0 (c = alpha)
+  const T qs = sqrt_<T>(xs < T(0) ? -xs : xs);
   const T rr = xr >= T(0) ? qr : T(0), ri = xr >= T(0) ? T(0) : qr;
   const T sr = xs >= T(0) ? qs : T(0), si = xs >= T(0) ? T(0) : qs;
   const T dr = T(1) - (rr * sr - ri * si);  // 1 - r s
   const T di = -(rr * si + ri * sr);
-  const T inv = T(1) / (dr * dr + di * di);
+  const T inv = special::rcp(dr * dr + di * di);
   const T zr = dr * inv, zi = -di * inv;    // 1 / (1 - r s)
   const T mu = mh * (c2 * ib2);             // mh (1 - s^2)
   const T h11r = mu * (rr * zr - ri * zi), h11i = mu * (rr * zi + ri * zr);
@@ -179,6 +180,27 @@ __device__ __forceinline__ void halfspace_det(const Block2<T>& S, T c2, T ia2, T
   const T er = S.s12 + h12r, ei = h12i;
   *re = ar * br - ai * bi - (er * er - ei * ei);
   *im = ar * bi + ai * br - T(2) * er * ei;
+}
+
+// Layer records are read-only for a whole launch and uniform across a
+// wavefront; reading them through the constant address space lets the
+// compiler use scalar loads into SGPRs, which VALU instructions take as
+// operands without occupying vector registers.
+template <typename T>
+using ConstRec = const __attribute__((address_space(4))) LayerRec<T>;
+
+template <typename T>
+__device__ __forceinline__ LayerRec<T> load_rec(const LayerRec<T>* L, int j) {
+  ConstRec<T>* p = (ConstRec<T>*)(L) + j;  // address-space cast (generic -> constant)
+  LayerRec<T> r;
+  r.ia2 = p->ia2;
+  r.ib2 = p->ib2;
+  r.rh = p->rh;
+  r.mh = p->mh;
+  r.h = p->h;
+  r.aux = p->aux;
+  r.pad1 = r.pad2 = T(0);
+  return r;
 }
 
 __device__ __forceinline__ int sign_code(bool negative, double v) {
@@ -199,13 +221,13 @@ __device__ __forceinline__ int det_sign(T c, T k, const LayerRec<T>* __restrict_
   bool neg = false;
   uint64_t mask = 0;
   for (int j = 0; j < N; ++j) {
-    const LayerRec<T> rec = L[j];
+    const LayerRec<T> rec = load_rec<T>(L, j);
     const LayerK<T> K = layer_entries<T>(c2, k * rec.h, rec.ia2, rec.ib2, rec.rh, rec.mh);
     if (kMask) mask ^= uint64_t(K.gD < T(0)) << (j & 63);
     const T d = schur_layer<T>(S, K);
     neg ^= (d < T(0));
   }
-  const LayerRec<T> hs = L[N];
+  const LayerRec<T> hs = load_rec<T>(L, N);
   T re, im;
   halfspace_det<T>(S, c2, hs.ia2, hs.ib2, hs.mh, &re, &im);
   if (kMask) *dmask = mask;
@@ -222,13 +244,13 @@ __device__ __forceinline__ int det_sign_logabs(T c, T k, const LayerRec<T>* __re
   bool neg = false;
   double acc = 0.0;
   for (int j = 0; j < N; ++j) {
-    const LayerRec<T> rec = L[j];
+    const LayerRec<T> rec = load_rec<T>(L, j);
     const LayerK<T> K = layer_entries<T>(c2, k * rec.h, rec.ia2, rec.ib2, rec.rh, rec.mh);
     const T d = schur_layer<T>(S, K);
     neg ^= (d < T(0));
     acc += ::log(::fabs(double(d)));
   }
-  const LayerRec<T> hs = L[N];
+  const LayerRec<T> hs = load_rec<T>(L, N);
   T re, im;
   halfspace_det<T>(S, c2, hs.ia2, hs.ib2, hs.mh, &re, &im);
   acc += ::log(::hypot(double(re), double(im)));

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -50,7 +51,8 @@ struct masw_ctx {
   char* arena = nullptr;
   size_t arena_size = 0;
   int cus = 0;
-  int blocks_per_cu[2][4] = {};   // [mode][log2 G]
+  int blocks_per_cu[2][5] = {};   // [mode][log2 G], G = 1..16
+  int forced_waves = 0;           // MASW_WAVES_PER_ITEM override (tuning)
   std::mutex mu;
   masw_stats last = {};
   bool stats_pending = false;
@@ -162,20 +164,32 @@ size_t workspace_bytes(const Inputs& in, bool stage_inputs, bool stage_outputs) 
   return b.off + kAlign;
 }
 
+int log2_of(int g) { return g <= 1 ? 0 : g <= 2 ? 1 : g <= 4 ? 2 : g <= 8 ? 3 : 4; }
+
+// Wavefronts per item.  Items run to an early exit whose depth varies by two
+// orders of magnitude across wavelengths, so a launch with few items is
+// bounded by its deepest item: give each item as many wavefronts as keeps
+// every item queued at most about four times over the resident slots, and one
+// wavefront per item when items outnumber slots.  G stays small enough that
+// two groups fit on a compute unit, so that one group's single-wavefront FP64
+// re-check and refinement overlap the other group's sweep.  The persistent
+// grid then pulls items longest-expected-first until the queue is empty.
 int pick_waves_per_item(masw_ctx* ctx, int mode, int64_t n_items, int* blocks) {
-  // One wavefront per item when items outnumber wavefront slots; otherwise
-  // split each item over G wavefronts so that items * G roughly fills them.
   int G = 1;
-  for (int lg = 3; lg >= 0; --lg) {
-    const int g = 1 << lg;
-    const int64_t slots = int64_t(ctx->cus) * ctx->blocks_per_cu[mode][lg] * g;
-    if (n_items * g <= slots) {
-      G = g;
-      break;
+  if (ctx->forced_waves) {
+    G = ctx->forced_waves;
+  } else {
+    for (int lg = 4; lg >= 0; --lg) {
+      const int g = 1 << lg;
+      const int bpc = ctx->blocks_per_cu[mode][lg];
+      const int64_t slots = int64_t(ctx->cus) * bpc * g;
+      if (bpc >= 2 && n_items * g <= 4 * slots) {
+        G = g;
+        break;
+      }
     }
   }
-  const int lg = G == 1 ? 0 : G == 2 ? 1 : G == 4 ? 2 : 3;
-  const int64_t max_blocks = int64_t(ctx->cus) * std::max(1, ctx->blocks_per_cu[mode][lg]);
+  const int64_t max_blocks = int64_t(ctx->cus) * std::max(1, ctx->blocks_per_cu[mode][log2_of(G)]);
   *blocks = int(std::max<int64_t>(1, std::min<int64_t>(n_items, max_blocks)));
   return G;
 }
@@ -361,7 +375,11 @@ int masw_create(int device, size_t hbm_budget_bytes, masw_ctx** out) {
   ctx->arena_size = budget;
   ctx->counters = reinterpret_cast<Counters*>(ctx->arena);
   for (int mode = 0; mode < 2; ++mode)
-    for (int lg = 0; lg < 4; ++lg) ctx->blocks_per_cu[mode][lg] = sweep_blocks_per_cu(mode, 1 << lg);
+    for (int lg = 0; lg < 5; ++lg) ctx->blocks_per_cu[mode][lg] = sweep_blocks_per_cu(mode, 1 << lg);
+  if (const char* f = std::getenv("MASW_WAVES_PER_ITEM")) {
+    const int g = std::atoi(f);
+    if (g == 1 || g == 2 || g == 4 || g == 8 || g == 16) ctx->forced_waves = g;
+  }
   *out = ctx;
   return MASW_OK;
 }
