@@ -126,6 +126,101 @@ def time_path(job, ctx, prec, steps, warmup):
     return wall, float(np.mean(sweep_ms)), float(np.mean(total_ms)), stats
 
 
+# ------------------------------------------------------------------ serving --
+def serving_trace(rate: float, warm_s: float, dur_s: float, seed: int = 55):
+    """Arrival times and request models: each arrival picks one of 64 chains
+    uniformly and advances it one random-walk step."""
+    import workloads as WL
+    bases = WL.chain_bases(64, 5)
+    times = WL.poisson_arrivals(rate, warm_s + dur_s, seed)
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    pick = rng.integers(0, len(bases), size=len(times))
+    state = [b.model for b in bases]
+    reqs = []
+    for i in range(len(times)):
+        ch = int(pick[i])
+        state[ch] = WL.chain_step(rng, state[ch])
+        m = state[ch]
+        reqs.append((np.ascontiguousarray(m.h), np.ascontiguousarray(m.alpha), np.ascontiguousarray(m.beta),
+                     np.ascontiguousarray(m.rho), bases[ch].lambdas, m.n_layers))
+    return times, reqs
+
+
+def run_serving(M, ctx, prec, times, reqs, c, warm_s: float):
+    """Replay the trace against the serving loop: a submitter thread at the
+    arrival times, a collector waiting on tickets in order.  Latency = the
+    library's completion timestamp - the scheduled arrival (CLOCK_MONOTONIC)."""
+    import threading
+    n = len(times)
+    tickets = [None] * n
+    sched = [0] * n
+    ready = threading.Semaphore(0)
+    M.masw_server_start(ctx)
+    t0 = time.monotonic_ns() + 50_000_000
+
+    def submitter():
+        for i in range(n):
+            at = t0 + int(times[i] * 1e9)
+            dt = (at - time.monotonic_ns()) / 1e9
+            if dt > 0:
+                time.sleep(dt)
+            h, a, b, r, lam, _ = reqs[i]
+            sched[i] = at
+            tickets[i] = M.masw_submit(ctx, c, lam, h, a, b, r, prec)
+            ready.release()
+
+    results = [None] * n
+    th = threading.Thread(target=submitter)
+    th.start()
+    for i in range(n):
+        ready.acquire()
+        W = len(reqs[i][4])
+        out = (np.empty(W), np.empty(W, np.int32), np.empty(W, np.int32), np.empty(W))
+        info = M.masw_wait(ctx, tickets[i], -1, *out)
+        results[i] = (info, out[1])
+    th.join()
+    stats = M.masw_server_get_stats(ctx)
+    M.masw_server_stop(ctx)
+    meas = [i for i in range(n) if times[i] >= warm_s]
+    lat = np.array([(results[i][0]["done_ns"] - sched[i]) / 1e6 for i in meas])
+    t_first = min(sched[i] for i in meas)
+    t_last = max(results[i][0]["done_ns"] for i in meas)
+    span = (t_last - t_first) / 1e9
+    useful = sum(int(np.where(results[i][1] >= 0, results[i][1] + 1, c.shape[0]).sum()) for i in meas)
+    return {"requests": len(meas), "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat.mean()), "max_ms": float(lat.max()), "curves_per_s": len(meas) / span,
+            "det_evals_per_s": useful / span, "useful_evals": useful, "span_s": span,
+            "ticks": stats["ticks"], "max_resident": stats["max_resident"], "admit_waits": stats["admit_waits"],
+            "busy_frac": stats["busy_ms"] / (span * 1e3)}, [r[1] for r in results]
+
+
+def serving_bench(M, torch, a):
+    import workloads as WL
+    c = WL.serving_grid()
+    warm = 1.0
+    times, reqs = serving_trace(2000.0, warm, a.serve_seconds)
+    log(f"serving trace: {len(times)} requests over {warm + a.serve_seconds:.0f} s")
+    ctx_obj = M.Context(0, 4 << 30)
+    split, idx_s = run_serving(M, ctx_obj.ctx, M.MASW_PREC_SPLIT, times, reqs, c, warm)
+    log(f"split: {split}")
+    fp64, idx_d = run_serving(M, ctx_obj.ctx, M.MASW_PREC_FP64, times, reqs, c, warm)
+    log(f"fp64: {fp64}")
+    mism = sum(int(np.sum(x != y)) for x, y in zip(idx_s, idx_d))
+    ctx_obj.close()
+    n_lam = int(np.mean([len(r[4]) for r in reqs]))
+    res = {
+        "metric": METRIC, "value": split["det_evals_per_s"], "unit": "det evals/s", "n_gpus": 1,
+        "steps": split["requests"], "warmup": int(np.sum(times < warm)), "ms_per_step": split["mean_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 sweep + f64 re-check/refine", "data": "synthetic",
+        "config": {"workload": "serving_64chains_2000rps", "arrival_rate": 2000, "seconds": a.serve_seconds,
+                   "n_c": int(c.shape[0]), "wavelengths_mean": n_lam},
+        "p50_ms": split["p50_ms"], "p99_ms": split["p99_ms"], "curves_per_s": split["curves_per_s"],
+        "split": split, "fp64": fp64, "idx_mismatch_split_vs_fp64": mism,
+    }
+    print(json.dumps(res), flush=True)
+
+
 # ------------------------------------------------------------- cpu baseline --
 def _oracle_point(args):
     import oracle as O
@@ -173,7 +268,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="fine_scale", choices=["fine_scale", "two_layer", "batch"])
+    ap.add_argument("--workload", default="fine_scale", choices=["fine_scale", "two_layer", "batch", "serving"])
+    ap.add_argument("--serve-seconds", type=float, default=10.0, help="measured seconds of the serving trace")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target CPU work of the oracle sample")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -200,6 +296,9 @@ def main():
         print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "copies": 3}), flush=True)
         return
     M.library()
+    if a.workload == "serving":
+        serving_bench(M, torch, a)
+        return
     dev = torch.device("cuda:0")
     wl = make_workload(a.workload)
     log(f"workload {wl.name}: {len(wl.models)} model(s), {wl.n_lambda_total} wavelengths, {wl.c_test.shape[0]} c")

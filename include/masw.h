@@ -179,6 +179,77 @@ int masw_sign_map(masw_ctx *ctx, const double *c_test, int32_t n_c,
                   uint32_t flags, void *stream,
                   int8_t *sigma, double *log_abs_det);
 
+/* ------------------------------------------------------------- serving -- */
+/* A serving loop takes requests (one model each, as masw_dispersion_curve)
+ * as they arrive and batches them continuously: a driver thread admits
+ * queued requests while a slot is free and their device memory fits the
+ * serving pool (HBM-budget admission), and every tick replays one captured
+ * hipGraph that advances every unfinished wavelength of every resident
+ * request by a bounded number of sweep rounds, keeping each wavelength's
+ * search state in HBM between ticks.  A request admitted while others are
+ * in flight joins the next tick; its results are the same as from
+ * masw_dispersion_curve, bit for bit.  Inputs are host pointers, copied at
+ * submit; results are delivered by masw_poll / masw_wait. */
+typedef struct {
+    int32_t max_layers;      /* per request, <= MASW_MAX_LAYERS (0 = 64)          */
+    int32_t max_lambda;      /* wavelengths per request (0 = 512)                 */
+    int32_t max_grid;        /* c values per request (0 = 32768)                  */
+    int32_t rounds_per_tick; /* sweep rounds per wavelength per tick (0 = 16)     */
+    size_t pool_bytes;       /* device memory for resident requests, taken from
+                                the context's budget (0 = half of it)            */
+} masw_server_opts;
+
+/* Timing of one request (CLOCK_MONOTONIC ns) and the ticks it took part in. */
+typedef struct {
+    uint64_t submit_ns;
+    uint64_t admit_ns;
+    uint64_t done_ns;
+    uint32_t ticks;
+    uint32_t reserved;
+} masw_request_info;
+
+typedef struct {
+    uint64_t ticks;           /* graph replays                                  */
+    uint64_t submitted;
+    uint64_t completed;
+    uint64_t admit_waits;     /* ticks in which a queued request did not fit    */
+    uint32_t max_resident;    /* most requests resident at once                 */
+    uint32_t resident;        /* requests resident now                          */
+    uint64_t pool_bytes;
+    double busy_ms;           /* host time spent in ticks (launch to completion) */
+} masw_server_stats;
+
+/* Start the serving loop on ctx (opts may be NULL).  MASW_EBUSY if it is
+ * already running, MASW_ENOMEM if the pool does not fit the budget.  While
+ * it runs, synchronous calls on ctx use the rest of the budget. */
+int masw_server_start(masw_ctx *ctx, const masw_server_opts *opts);
+
+/* Finish every submitted request, then stop the loop and release the pool.
+ * Results not yet collected are discarded. */
+int masw_server_stop(masw_ctx *ctx);
+
+/* Queue one request.  Arguments as masw_dispersion_curve with host pointers;
+ * they are checked and copied before the call returns.  MASW_EINVAL on a bad
+ * argument or one above the server's limits, MASW_ENOMEM if the request could
+ * never fit the pool, MASW_EBUSY if the loop is not running.  *ticket
+ * identifies the request. */
+int masw_submit(masw_ctx *ctx, const double *c_test, int32_t n_c, const double *lambda,
+                int32_t n_lambda, const masw_model *model, masw_precision prec,
+                uint64_t *ticket);
+
+/* If the request is finished, copy its results (arrays of its n_lambda;
+ * c_ref and info may be NULL) and forget the ticket: MASW_OK.  MASW_EBUSY if
+ * it is not finished, MASW_ENOENT if the ticket is unknown or was collected. */
+int masw_poll(masw_ctx *ctx, uint64_t ticket, double *C_t, int32_t *idx, int32_t *status,
+              double *c_ref, masw_request_info *info);
+
+/* As masw_poll, waiting up to timeout_us microseconds (< 0: no limit);
+ * MASW_ETIMEOUT if the request is still not finished. */
+int masw_wait(masw_ctx *ctx, uint64_t ticket, int64_t timeout_us, double *C_t, int32_t *idx,
+              int32_t *status, double *c_ref, masw_request_info *info);
+
+int masw_server_get_stats(masw_ctx *ctx, masw_server_stats *out);
+
 /* Counters of the last completed call on ctx (for MASW_DEVICE_PTRS calls,
  * after the stream has been synchronised; this function synchronises). */
 int masw_get_stats(masw_ctx *ctx, masw_stats *out);

@@ -76,6 +76,28 @@ class masw_stats(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class masw_server_opts(ctypes.Structure):
+    _fields_ = [("max_layers", ctypes.c_int32), ("max_lambda", ctypes.c_int32), ("max_grid", ctypes.c_int32),
+                ("rounds_per_tick", ctypes.c_int32), ("pool_bytes", ctypes.c_size_t)]
+
+
+class masw_request_info(ctypes.Structure):
+    _fields_ = [("submit_ns", ctypes.c_uint64), ("admit_ns", ctypes.c_uint64), ("done_ns", ctypes.c_uint64),
+                ("ticks", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+class masw_server_stats(ctypes.Structure):
+    _fields_ = [("ticks", ctypes.c_uint64), ("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("admit_waits", ctypes.c_uint64), ("max_resident", ctypes.c_uint32), ("resident", ctypes.c_uint32),
+                ("pool_bytes", ctypes.c_uint64), ("busy_ms", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 # ------------------------------------------------------------------ loading --
 _lib = None
 
@@ -99,6 +121,14 @@ def library() -> ctypes.CDLL:
             "masw_sign_map": (ctypes.c_int, [vp, vp, i32, vp, i32, ctypes.POINTER(masw_model),
                                              ctypes.c_int, u32, vp, vp, vp]),
             "masw_get_stats": (ctypes.c_int, [vp, ctypes.POINTER(masw_stats)]),
+            "masw_server_start": (ctypes.c_int, [vp, ctypes.POINTER(masw_server_opts)]),
+            "masw_server_stop": (ctypes.c_int, [vp]),
+            "masw_submit": (ctypes.c_int, [vp, vp, i32, vp, i32, ctypes.POINTER(masw_model), ctypes.c_int,
+                                           ctypes.POINTER(ctypes.c_uint64)]),
+            "masw_poll": (ctypes.c_int, [vp, ctypes.c_uint64, vp, vp, vp, vp, ctypes.POINTER(masw_request_info)]),
+            "masw_wait": (ctypes.c_int, [vp, ctypes.c_uint64, ctypes.c_int64, vp, vp, vp, vp,
+                                         ctypes.POINTER(masw_request_info)]),
+            "masw_server_get_stats": (ctypes.c_int, [vp, ctypes.POINTER(masw_server_stats)]),
             "masw_strerror": (ctypes.c_char_p, [ctypes.c_int]),
             "masw_last_error": (ctypes.c_char_p, []),
             "masw_version": (ctypes.c_char_p, []),
@@ -235,6 +265,50 @@ def masw_sign_map(ctx, c_test, lam, h, alpha, beta, rho, prec: int, flags: int, 
 def masw_get_stats(ctx) -> dict:
     s = masw_stats()
     _check(library().masw_get_stats(ctx, ctypes.byref(s)), "masw_get_stats")
+    return s.as_dict()
+
+
+def masw_server_start(ctx, max_layers=0, max_lambda=0, max_grid=0, rounds_per_tick=0, pool_bytes=0) -> int:
+    o = masw_server_opts(max_layers, max_lambda, max_grid, rounds_per_tick, pool_bytes)
+    return _check(library().masw_server_start(ctx, ctypes.byref(o)), "masw_server_start")
+
+
+def masw_server_stop(ctx) -> int:
+    return _check(library().masw_server_stop(ctx), "masw_server_stop")
+
+
+def masw_submit(ctx, c_test, lam, h, alpha, beta, rho, prec: int) -> int:
+    """Host numpy arrays only (copied before returning); returns the ticket."""
+    m = _model_struct(h, alpha, beta, rho)
+    t = ctypes.c_uint64()
+    _check(library().masw_submit(ctx, _ptr(c_test, np.float64), int(c_test.shape[0]), _ptr(lam, np.float64),
+                                 int(lam.shape[0]), ctypes.byref(m), prec, ctypes.byref(t)), "masw_submit")
+    return t.value
+
+
+def _collect(fn, ctx, ticket, extra, C_t, idx, status, c_ref):
+    info = masw_request_info()
+    rc = fn(ctx, ctypes.c_uint64(ticket), *extra, _ptr(C_t, np.float64), _ptr(idx, np.int32),
+            _ptr(status, np.int32), _ptr(c_ref, np.float64), ctypes.byref(info))
+    if rc == MASW_EBUSY:
+        return None
+    _check(rc, fn.__name__)
+    return info.as_dict()
+
+
+def masw_poll(ctx, ticket, C_t, idx, status, c_ref=None):
+    """Results into the given host arrays and the request's timing dict, or
+    None while the request is unfinished."""
+    return _collect(library().masw_poll, ctx, ticket, (), C_t, idx, status, c_ref)
+
+
+def masw_wait(ctx, ticket, timeout_us, C_t, idx, status, c_ref=None):
+    return _collect(library().masw_wait, ctx, ticket, (ctypes.c_int64(int(timeout_us)),), C_t, idx, status, c_ref)
+
+
+def masw_server_get_stats(ctx) -> dict:
+    s = masw_server_stats()
+    _check(library().masw_server_get_stats(ctx, ctypes.byref(s)), "masw_server_get_stats")
     return s.as_dict()
 
 

@@ -15,8 +15,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libmasw.so")
 
-SOURCES = ["masw_kernels.hip", "masw_runtime.hip"]
-HEADERS = ["masw_internal.hpp", "masw_math.hpp"]
+SOURCES = ["masw_kernels.hip", "masw_runtime.hip", "masw_server.hip"]
+HEADERS = ["masw_internal.hpp", "masw_math.hpp", "masw_special.hpp", "masw_host.hpp"]
 
 # Packed FP32 instructions stay disabled; the compiler would otherwise form
 # v_pk_* from ordinary float code.

@@ -1,0 +1,59 @@
+// Host-side declarations shared by the runtime (masw_runtime.hip) and the
+// serving loop (masw_server.hip): the context, error reporting, and the
+// kernel launchers defined next to the kernels (masw_kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <mutex>
+#include <string>
+
+#include "masw.h"
+#include "masw_internal.hpp"
+
+namespace masw {
+int sweep_blocks_per_cu(int mode, int G);
+int tick_blocks_per_cu(int G);
+hipError_t launch_sweep(int mode, int G, int blocks, hipStream_t s, const SweepArgs& a);
+hipError_t launch_prep(const PrepArgs& a, int single_N, int single_W, hipStream_t s);
+hipError_t launch_sign_map(bool fp32, const SignMapArgs& a, hipStream_t s);
+hipError_t launch_admit(const AdmitList* list_dev, int n, int32_t* slot_remaining, hipStream_t s);
+hipError_t launch_tick(int G, int blocks, hipStream_t s, const TickArgs& a);
+
+// Records `msg` as the calling thread's last error and returns `code`.
+int fail(int code, const std::string& msg);
+
+// Host-side argument checks (host pointers); MASW_OK or MASW_EINVAL via fail().
+int check_model_values(int32_t N, const double* h, const double* alpha, const double* beta,
+                       const double* rho, const char* what);
+int check_grid(const double* c, int32_t n_c, bool values);
+int check_lambda(const double* lam, int32_t n, bool values);
+
+struct Server;  // masw_server.hip
+void server_destroy(Server* s);
+}  // namespace masw
+
+#define MASW_HIP(call)                                                                     \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return ::masw::fail(MASW_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct masw_ctx {
+  int device = -1;
+  hipStream_t stream = nullptr;   // the context's own stream (default priority)
+  hipStream_t last_stream = nullptr;
+  char* arena = nullptr;
+  size_t arena_size = 0;          // whole HBM budget
+  size_t sync_size = 0;           // front part used by the synchronous calls
+  int cus = 0;
+  int blocks_per_cu[2][5] = {};   // [mode][log2 G], G = 1..16
+  int forced_waves = 0;           // MASW_WAVES_PER_ITEM override (tuning)
+  std::mutex mu;
+  masw_stats last = {};
+  bool stats_pending = false;
+  masw::Counters* counters = nullptr;  // arena offset 0
+  hipEvent_t ev[3] = {};          // start, sweep start, sweep end
+  masw::Server* server = nullptr; // serving loop, if started
+};

@@ -104,6 +104,65 @@ struct PrepArgs {
   Counters* counters;
 };
 
+// Where one item's search stands.  The batch kernels keep it in registers;
+// the serving tick kernel keeps it in HBM between ticks.
+struct ItemState {
+  int32_t start;  // first grid position of the next sweep round
+  int32_t carry;  // sign at start - 1 (kNoSign before the first round)
+  int32_t done;   // 1 once the outputs are written
+  int32_t pad;
+};
+
+// ------------------------------------------------------------- serving --
+constexpr int kMaxSlots = 256;     // requests resident on the device at once
+constexpr int kMaxAdmit = 64;      // requests admitted per tick
+
+// One resident request (slot).  Pointers address the request's own region of
+// the serving pool; outputs go to pinned host memory at out_base.
+struct alignas(64) SlotDesc {
+  const double* raw;        // staged inputs: h[N], alpha, beta, rho[N+1], lambda[W], c[n_c]
+  LayerRec64* L64;          // [N+1]
+  LayerRec32* L32;          // [N+1]
+  float* c32;               // [n_c]
+  double* lam_k;            // [W]
+  ItemState* state;         // [W]
+  int32_t N, W, n_c, prec;  // prec: MASW_PREC_*
+  int32_t out_base;         // first output index (slot * w_max)
+  int32_t pad[3];
+};
+
+// Per-tick descriptor, written by the host into pinned memory and copied to
+// the device by the captured graph.
+struct TickDesc {
+  int32_t n_active;              // active slots in this tick
+  int32_t n_units;               // sum of their W
+  int32_t budget;                // sweep rounds per item per tick
+  int32_t pad;
+  int32_t active[kMaxSlots];     // slot ids
+  int32_t prefix[kMaxSlots + 1]; // prefix sums of W over `active`
+  int32_t pad2[3];
+  SlotDesc slot[kMaxSlots];
+};
+
+struct AdmitList {
+  int32_t n;
+  int32_t slot[kMaxAdmit];
+  SlotDesc desc[kMaxAdmit];
+};
+
+struct TickArgs {
+  const TickDesc* desc;      // device copy
+  int32_t* slot_remaining;   // [kMaxSlots] items not finished
+  Counters* counters;
+  int32_t refine;
+  // outputs in pinned host memory (device-accessible)
+  double* out_ct;
+  int32_t* out_idx;
+  int32_t* out_status;
+  double* out_cref;
+  int32_t* host_done;        // [kMaxSlots] set to 1 when a slot's last item finishes
+};
+
 struct SignMapArgs {
   const ModelDesc* models;
   const LayerRec64* layers64;

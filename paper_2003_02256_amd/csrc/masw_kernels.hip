@@ -249,170 +249,364 @@ __global__ void order_scatter_kernel(PrepArgs a) {
 // --------------------------------------------------------------- sweep --
 enum { kModeFP64 = 0, kModeSplit = 1 };
 
+template <int G>
+struct SweepShared {
+  int item;
+  int last[G];
+  int first[G];
+  int pair[2];
+  int check[4];
+};
+
+struct WorkCount {
+  unsigned long long sweep = 0, check = 0, refine = 0, useful = 0;
+};
+
+// Everything uniform about one item.
+struct ItemRef {
+  int N, n_c;
+  double k64;
+  const double* c64;
+  const float* c32;
+  const LayerRec64* L64;
+  const LayerRec32* L32;
+};
+
+// Output slots of one item.
+struct ItemOut {
+  double* ct;
+  int32_t* idx;
+  int32_t* status;
+  double* cref;  // may be null
+  int refine;
+};
+
+template <int G>
+__device__ __forceinline__ void write_missing(const ItemOut& o, int status) {
+  if (threadIdx.x == 0) {
+    *o.idx = -1;
+    *o.status = status;
+    *o.ct = __builtin_nan("");
+    if (o.cref) *o.cref = __builtin_nan("");
+  }
+}
+
+// Advance one item by at most `budget` sweep rounds of G*64 positions.  When
+// the first sign change is known (after the FP64 re-check for the split
+// path), refine it in FP64 and write the outputs through wavefront 0, then
+// return true.  If the budget runs out first, save where the sweep stands
+// in `st` and return false; resuming from `st` gives the same result as an
+// uninterrupted run, whatever G the resumed call uses.
 template <int MODE, int G>
-__global__ __launch_bounds__(64 * G) void sweep_kernel(SweepArgs a) {
-  constexpr int P = 64 * G;  // positions per round
-  __shared__ int s_item;
-  __shared__ int s_last[G];
-  __shared__ int s_first[G];
-  __shared__ int s_pair[2];
-  __shared__ int s_check[4];
+__device__ bool run_item(const ItemRef& r, ItemState& st, int budget, SweepShared<G>& sh, WorkCount& wc,
+                         const ItemOut& o) {
+  constexpr int P = 64 * G;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  unsigned long long n_sweep = 0, n_check = 0, n_refine = 0, n_useful = 0;
+  const int n_c = r.n_c;
+  int found = -1, sig_f = 0, prev_f = 0;
+  int start = st.start, carry = st.carry, rounds = 0;
+  if (MODE == kModeFP64) {
+    for (int base = start; base < n_c; base += P) {
+      if (rounds == budget) {
+        st.start = base;
+        st.carry = carry;
+        return false;
+      }
+      ++rounds;
+      const int i = base + tid;
+      const int sg = (i < n_c) ? det_sign<double, false>(r.c64[i], r.k64, r.L64, r.N, nullptr) : kNoSign;
+      const int f = round_first_change<G>(sg, carry, sh.last, sh.first, sh.pair, &carry, &sig_f, &prev_f);
+      wc.sweep += (unsigned long long)min(P, n_c - base);
+      if (f >= 0) {
+        found = base + f;
+        break;
+      }
+    }
+  } else {
+    const float k32 = float(r.k64);
+    while (start < n_c && found < 0) {
+      // FP32 sweep from `start` for a candidate change.
+      int cand = -1;
+      for (int base = start; base < n_c; base += P) {
+        if (rounds == budget) {
+          st.start = base;
+          st.carry = carry;
+          return false;
+        }
+        ++rounds;
+        const int i = base + tid;
+        const int sg = (i < n_c) ? det_sign<float, false>(r.c32[i], k32, r.L32, r.N, nullptr) : kNoSign;
+        int s_c, p_c;
+        const int f = round_first_change<G>(sg, carry, sh.last, sh.first, sh.pair, &carry, &s_c, &p_c);
+        wc.sweep += (unsigned long long)min(P, n_c - base);
+        if (f >= 0) {
+          cand = base + f;
+          break;
+        }
+      }
+      if (cand < 0) break;
+      // FP64 re-check of the 64 positions ws-1 .. ws+62 around the
+      // candidate (48 before it, 15 after), one per lane of wavefront 0;
+      // the other wavefronts wait.  The window does not depend on the
+      // group size, so neither does the outcome.
+      const int ws = max(1, cand - 48);
+      if (wave == 0) {
+        const int i = ws - 1 + lane;
+        const int sg = (i < n_c) ? det_sign<double, false>(r.c64[i], r.k64, r.L64, r.N, nullptr) : kNoSign;
+        int last, s_c = 0, p_c = 0;
+        const int f = wave_first_change(sg, &s_c, &p_c, &last);
+        if (lane == 0) {
+          sh.check[0] = f;
+          sh.check[1] = last;
+          sh.check[2] = s_c;
+          sh.check[3] = p_c;
+        }
+      }
+      __syncthreads();
+      const int f = sh.check[0];
+      const int last = sh.check[1];
+      sig_f = sh.check[2];
+      prev_f = sh.check[3];
+      __syncthreads();
+      wc.check += (unsigned long long)min(64, n_c - (ws - 1));
+      if (f >= 0) {
+        found = ws - 1 + f;
+      } else {
+        // Rejected: resume the FP32 sweep after the checked window,
+        // carrying the FP64 sign of its last position.
+        start = ws + 63;
+        carry = last;
+      }
+    }
+  }
+  st.done = 1;
 
+  if (found < 0) {
+    write_missing<G>(o, MASW_STATUS_NOT_FOUND);
+    wc.useful += (unsigned long long)n_c;
+    return true;
+  }
+  wc.useful += (unsigned long long)(found + 1);
+
+  // Refinement and output by wavefront 0 alone; the others go on to the
+  // next barrier.  One wavefront at a time on a SIMD finishes these few
+  // rounds sooner than the whole group sharing the SIMDs would.
+  if (wave == 0) {
+    int status = MASW_STATUS_FOUND;
+    if (sig_f == kNaNSign || prev_f == kNaNSign) status = MASW_STATUS_NAN;
+    double c_ref = __builtin_nan("");
+    if (status == MASW_STATUS_FOUND) {
+      // FP64 multisection of [c[found-1], c[found]]: 64 points per round,
+      // both ends included, one per lane; the new bracket is the first sign
+      // change.  The first round also yields the layer-denominator sign
+      // masks at the two grid points (pole flag).
+      double lo = r.c64[found - 1], hi = r.c64[found];
+      const double tol = kRefineRel * hi;
+      for (int k = 0; k < 24; ++k) {
+        const double w = hi - lo;
+        const double c = (lane == 63) ? hi : lo + w * (double(lane) / 63.0);
+        uint64_t dm = 0;
+        const int sg = det_sign<double, true>(c, r.k64, r.L64, r.N, &dm);
+        if (k == 0 && __shfl(dm, 0, 64) != __shfl(dm, 63, 64)) status |= MASW_FLAG_POLE;
+        int s_c = 0, p_c = 0, unused;
+        const int f = wave_first_change(sg, &s_c, &p_c, &unused);
+        wc.refine += 64ull;
+        if (f < 0 || s_c == kNaNSign || p_c == kNaNSign) break;
+        const double nhi = (f == 63) ? hi : lo + w * (double(f) / 63.0);
+        const double nlo = lo + w * (double(f - 1) / 63.0);
+        lo = nlo;
+        hi = nhi;
+        if (!o.refine || hi - lo <= tol) break;
+      }
+      if (o.refine) c_ref = 0.5 * (lo + hi);
+    }
+    if (tid == 0) {
+      *o.idx = found;
+      *o.status = status;
+      *o.ct = r.c64[found];
+      if (o.cref) *o.cref = c_ref;
+    }
+  }
+  return true;
+}
+
+template <int G>
+__device__ __forceinline__ void flush_counts(Counters* c, const WorkCount& wc) {
+  if (threadIdx.x == 0) {
+    atomicAdd(&c->sweep, wc.sweep);
+    atomicAdd(&c->check, wc.check);
+    atomicAdd(&c->refine, wc.refine);
+    atomicAdd(&c->useful, wc.useful);
+  }
+}
+
+// Batch launch: a persistent grid pulls items from the ordered queue and runs
+// each to completion.
+template <int MODE, int G>
+__global__ __launch_bounds__(64 * G) void sweep_kernel(SweepArgs a) {
+  __shared__ SweepShared<G> sh;
+  WorkCount wc;
   for (;;) {
-    if (tid == 0) s_item = (int)atomicAdd(&a.counters->queue_head, 1u);
+    if (threadIdx.x == 0) sh.item = (int)atomicAdd(&a.counters->queue_head, 1u);
     __syncthreads();
-    const int it = uniform(s_item);
+    const int it = uniform(sh.item);
     __syncthreads();
     if (it >= a.n_items) break;
 
     const int g = uniform(a.order[it]);
     const int m = uniform(a.lam_model[g]);
     const ModelDesc d = a.models[m];
-    const int N = uniform(d.n_layers);
-    const int n_c = uniform(d.n_c);
-    const double k64 = a.lam_k[g];
-    const double* __restrict__ c64 = a.c64 + uniform(d.c_base);
-    const float* __restrict__ c32 = a.c32 + uniform(d.c_base);
-    const LayerRec64* __restrict__ L64 = a.layers64 + uniform(d.layer_base);
-    const LayerRec32* __restrict__ L32 = a.layers32 + uniform(d.layer_base);
-
-    if (!(k64 == k64)) {  // invalid model, grid or wavelength
-      if (tid == 0) {
-        a.out_idx[g] = -1;
-        a.out_status[g] = MASW_STATUS_INVALID;
-        a.out_ct[g] = __builtin_nan("");
-        if (a.out_cref) a.out_cref[g] = __builtin_nan("");
-      }
+    ItemRef r;
+    r.N = uniform(d.n_layers);
+    r.n_c = uniform(d.n_c);
+    r.k64 = a.lam_k[g];
+    r.c64 = a.c64 + uniform(d.c_base);
+    r.c32 = a.c32 + uniform(d.c_base);
+    r.L64 = a.layers64 + uniform(d.layer_base);
+    r.L32 = a.layers32 + uniform(d.layer_base);
+    const ItemOut o{a.out_ct + g, a.out_idx + g, a.out_status + g, a.out_cref ? a.out_cref + g : nullptr,
+                    a.refine};
+    if (!(r.k64 == r.k64)) {  // invalid model, grid or wavelength
+      write_missing<G>(o, MASW_STATUS_INVALID);
       continue;
     }
+    ItemState st{0, kNoSign, 0, 0};
+    run_item<MODE, G>(r, st, 0x7fffffff, sh, wc, o);
+  }
+  flush_counts<G>(a.counters, wc);
+}
 
-    int found = -1, sig_f = 0, prev_f = 0, carry = kNoSign;
-    if (MODE == kModeFP64) {
-      for (int base = 0; base < n_c; base += P) {
-        const int i = base + tid;
-        const int sg = (i < n_c) ? det_sign<double, false>(c64[i], k64, L64, N, nullptr) : kNoSign;
-        const int f = round_first_change<G>(sg, carry, s_last, s_first, s_pair, &carry, &sig_f, &prev_f);
-        n_sweep += (unsigned long long)min(P, n_c - base);
-        if (f >= 0) {
-          found = base + f;
-          break;
-        }
-      }
+// ------------------------------------------------------------- serving --
+// Precompute of newly admitted requests: one workgroup per request validates
+// the model and grid, writes the layer records, k per wavelength and the FP32
+// grid, and resets the item states.
+__global__ __launch_bounds__(256) void admit_kernel(const AdmitList* __restrict__ list,
+                                                    int32_t* slot_remaining) {
+  __shared__ int s_bad;
+  __shared__ double s_mu_ref;
+  const int b = blockIdx.x;
+  if (b >= list->n) return;
+  const SlotDesc d = list->desc[b];
+  const int N = d.N, W = d.W, n_c = d.n_c;
+  const double* h = d.raw;
+  const double* alpha = h + N;
+  const double* beta = alpha + (N + 1);
+  const double* rho = beta + (N + 1);
+  const double* lam = rho + (N + 1);
+  const double* c = lam + W;
+  if (threadIdx.x == 0) {
+    s_bad = (N < 0 || N > MASW_MAX_LAYERS) ? 1 : 0;
+    s_mu_ref = rho[N] * beta[N] * beta[N];
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j <= N; j += blockDim.x) {
+    const double al = alpha[j], be = beta[j], rh = rho[j];
+    bool ok = (al < __builtin_inf()) && (rh < __builtin_inf()) && (be > 0.0) && (al > be) && (rh > 0.0);
+    if (j < N) ok = ok && (h[j] > 0.0) && (h[j] < __builtin_inf());
+    if (!ok) atomicOr(&s_bad, 1);
+  }
+  for (int i = threadIdx.x; i < n_c; i += blockDim.x) {
+    const double ci = c[i];
+    bool ok = (ci > 0.0) && (ci < __builtin_inf());
+    if (i + 1 < n_c) ok = ok && (ci < c[i + 1]);
+    if (!ok) atomicOr(&s_bad, 1);
+    d.c32[i] = float(ci);
+  }
+  __syncthreads();
+  const bool valid = (s_bad == 0);
+  const double mu_ref = s_mu_ref;
+  if (valid) {
+    for (int j = threadIdx.x; j <= N; j += blockDim.x) {
+      const double al = alpha[j], be = beta[j], rh = rho[j];
+      LayerRec64 r;
+      r.ia2 = 1.0 / (al * al);
+      r.ib2 = 1.0 / (be * be);
+      r.rh = rh / mu_ref;
+      r.mh = rh * be * be / mu_ref;
+      r.h = (j < N) ? h[j] : 0.0;
+      r.aux = (j == N) ? mu_ref : 0.0;
+      r.pad1 = r.pad2 = 0.0;
+      d.L64[j] = r;
+      LayerRec32 q;
+      q.ia2 = float(r.ia2);
+      q.ib2 = float(r.ib2);
+      q.rh = float(r.rh);
+      q.mh = float(r.mh);
+      q.h = float(r.h);
+      q.aux = float(mu_ref);
+      q.pad1 = q.pad2 = 0.0f;
+      d.L32[j] = q;
+    }
+  }
+  for (int w = threadIdx.x; w < W; w += blockDim.x) {
+    const double l = lam[w];
+    const bool ok = valid && (l > 0.0) && (l < __builtin_inf());
+    d.lam_k[w] = ok ? (2.0 * M_PI / l) : __builtin_nan("");
+    d.state[w] = ItemState{0, kNoSign, 0, 0};
+  }
+  if (threadIdx.x == 0) slot_remaining[list->slot[b]] = W;
+}
+
+// One serving tick: every unfinished item of every active request advances by
+// at most desc->budget sweep rounds (then its re-check and refinement if its
+// change was found).  The last item of a request to finish raises the
+// request's completion flag in pinned host memory.
+template <int G>
+__global__ __launch_bounds__(64 * G) void tick_kernel(TickArgs a) {
+  __shared__ SweepShared<G> sh;
+  WorkCount wc;
+  const TickDesc* __restrict__ D = a.desc;
+  const int n_units = D->n_units;
+  const int n_active = D->n_active;
+  const int budget = D->budget;
+  for (;;) {
+    if (threadIdx.x == 0) sh.item = (int)atomicAdd(&a.counters->queue_head, 1u);
+    __syncthreads();
+    const int u = uniform(sh.item);
+    __syncthreads();
+    if (u >= n_units) break;
+    int lo = 0, hi = n_active;  // last active slot with prefix <= u
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (D->prefix[mid] <= u) lo = mid; else hi = mid;
+    }
+    const int slot = uniform(D->active[lo]);
+    const int j = u - D->prefix[lo];
+    const SlotDesc& sd = D->slot[slot];
+    ItemState st = sd.state[j];
+    if (st.done) continue;
+    ItemRef r;
+    r.N = uniform(sd.N);
+    r.n_c = uniform(sd.n_c);
+    r.k64 = sd.lam_k[j];
+    r.c64 = sd.raw + (r.N + 3 * (r.N + 1) + sd.W);
+    r.c32 = sd.c32;
+    r.L64 = sd.L64;
+    r.L32 = sd.L32;
+    const int og = sd.out_base + j;
+    const ItemOut o{a.out_ct + og, a.out_idx + og, a.out_status + og, a.out_cref + og, a.refine};
+    bool done;
+    if (!(r.k64 == r.k64)) {
+      write_missing<G>(o, MASW_STATUS_INVALID);
+      st.done = 1;
+      done = true;
+    } else if (sd.prec == MASW_PREC_SPLIT) {
+      done = run_item<kModeSplit, G>(r, st, budget, sh, wc, o);
     } else {
-      const float k32 = float(k64);
-      int start = 0;
-      while (start < n_c && found < 0) {
-        // FP32 sweep from `start` for a candidate change.
-        int cand = -1;
-        for (int base = start; base < n_c; base += P) {
-          const int i = base + tid;
-          const int sg = (i < n_c) ? det_sign<float, false>(c32[i], k32, L32, N, nullptr) : kNoSign;
-          int s_c, p_c;
-          const int f = round_first_change<G>(sg, carry, s_last, s_first, s_pair, &carry, &s_c, &p_c);
-          n_sweep += (unsigned long long)min(P, n_c - base);
-          if (f >= 0) {
-            cand = base + f;
-            break;
-          }
-        }
-        if (cand < 0) break;
-        // FP64 re-check of the 64 positions ws-1 .. ws+62 around the
-        // candidate (48 before it, 15 after), one per lane of wavefront 0;
-        // the other wavefronts wait.  The window does not depend on the
-        // group size, so neither does the outcome.
-        const int ws = max(1, cand - 48);
-        if (wave == 0) {
-          const int i = ws - 1 + lane;
-          const int sg = (i < n_c) ? det_sign<double, false>(c64[i], k64, L64, N, nullptr) : kNoSign;
-          int last, s_c = 0, p_c = 0;
-          const int f = wave_first_change(sg, &s_c, &p_c, &last);
-          if (lane == 0) {
-            s_check[0] = f;
-            s_check[1] = last;
-            s_check[2] = s_c;
-            s_check[3] = p_c;
-          }
-        }
-        __syncthreads();
-        const int f = s_check[0];
-        const int last = s_check[1];
-        sig_f = s_check[2];
-        prev_f = s_check[3];
-        __syncthreads();
-        n_check += (unsigned long long)min(64, n_c - (ws - 1));
-        if (f >= 0) {
-          found = ws - 1 + f;
-        } else {
-          // Rejected: resume the FP32 sweep after the checked window,
-          // carrying the FP64 sign of its last position.
-          start = ws + 63;
-          carry = last;
-        }
+      done = run_item<kModeFP64, G>(r, st, budget, sh, wc, o);
+    }
+    if (threadIdx.x == 0) {
+      sd.state[j] = st;
+      if (done) {
+        __threadfence_system();
+        if (atomicSub(&a.slot_remaining[slot], 1) == 1) a.host_done[slot] = 1;
       }
     }
-
-    if (found < 0) {
-      if (tid == 0) {
-        a.out_idx[g] = -1;
-        a.out_status[g] = MASW_STATUS_NOT_FOUND;
-        a.out_ct[g] = __builtin_nan("");
-        if (a.out_cref) a.out_cref[g] = __builtin_nan("");
-      }
-      n_useful += (unsigned long long)n_c;
-      continue;
-    }
-    n_useful += (unsigned long long)(found + 1);
-
-    // Refinement and output by wavefront 0 alone; the others go on to the
-    // next item's queue barrier.  One wavefront at a time on a SIMD finishes
-    // these few rounds sooner than the whole group sharing the SIMDs would.
-    if (wave == 0) {
-      int status = MASW_STATUS_FOUND;
-      if (sig_f == kNaNSign || prev_f == kNaNSign) status = MASW_STATUS_NAN;
-      double c_ref = __builtin_nan("");
-      if (status == MASW_STATUS_FOUND) {
-        // FP64 multisection of [c[found-1], c[found]]: 64 points per round,
-        // both ends included, one per lane; the new bracket is the first
-        // sign change.  The first round also yields the layer-denominator
-        // sign masks at the two grid points (pole flag).
-        double lo = c64[found - 1], hi = c64[found];
-        const double tol = kRefineRel * hi;
-        for (int r = 0; r < 24; ++r) {
-          const double w = hi - lo;
-          const double c = (lane == 63) ? hi : lo + w * (double(lane) / 63.0);
-          uint64_t dm = 0;
-          const int sg = det_sign<double, true>(c, k64, L64, N, &dm);
-          if (r == 0 && __shfl(dm, 0, 64) != __shfl(dm, 63, 64)) status |= MASW_FLAG_POLE;
-          int s_c = 0, p_c = 0, unused;
-          const int f = wave_first_change(sg, &s_c, &p_c, &unused);
-          n_refine += 64ull;
-          if (f < 0 || s_c == kNaNSign || p_c == kNaNSign) break;
-          const double nhi = (f == 63) ? hi : lo + w * (double(f) / 63.0);
-          const double nlo = lo + w * (double(f - 1) / 63.0);
-          lo = nlo;
-          hi = nhi;
-          if (!a.refine || hi - lo <= tol) break;
-        }
-        if (a.refine) c_ref = 0.5 * (lo + hi);
-      }
-      if (tid == 0) {
-        a.out_idx[g] = found;
-        a.out_status[g] = status;
-        a.out_ct[g] = c64[found];
-        if (a.out_cref) a.out_cref[g] = c_ref;
-      }
-    }
+    __syncthreads();  // wavefront 0's outputs are written before the next item is fetched
   }
-  if (tid == 0) {
-    atomicAdd(&a.counters->sweep, n_sweep);
-    atomicAdd(&a.counters->check, n_check);
-    atomicAdd(&a.counters->refine, n_refine);
-    atomicAdd(&a.counters->useful, n_useful);
-  }
+  flush_counts<G>(a.counters, wc);
 }
 
 // ------------------------------------------------------------ sign map --
@@ -502,6 +696,39 @@ hipError_t launch_prep(const PrepArgs& a, int single_N, int single_W, hipStream_
     hipLaunchKernelGGL(order_scatter_kernel, dim3(nb), dim3(256), 0, s, a);
   }
   return hipGetLastError();
+}
+
+static const void* tick_symbol(int G) {
+  switch (G) {
+    case 1: return reinterpret_cast<const void*>(&tick_kernel<1>);
+    case 2: return reinterpret_cast<const void*>(&tick_kernel<2>);
+    case 4: return reinterpret_cast<const void*>(&tick_kernel<4>);
+    case 8: return reinterpret_cast<const void*>(&tick_kernel<8>);
+  }
+  return nullptr;
+}
+
+int tick_blocks_per_cu(int G) {
+  const void* f = tick_symbol(G);
+  int n = 0;
+  if (!f || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 64 * G, 0) != hipSuccess) return 0;
+  return n;
+}
+
+hipError_t launch_admit(const AdmitList* list_dev, int n, int32_t* slot_remaining, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(admit_kernel, dim3(n), dim3(256), 0, s, list_dev, slot_remaining);
+  return hipGetLastError();
+}
+
+// Clears the tick's queue head and counters (a kernel, not a memset, so that
+// the graph holding it replays correctly).
+hipError_t launch_tick(int G, int blocks, hipStream_t s, const TickArgs& a) {
+  hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(256), 0, s, a.counters);
+  const void* f = tick_symbol(G);
+  if (!f) return hipErrorInvalidValue;
+  void* args[] = {const_cast<TickArgs*>(&a)};
+  return hipLaunchKernel(f, dim3(blocks), dim3(64 * G), args, 0, s);
 }
 
 hipError_t launch_sign_map(bool fp32, const SignMapArgs& a, hipStream_t s) {

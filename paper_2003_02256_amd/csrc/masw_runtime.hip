@@ -17,48 +17,59 @@
 #include <vector>
 
 #include "masw.h"
+#include "masw_host.hpp"
 #include "masw_internal.hpp"
-
-namespace masw {
-int sweep_blocks_per_cu(int mode, int G);
-hipError_t launch_sweep(int mode, int G, int blocks, hipStream_t s, const SweepArgs& a);
-hipError_t launch_prep(const PrepArgs& a, int single_N, int single_W, hipStream_t s);
-hipError_t launch_sign_map(bool fp32, const SignMapArgs& a, hipStream_t s);
-}  // namespace masw
 
 using namespace masw;
 
 // ------------------------------------------------------------ errors --
 static thread_local std::string g_last_error;
 
-static int fail(int code, const std::string& msg) {
+int masw::fail(int code, const std::string& msg) {
   g_last_error = msg;
   return code;
 }
 
-#define MASW_HIP(call)                                                              \
-  do {                                                                              \
-    hipError_t e_ = (call);                                                         \
-    if (e_ != hipSuccess)                                                           \
-      return fail(MASW_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
-  } while (0)
+// ------------------------------------------------------- validation --
+static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
-// ----------------------------------------------------------- context --
-struct masw_ctx {
-  int device = -1;
-  hipStream_t stream = nullptr;   // the context's own stream (default priority)
-  hipStream_t last_stream = nullptr;
-  char* arena = nullptr;
-  size_t arena_size = 0;
-  int cus = 0;
-  int blocks_per_cu[2][5] = {};   // [mode][log2 G], G = 1..16
-  int forced_waves = 0;           // MASW_WAVES_PER_ITEM override (tuning)
-  std::mutex mu;
-  masw_stats last = {};
-  bool stats_pending = false;
-  Counters* counters = nullptr;   // arena offset 0
-  hipEvent_t ev[3] = {};          // start, sweep start, sweep end
-};
+// Host-side checks of one model's values (host pointers only).
+int masw::check_model_values(int32_t N, const double* h, const double* alpha, const double* beta,
+                       const double* rho, const char* what) {
+  if (N < 0 || N > MASW_MAX_LAYERS)
+    return fail(MASW_EINVAL, std::string(what) + ": n_layers out of range [0, MASW_MAX_LAYERS]");
+  if ((N > 0 && !h) || !alpha || !beta || !rho)
+    return fail(MASW_EINVAL, std::string(what) + ": null model array");
+  for (int j = 0; j < N; ++j)
+    if (!finite_pos(h[j])) return fail(MASW_EINVAL, std::string(what) + ": h must be finite and > 0");
+  for (int j = 0; j <= N; ++j) {
+    if (!finite_pos(beta[j]) || !finite_pos(alpha[j]) || !finite_pos(rho[j]))
+      return fail(MASW_EINVAL, std::string(what) + ": alpha, beta, rho must be finite and > 0");
+    if (!(alpha[j] > beta[j]))
+      return fail(MASW_EINVAL, std::string(what) + ": alpha must exceed beta in every layer");
+  }
+  return MASW_OK;
+}
+
+int masw::check_grid(const double* c, int32_t n_c, bool values) {
+  if (n_c < 2) return fail(MASW_EINVAL, "c_test: n_c must be >= 2");
+  if (!c) return fail(MASW_EINVAL, "c_test: null pointer");
+  if (!values) return MASW_OK;
+  for (int i = 0; i < n_c; ++i) {
+    if (!finite_pos(c[i])) return fail(MASW_EINVAL, "c_test: values must be finite and > 0");
+    if (i > 0 && !(c[i] > c[i - 1])) return fail(MASW_EINVAL, "c_test: must be strictly increasing");
+  }
+  return MASW_OK;
+}
+
+int masw::check_lambda(const double* lam, int32_t n, bool values) {
+  if (n < 0) return fail(MASW_EINVAL, "lambda: n_lambda must be >= 0");
+  if (n > 0 && !lam) return fail(MASW_EINVAL, "lambda: null pointer");
+  if (!values) return MASW_OK;
+  for (int i = 0; i < n; ++i)
+    if (!finite_pos(lam[i])) return fail(MASW_EINVAL, "lambda: values must be finite and > 0");
+  return MASW_OK;
+}
 
 namespace {
 
@@ -77,46 +88,6 @@ struct Bump {
   }
   bool ok() const { return off <= cap; }
 };
-
-bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
-
-// Host-side checks of one model's values (host pointers only).
-int check_model_values(int32_t N, const double* h, const double* alpha, const double* beta,
-                       const double* rho, const char* what) {
-  if (N < 0 || N > MASW_MAX_LAYERS)
-    return fail(MASW_EINVAL, std::string(what) + ": n_layers out of range [0, MASW_MAX_LAYERS]");
-  if ((N > 0 && !h) || !alpha || !beta || !rho)
-    return fail(MASW_EINVAL, std::string(what) + ": null model array");
-  for (int j = 0; j < N; ++j)
-    if (!finite_pos(h[j])) return fail(MASW_EINVAL, std::string(what) + ": h must be finite and > 0");
-  for (int j = 0; j <= N; ++j) {
-    if (!finite_pos(beta[j]) || !finite_pos(alpha[j]) || !finite_pos(rho[j]))
-      return fail(MASW_EINVAL, std::string(what) + ": alpha, beta, rho must be finite and > 0");
-    if (!(alpha[j] > beta[j]))
-      return fail(MASW_EINVAL, std::string(what) + ": alpha must exceed beta in every layer");
-  }
-  return MASW_OK;
-}
-
-int check_grid(const double* c, int32_t n_c, bool values) {
-  if (n_c < 2) return fail(MASW_EINVAL, "c_test: n_c must be >= 2");
-  if (!c) return fail(MASW_EINVAL, "c_test: null pointer");
-  if (!values) return MASW_OK;
-  for (int i = 0; i < n_c; ++i) {
-    if (!finite_pos(c[i])) return fail(MASW_EINVAL, "c_test: values must be finite and > 0");
-    if (i > 0 && !(c[i] > c[i - 1])) return fail(MASW_EINVAL, "c_test: must be strictly increasing");
-  }
-  return MASW_OK;
-}
-
-int check_lambda(const double* lam, int32_t n, bool values) {
-  if (n < 0) return fail(MASW_EINVAL, "lambda: n_lambda must be >= 0");
-  if (n > 0 && !lam) return fail(MASW_EINVAL, "lambda: null pointer");
-  if (!values) return MASW_OK;
-  for (int i = 0; i < n; ++i)
-    if (!finite_pos(lam[i])) return fail(MASW_EINVAL, "lambda: values must be finite and > 0");
-  return MASW_OK;
-}
 
 // Flattened view of the inputs, host or device, with sizes.
 struct Inputs {
@@ -200,12 +171,12 @@ int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t fl
   const bool dev = (flags & MASW_DEVICE_PTRS) != 0;
   hipStream_t s = stream ? static_cast<hipStream_t>(stream) : ctx->stream;
   const size_t need = workspace_bytes(in, !dev, !dev);
-  if (need > ctx->arena_size)
+  if (need > ctx->sync_size)
     return fail(MASW_ENOMEM, "request needs " + std::to_string(need) + " B of device memory, budget is " +
-                                 std::to_string(ctx->arena_size) + " B");
+                                 std::to_string(ctx->sync_size) + " B");
   MASW_HIP(hipSetDevice(ctx->device));
 
-  Bump b{ctx->arena, ctx->arena_size, 0};
+  Bump b{ctx->arena, ctx->sync_size, 0};
   const size_t R = size_t(in.n_layers_total + in.n_models);
   PrepArgs p{};
   p.counters = b.take<Counters>(1);
@@ -373,6 +344,7 @@ int masw_create(int device, size_t hbm_budget_bytes, masw_ctx** out) {
     if (hipEventCreate(&e) != hipSuccess) return cleanup(MASW_EDEVICE, "hipEventCreate failed");
   if (hipMalloc(&ctx->arena, budget) != hipSuccess) return cleanup(MASW_ENOMEM, "cannot allocate the HBM budget");
   ctx->arena_size = budget;
+  ctx->sync_size = budget;
   ctx->counters = reinterpret_cast<Counters*>(ctx->arena);
   for (int mode = 0; mode < 2; ++mode)
     for (int lg = 0; lg < 5; ++lg) ctx->blocks_per_cu[mode][lg] = sweep_blocks_per_cu(mode, 1 << lg);
@@ -386,6 +358,10 @@ int masw_create(int device, size_t hbm_budget_bytes, masw_ctx** out) {
 
 void masw_destroy(masw_ctx* ctx) {
   if (!ctx) return;
+  if (ctx->server) {
+    server_destroy(ctx->server);
+    ctx->server = nullptr;
+  }
   (void)hipSetDevice(ctx->device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   if (ctx->last_stream && ctx->last_stream != ctx->stream) (void)hipStreamSynchronize(ctx->last_stream);
@@ -519,9 +495,9 @@ int masw_sign_map(masw_ctx* ctx, const double* c_test, int32_t n_c, const double
   const size_t cells = size_t(n_lambda) * size_t(n_c);
   size_t need = workspace_bytes(in, !dev, false);
   if (!dev) need += cells * (sizeof(int8_t) + sizeof(double)) + 2 * kAlign;
-  if (need > ctx->arena_size) return fail(MASW_ENOMEM, "sign map exceeds the HBM budget");
+  if (need > ctx->sync_size) return fail(MASW_ENOMEM, "sign map exceeds the HBM budget");
   MASW_HIP(hipSetDevice(ctx->device));
-  Bump b{ctx->arena, ctx->arena_size, 0};
+  Bump b{ctx->arena, ctx->sync_size, 0};
   const size_t R = size_t(model->n_layers + 1);
   PrepArgs p{};
   p.counters = b.take<Counters>(1);

@@ -1,0 +1,174 @@
+"""The serving loop (masw_server_start / masw_submit / masw_poll / masw_wait).
+
+Each request's results must equal, bit for bit, those of the synchronous
+masw_dispersion_curve on the same inputs, whether it ran alone or among
+other requests admitted and advanced in the same ticks; those in turn match
+the oracle (tests/test_gpu_parity.py)."""
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2003_02256_amd as M
+import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture
+def ctx(gpu):
+    c = M.Context(0, 1 << 30)
+    yield c
+    c.close()
+
+
+def f64(x):
+    return np.ascontiguousarray(x, dtype=np.float64)
+
+
+def submit(ctx, c, lam, m, prec):
+    return M.masw_submit(ctx.ctx, f64(c), f64(lam), f64(m.h), f64(m.alpha), f64(m.beta), f64(m.rho), prec)
+
+
+def out_arrays(W):
+    return np.empty(W), np.empty(W, np.int32), np.empty(W, np.int32), np.empty(W)
+
+
+def wait(ctx, ticket, W, timeout_us=60_000_000):
+    o = out_arrays(W)
+    info = M.masw_wait(ctx.ctx, ticket, timeout_us, *o)
+    assert info is not None
+    return o, info
+
+
+def chain_requests(n, seed=5, steps=3):
+    bases = WL.chain_bases(64, seed)
+    rng = np.random.Generator(np.random.PCG64(seed + 100))
+    reqs = []
+    for i in range(n):
+        ch = bases[i % len(bases)]
+        m = ch.model
+        for _ in range(steps):
+            m = WL.chain_step(rng, m)
+        reqs.append((m, ch.lambdas))
+    return reqs
+
+
+def test_server_matches_synchronous_path_bitwise(ctx):
+    wl = WL.two_layer_case()
+    m, lam, c = wl.models[0], wl.lambdas[0], wl.c_test
+    M.masw_server_start(ctx.ctx)
+    for prec in (M.MASW_PREC_FP64, M.MASW_PREC_SPLIT):
+        t = submit(ctx, c, lam, m, prec)
+        got, info = wait(ctx, t, len(lam))
+        want = ctx.curve(c, lam, m, prec)
+        for x, y in zip(got, want):
+            np.testing.assert_array_equal(x, y)
+        assert info["done_ns"] >= info["admit_ns"] >= info["submit_ns"] > 0 and info["ticks"] >= 1
+        pts = O.dispersion_curve(lam, c, m)
+        assert list(got[1]) == [p.idx for p in pts]
+    M.masw_server_stop(ctx.ctx)
+
+
+def test_alone_equals_in_mix(ctx):
+    c = WL.serving_grid()
+    reqs = chain_requests(48)
+    M.masw_server_start(ctx.ctx, rounds_per_tick=4)
+    # all at once: they share ticks
+    mixed = []
+    tickets = [(submit(ctx, c, lam, m, M.MASW_PREC_SPLIT if i % 2 else M.MASW_PREC_FP64), len(lam))
+               for i, (m, lam) in enumerate(reqs)]
+    for t, W in tickets:
+        mixed.append(wait(ctx, t, W)[0])
+    stats = M.masw_server_get_stats(ctx.ctx)
+    assert stats["max_resident"] > 1, stats
+    # one at a time
+    for i, (m, lam) in enumerate(reqs):
+        prec = M.MASW_PREC_SPLIT if i % 2 else M.MASW_PREC_FP64
+        alone, _ = wait(ctx, submit(ctx, c, lam, m, prec), len(lam))
+        for x, y in zip(alone, mixed[i]):
+            np.testing.assert_array_equal(x, y)
+        if i % 8 == 0:   # and the synchronous path
+            for x, y in zip(ctx.curve(c, lam, m, prec), alone):
+                np.testing.assert_array_equal(x, y)
+    M.masw_server_stop(ctx.ctx)
+    print(f"served {2 * len(reqs)} requests, stats {stats}", flush=True)
+
+
+def test_poll_wait_and_ticket_lifecycle(ctx):
+    wl = WL.fine_scale_case()
+    m, lam, c = wl.models[0], wl.lambdas[0][::4].copy(), wl.c_test
+    M.masw_server_start(ctx.ctx, max_grid=120_000, rounds_per_tick=1)
+    t = submit(ctx, c, lam, m, M.MASW_PREC_FP64)
+    o = out_arrays(len(lam))
+    # a 250-wavelength, 115,001-point request needs many 1-round ticks
+    assert M.masw_poll(ctx.ctx, t, *o) is None
+    with pytest.raises(M.MaswError) as e:
+        M.masw_wait(ctx.ctx, t, 1, *o)
+    assert e.value.code == M.MASW_ETIMEOUT
+    info = M.masw_wait(ctx.ctx, t, -1, *o)
+    assert info["ticks"] > 1
+    with pytest.raises(M.MaswError) as e:
+        M.masw_poll(ctx.ctx, t, *o)
+    assert e.value.code == M.MASW_ENOENT
+    with pytest.raises(M.MaswError) as e:
+        M.masw_poll(ctx.ctx, 987654321, *o)
+    assert e.value.code == M.MASW_ENOENT
+    want = ctx.curve(c, lam, m, M.MASW_PREC_FP64)
+    for x, y in zip(o, want):
+        np.testing.assert_array_equal(x, y)
+    M.masw_server_stop(ctx.ctx)
+
+
+def test_hbm_budget_admission(ctx):
+    c = WL.serving_grid()
+    reqs = chain_requests(12, seed=6)
+    # a pool that holds only about two requests at a time
+    M.masw_server_start(ctx.ctx, pool_bytes=200_000, rounds_per_tick=8)
+    tickets = [(submit(ctx, c, lam, m, M.MASW_PREC_SPLIT), len(lam)) for m, lam in reqs]
+    res = [wait(ctx, t, W)[0] for t, W in tickets]
+    stats = M.masw_server_get_stats(ctx.ctx)
+    assert stats["admit_waits"] > 0 and stats["max_resident"] <= 3, stats
+    for (m, lam), got in zip(reqs, res):
+        for x, y in zip(ctx.curve(c, lam, m, M.MASW_PREC_SPLIT), got):
+            np.testing.assert_array_equal(x, y)
+    with pytest.raises(M.MaswError) as e:   # can never fit
+        big = WL.fine_scale_case()
+        submit(ctx, big.c_test[:30000], big.lambdas[0][:500], big.models[0], M.MASW_PREC_FP64)
+    assert e.value.code in (M.MASW_ENOMEM, M.MASW_EINVAL)
+    M.masw_server_stop(ctx.ctx)
+
+
+def test_stop_drains_and_restart(ctx):
+    c = WL.serving_grid()
+    reqs = chain_requests(6, seed=7)
+    M.masw_server_start(ctx.ctx)
+    for m, lam in reqs:
+        submit(ctx, c, lam, m, M.MASW_PREC_FP64)
+    st = M.masw_server_get_stats(ctx.ctx)
+    M.masw_server_stop(ctx.ctx)          # waits for the six requests
+    assert st["submitted"] == 6
+    with pytest.raises(M.MaswError) as e:
+        submit(ctx, c, reqs[0][1], reqs[0][0], M.MASW_PREC_FP64)
+    assert e.value.code == M.MASW_EBUSY
+    # restart; an empty request completes at once; the synchronous path still works
+    M.masw_server_start(ctx.ctx)
+    with pytest.raises(M.MaswError) as e:
+        M.masw_server_start(ctx.ctx)
+    assert e.value.code == M.MASW_EBUSY
+    t = submit(ctx, c, np.zeros(0), reqs[0][0], M.MASW_PREC_FP64)
+    assert M.masw_poll(ctx.ctx, t, np.empty(0), np.empty(0, np.int32), np.empty(0, np.int32)) is not None
+    wl = WL.two_layer_case()
+    got = ctx.curve(wl.c_test, wl.lambdas[0], wl.models[0])
+    assert int(got[1][0]) == 176
+    M.masw_server_stop(ctx.ctx)
+
+
+def test_submit_validates_on_host(ctx):
+    wl = WL.two_layer_case()
+    m = wl.models[0].copy()
+    M.masw_server_start(ctx.ctx)
+    m.alpha[0] = 0.5 * m.beta[0]
+    with pytest.raises(M.MaswError) as e:
+        submit(ctx, wl.c_test, wl.lambdas[0], m, M.MASW_PREC_FP64)
+    assert e.value.code == M.MASW_EINVAL
+    M.masw_server_stop(ctx.ctx)
