@@ -107,11 +107,16 @@ struct PrepArgs {
 // Where one item's search stands.  The batch kernels keep it in registers;
 // the serving tick kernel keeps it in HBM between ticks.
 struct ItemState {
-  int32_t start;  // first grid position of the next sweep round
-  int32_t carry;  // sign at start - 1 (kNoSign before the first round)
-  int32_t done;   // 1 once the outputs are written
-  int32_t pad;
+  int32_t start;      // first grid position of the next sweep round
+  int32_t carry;      // sign at start - 1 (kNoSign before the first round)
+  int32_t seg_start;  // split path: where the current FP32 segment began
+  int32_t seg_carry;  // split path: FP64 sign at seg_start - 1 (kNoSign at the grid start)
+  int32_t done;       // 1 once the outputs are written
+  int32_t fp64;       // split path: 1 once it fell back to the FP64 sweep
+  int32_t pad[2];
 };
+
+__host__ __device__ inline ItemState item_state_init() { return ItemState{0, kNoSign, 0, kNoSign, 0, 0, {0, 0}}; }
 
 // ------------------------------------------------------------- serving --
 constexpr int kMaxSlots = 256;     // requests resident on the device at once

@@ -255,7 +255,7 @@ struct SweepShared {
   int last[G];
   int first[G];
   int pair[2];
-  int check[4];
+  int check[6];
 };
 
 struct WorkCount {
@@ -297,6 +297,14 @@ __device__ __forceinline__ void write_missing(const ItemOut& o, int status) {
 // return true.  If the budget runs out first, save where the sweep stands
 // in `st` and return false; resuming from `st` gives the same result as an
 // uninterrupted run, whatever G the resumed call uses.
+//
+// The split path trusts FP32 signs only where FP64 confirms them: every FP32
+// candidate is re-checked in FP64 on a 64-point window, and the FP64 sign
+// just before the window must equal the sign FP32 saw since the last
+// FP64-confirmed point (likewise at the end of the grid before reporting no
+// change).  If it does not, FP32 missed a change and the item continues as
+// an FP64 sweep from that point, so the split pick equals the FP64 pick
+// unless FP32 misses an even number of changes between confirmed points.
 template <int MODE, int G>
 __device__ bool run_item(const ItemRef& r, ItemState& st, int budget, SweepShared<G>& sh, WorkCount& wc,
                          const ItemOut& o) {
@@ -307,7 +315,91 @@ __device__ bool run_item(const ItemRef& r, ItemState& st, int budget, SweepShare
   const int n_c = r.n_c;
   int found = -1, sig_f = 0, prev_f = 0;
   int start = st.start, carry = st.carry, rounds = 0;
-  if (MODE == kModeFP64) {
+  bool fp64 = (MODE == kModeFP64) || st.fp64;
+
+  if (!fp64) {
+    const float k32 = float(r.k64);
+    int seg_start = st.seg_start, seg_carry = st.seg_carry;
+    for (;;) {
+      // FP32 sweep for a candidate, from `start` (inside the segment that
+      // began at seg_start, whose predecessor's FP64 sign is seg_carry).
+      int cand = -1, fp32_before = kNoSign;
+      for (int base = start; base < n_c; base += P) {
+        if (rounds == budget) {
+          st.start = base;
+          st.carry = carry;
+          st.seg_start = seg_start;
+          st.seg_carry = seg_carry;
+          return false;
+        }
+        ++rounds;
+        const int i = base + tid;
+        const int sg = (i < n_c) ? det_sign<float, false>(r.c32[i], k32, r.L32, r.N, nullptr) : kNoSign;
+        int s_c, p_c;
+        const int f = round_first_change<G>(sg, carry, sh.last, sh.first, sh.pair, &carry, &s_c, &p_c);
+        wc.sweep += (unsigned long long)min(P, n_c - base);
+        if (f >= 0) {
+          cand = base + f;
+          fp32_before = p_c;
+          break;
+        }
+      }
+      // FP64 check by wavefront 0 while the others wait: the 64 positions
+      // ws-1 .. ws+62 around a candidate (48 before it, 15 after), or, when
+      // FP32 saw no change up to the end of the grid, the last position
+      // (lane 0 in FP64, lane 1 in FP32).  The positions do not depend on
+      // the group size, so neither does the outcome.
+      const bool at_end = cand < 0;
+      const int ws = at_end ? n_c : max(1, cand - 48);
+      if (wave == 0) {
+        const int i = ws - 1 + lane;
+        int sg = kNoSign;
+        if (at_end ? lane == 0 : i < n_c) sg = det_sign<double, false>(r.c64[i], r.k64, r.L64, r.N, nullptr);
+        int last, s_c = 0, p_c = 0;
+        const int f = at_end ? -1 : wave_first_change(sg, &s_c, &p_c, &last);
+        if (at_end && lane == 1) sh.check[5] = det_sign<float, false>(r.c32[n_c - 1], k32, r.L32, r.N, nullptr);
+        if (lane == 0) {
+          sh.check[0] = f;
+          sh.check[1] = at_end ? kNoSign : last;
+          sh.check[2] = s_c;
+          sh.check[3] = p_c;
+          sh.check[4] = sg;  // FP64 sign at ws - 1
+        }
+      }
+      __syncthreads();
+      const int f = sh.check[0];
+      const int last = sh.check[1];
+      const int first64 = sh.check[4];
+      const int fp32_last = sh.check[5];
+      sig_f = sh.check[2];
+      prev_f = sh.check[3];
+      __syncthreads();
+      wc.check += at_end ? 1ull : (unsigned long long)min(64, n_c - (ws - 1));
+      // The FP64 sign at ws - 1 must be the sign the segment started from.
+      const int ref = (seg_carry != kNoSign) ? seg_carry : (at_end ? fp32_last : fp32_before);
+      if (first64 != ref) {
+        // FP32 missed a change in [seg_start, ws - 1]: continue in FP64.
+        fp64 = true;
+        st.fp64 = 1;
+        start = seg_start;
+        carry = seg_carry;
+        break;
+      }
+      if (at_end) break;  // no change in the grid
+      if (f >= 0) {
+        found = ws - 1 + f;
+        break;
+      }
+      // Rejected: a new segment begins after the window, from the FP64 sign
+      // of its last position.  A window that reached the end of the grid
+      // leaves nothing to search.
+      start = ws + 63;
+      if (start >= n_c) break;
+      carry = seg_carry = last;
+      seg_start = start;
+    }
+  }
+  if (fp64) {
     for (int base = start; base < n_c; base += P) {
       if (rounds == budget) {
         st.start = base;
@@ -322,62 +414,6 @@ __device__ bool run_item(const ItemRef& r, ItemState& st, int budget, SweepShare
       if (f >= 0) {
         found = base + f;
         break;
-      }
-    }
-  } else {
-    const float k32 = float(r.k64);
-    while (start < n_c && found < 0) {
-      // FP32 sweep from `start` for a candidate change.
-      int cand = -1;
-      for (int base = start; base < n_c; base += P) {
-        if (rounds == budget) {
-          st.start = base;
-          st.carry = carry;
-          return false;
-        }
-        ++rounds;
-        const int i = base + tid;
-        const int sg = (i < n_c) ? det_sign<float, false>(r.c32[i], k32, r.L32, r.N, nullptr) : kNoSign;
-        int s_c, p_c;
-        const int f = round_first_change<G>(sg, carry, sh.last, sh.first, sh.pair, &carry, &s_c, &p_c);
-        wc.sweep += (unsigned long long)min(P, n_c - base);
-        if (f >= 0) {
-          cand = base + f;
-          break;
-        }
-      }
-      if (cand < 0) break;
-      // FP64 re-check of the 64 positions ws-1 .. ws+62 around the
-      // candidate (48 before it, 15 after), one per lane of wavefront 0;
-      // the other wavefronts wait.  The window does not depend on the
-      // group size, so neither does the outcome.
-      const int ws = max(1, cand - 48);
-      if (wave == 0) {
-        const int i = ws - 1 + lane;
-        const int sg = (i < n_c) ? det_sign<double, false>(r.c64[i], r.k64, r.L64, r.N, nullptr) : kNoSign;
-        int last, s_c = 0, p_c = 0;
-        const int f = wave_first_change(sg, &s_c, &p_c, &last);
-        if (lane == 0) {
-          sh.check[0] = f;
-          sh.check[1] = last;
-          sh.check[2] = s_c;
-          sh.check[3] = p_c;
-        }
-      }
-      __syncthreads();
-      const int f = sh.check[0];
-      const int last = sh.check[1];
-      sig_f = sh.check[2];
-      prev_f = sh.check[3];
-      __syncthreads();
-      wc.check += (unsigned long long)min(64, n_c - (ws - 1));
-      if (f >= 0) {
-        found = ws - 1 + f;
-      } else {
-        // Rejected: resume the FP32 sweep after the checked window,
-        // carrying the FP64 sign of its last position.
-        start = ws + 63;
-        carry = last;
       }
     }
   }
@@ -472,7 +508,7 @@ __global__ __launch_bounds__(64 * G) void sweep_kernel(SweepArgs a) {
       write_missing<G>(o, MASW_STATUS_INVALID);
       continue;
     }
-    ItemState st{0, kNoSign, 0, 0};
+    ItemState st = item_state_init();
     run_item<MODE, G>(r, st, 0x7fffffff, sh, wc, o);
   }
   flush_counts<G>(a.counters, wc);
@@ -544,7 +580,7 @@ __global__ __launch_bounds__(256) void admit_kernel(const AdmitList* __restrict_
     const double l = lam[w];
     const bool ok = valid && (l > 0.0) && (l < __builtin_inf());
     d.lam_k[w] = ok ? (2.0 * M_PI / l) : __builtin_nan("");
-    d.state[w] = ItemState{0, kNoSign, 0, 0};
+    d.state[w] = item_state_init();
   }
   if (threadIdx.x == 0) slot_remaining[list->slot[b]] = W;
 }

@@ -309,3 +309,25 @@ def test_batch_equals_single_model_runs(torch_dev, ctx):
         for x, y in zip(alone, res):
             np.testing.assert_array_equal(x, y[off:off + len(lam)])
         off += len(lam)
+
+
+def test_split_on_a_grid_finer_than_fp32(torch_dev, ctx):
+    # At c ~ 138 m/s one float spans about 1500 grid points of 1e-8 m/s, so
+    # the FP32 sweep sees its change hundreds of points off.  Early, the FP64
+    # re-check windows walk it forward; late, the FP64 sign before the window
+    # disagrees with FP32's and the item re-sweeps in FP64.  Either way the
+    # split pick must equal the FP64 pick.
+    wl = WL.two_layer_case()
+    m = wl.models[0]
+    c = WL.uniform_grid(137.9170, 1e-8, 60001)
+    lam = np.array([1.0])
+    want = oracle_curve(lam, c, m)
+    got64 = dev_curve(torch_dev, ctx, c, lam, m, M.MASW_PREC_FP64)
+    got32 = dev_curve(torch_dev, ctx, c, lam, m, M.MASW_PREC_SPLIT)
+    compare("fine grid FP64", got64, *want, lam, c, m)
+    compare("fine grid split", got32, *want, lam, c, m)
+    for x, y in zip(got64, got32):
+        np.testing.assert_array_equal(x, y)
+    st = ctx.stats()
+    print(f"fine grid split stats {st}", flush=True)
+    assert st["check_evals"] >= 64 and st["sweep_evals"] > st["useful_evals"] + 512
