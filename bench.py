@@ -223,6 +223,60 @@ def serving_bench(M, torch, a):
     print(json.dumps(res), flush=True)
 
 
+# ------------------------------------------------------------------ uniform --
+def uniform_bench(M, torch, a):
+    """The paper's uniform curves (Section 3.3): lengths 50-500 of one repeated
+    wavelength, picks at 72, 238, 256 m/s, 1000 test velocities, 14x14
+    matrices (N = 6).  Early exit (this library's curve) against evaluating
+    every (wavelength, velocity) matrix (the sign map, as the paper's GPU
+    code did)."""
+    import workloads as WL
+    dev = torch.device("cuda:0")
+    ctx_obj = M.Context(0, 1 << 30)
+    ctx = ctx_obj.ctx
+    rows, tot_useful, tot_s = [], 0, 0.0
+    t64 = lambda x: torch.as_tensor(np.ascontiguousarray(x, np.float64), device=dev)
+    for c_pick in (72.0, 238.0, 256.0):
+        for L in (50, 100, 200, 300, 400, 500):
+            wl = WL.uniform_case(c_pick, L)
+            m, lam, c = wl.models[0], wl.lambdas[0], wl.c_test
+            args = [t64(c), t64(lam), t64(m.h), t64(m.alpha), t64(m.beta), t64(m.rho)]
+            out = (torch.empty(L, dtype=torch.float64, device=dev), torch.empty(L, dtype=torch.int32, device=dev),
+                   torch.empty(L, dtype=torch.int32, device=dev), torch.empty(L, dtype=torch.float64, device=dev))
+            sig = torch.empty(L * c.shape[0], dtype=torch.int8, device=dev)
+
+            def curve():
+                M.masw_dispersion_curve(ctx, *args, M.MASW_PREC_FP64, 0, None, *out)
+
+            def smap():
+                M.masw_sign_map(ctx, *args, M.MASW_PREC_FP64, 0, None, sig)
+
+            res = {}
+            for name, fn in (("early_exit", curve), ("sign_map", smap)):
+                for _ in range(a.warmup):
+                    fn()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(a.steps):
+                    fn()
+                torch.cuda.synchronize()
+                res[name] = (time.perf_counter() - t0) / a.steps * 1e3
+            idx = out[1].cpu().numpy()
+            useful = int((idx + 1).sum())
+            tot_useful += useful
+            tot_s += res["early_exit"] * 1e-3
+            rows.append({"c_pick": c_pick, "length": L, "idx": int(idx[0]), "early_exit_ms": res["early_exit"],
+                         "sign_map_ms": res["sign_map"], "useful_evals": useful,
+                         "grid_evals": L * int(c.shape[0])})
+    ctx_obj.close()
+    out = {"metric": METRIC, "value": tot_useful / tot_s, "unit": "det evals/s", "n_gpus": 1, "steps": a.steps,
+           "warmup": a.warmup, "ms_per_step": tot_s * 1e3 / len(rows), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "uniform_curves_L50-500_c72_238_256", "n_c": 1000, "layers": 6},
+           "uniform": rows}
+    print(json.dumps(out), flush=True)
+
+
 # ------------------------------------------------------------- cpu baseline --
 def _oracle_point(args):
     import oracle as O
@@ -270,7 +324,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="fine_scale", choices=["fine_scale", "two_layer", "batch", "serving"])
+    ap.add_argument("--workload", default="fine_scale",
+                    choices=["fine_scale", "two_layer", "batch", "serving", "uniform"])
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="measured seconds of the serving trace")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target CPU work of the oracle sample")
@@ -300,6 +355,9 @@ def main():
     M.library()
     if a.workload == "serving":
         serving_bench(M, torch, a)
+        return
+    if a.workload == "uniform":
+        uniform_bench(M, torch, a)
         return
     dev = torch.device("cuda:0")
     wl = make_workload(a.workload)

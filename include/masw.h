@@ -250,6 +250,18 @@ int masw_wait(masw_ctx *ctx, uint64_t ticket, int64_t timeout_us, double *C_t, i
 
 int masw_server_get_stats(masw_ctx *ctx, masw_server_stats *out);
 
+/* Misfit of each model's theoretical curve against an experimental curve
+ * (Algorithm 2, Section 2.1): for model m with l_m wavelengths,
+ *     misfit[m] = (1/l_m) * sum_i |C_t[i] - C_e[i]| / C_e[i]
+ * over its wavelengths i (lambda_off as in masw_batch).  A NaN C_t (no sign
+ * change found) makes that model's misfit NaN; a model with no wavelengths
+ * gets NaN.  C_t, C_e: [lambda_off[n_models]]; C_e finite and > 0;
+ * misfit: [n_models].  The sum is a fixed-order tree, so the result does
+ * not depend on the launch. */
+int masw_misfit(masw_ctx *ctx, int32_t n_models, const int32_t *lambda_off,
+                const double *C_t, const double *C_e, uint32_t flags, void *stream,
+                double *misfit);
+
 /* Counters of the last completed call on ctx (for MASW_DEVICE_PTRS calls,
  * after the stream has been synchronised; this function synchronises). */
 int masw_get_stats(masw_ctx *ctx, masw_stats *out);

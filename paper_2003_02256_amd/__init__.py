@@ -121,6 +121,7 @@ def library() -> ctypes.CDLL:
             "masw_sign_map": (ctypes.c_int, [vp, vp, i32, vp, i32, ctypes.POINTER(masw_model),
                                              ctypes.c_int, u32, vp, vp, vp]),
             "masw_get_stats": (ctypes.c_int, [vp, ctypes.POINTER(masw_stats)]),
+            "masw_misfit": (ctypes.c_int, [vp, i32, vp, vp, vp, u32, vp, vp]),
             "masw_server_start": (ctypes.c_int, [vp, ctypes.POINTER(masw_server_opts)]),
             "masw_server_stop": (ctypes.c_int, [vp]),
             "masw_submit": (ctypes.c_int, [vp, vp, i32, vp, i32, ctypes.POINTER(masw_model), ctypes.c_int,
@@ -260,6 +261,15 @@ def masw_sign_map(ctx, c_test, lam, h, alpha, beta, rho, prec: int, flags: int, 
         ctx, _ptr(c_test, np.float64), int(c_test.shape[0]), _ptr(lam, np.float64), int(lam.shape[0]),
         ctypes.byref(m), prec, fl, _stream(stream, fl & MASW_DEVICE_PTRS),
         _ptr(sigma, np.int8), _ptr(log_abs_det, np.float64)), "masw_sign_map")
+
+
+def masw_misfit(ctx, lambda_off, C_t, C_e, flags: int, stream, misfit) -> int:
+    """Marshals to the C function (Algorithm 2 per model)."""
+    fl = flags | _device_flag(lambda_off, C_t, C_e, misfit)
+    return _check(library().masw_misfit(ctx, int(lambda_off.shape[0]) - 1, _ptr(lambda_off, np.int32),
+                                        _ptr(C_t, np.float64), _ptr(C_e, np.float64), fl,
+                                        _stream(stream, fl & MASW_DEVICE_PTRS), _ptr(misfit, np.float64)),
+                  "masw_misfit")
 
 
 def masw_get_stats(ctx) -> dict:

@@ -645,6 +645,34 @@ __global__ __launch_bounds__(64 * G) void tick_kernel(TickArgs a) {
   flush_counts<G>(a.counters, wc);
 }
 
+// -------------------------------------------------------------- misfit --
+// Algorithm 2 per model: one workgroup of 256 threads per model; each thread
+// sums a strided subset in order, then a fixed-order tree in LDS.
+__global__ __launch_bounds__(256) void misfit_kernel(int n_models, const int32_t* __restrict__ lambda_off,
+                                                     const double* __restrict__ c_t,
+                                                     const double* __restrict__ c_e, double* __restrict__ out) {
+  __shared__ double s[256];
+  const int m = blockIdx.x;
+  if (m >= n_models) return;
+  const int lo = lambda_off[m], hi = lambda_off[m + 1];
+  double acc = 0.0;
+  for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) acc += ::fabs(c_t[i] - c_e[i]) / c_e[i];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[m] = (hi > lo) ? s[0] / double(hi - lo) : __builtin_nan("");
+}
+
+hipError_t launch_misfit(int n_models, const int32_t* lambda_off, const double* c_t, const double* c_e,
+                         double* out, hipStream_t st) {
+  if (n_models <= 0) return hipSuccess;
+  hipLaunchKernelGGL(misfit_kernel, dim3(n_models), dim3(256), 0, st, n_models, lambda_off, c_t, c_e, out);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------ sign map --
 // Every (wavelength, grid point) of model 0, no early exit: blockIdx.y is
 // the wavelength, x covers the grid.

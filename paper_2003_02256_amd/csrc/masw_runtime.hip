@@ -75,6 +75,14 @@ namespace {
 
 constexpr size_t kAlign = 256;
 
+// Every synchronous call reuses the front of the arena.  A call on a stream
+// other than the previous call's first waits for that stream, so the previous
+// call's kernels are done with the memory.
+hipError_t claim_arena(masw_ctx* ctx, hipStream_t s) {
+  if (ctx->last_stream && ctx->last_stream != s) return hipStreamSynchronize(ctx->last_stream);
+  return hipSuccess;
+}
+
 struct Bump {
   char* base;
   size_t cap;
@@ -175,6 +183,7 @@ int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t fl
     return fail(MASW_ENOMEM, "request needs " + std::to_string(need) + " B of device memory, budget is " +
                                  std::to_string(ctx->sync_size) + " B");
   MASW_HIP(hipSetDevice(ctx->device));
+  MASW_HIP(claim_arena(ctx, s));
 
   Bump b{ctx->arena, ctx->sync_size, 0};
   const size_t R = size_t(in.n_layers_total + in.n_models);
@@ -497,6 +506,7 @@ int masw_sign_map(masw_ctx* ctx, const double* c_test, int32_t n_c, const double
   if (!dev) need += cells * (sizeof(int8_t) + sizeof(double)) + 2 * kAlign;
   if (need > ctx->sync_size) return fail(MASW_ENOMEM, "sign map exceeds the HBM budget");
   MASW_HIP(hipSetDevice(ctx->device));
+  MASW_HIP(claim_arena(ctx, s));
   Bump b{ctx->arena, ctx->sync_size, 0};
   const size_t R = size_t(model->n_layers + 1);
   PrepArgs p{};
@@ -556,6 +566,53 @@ int masw_sign_map(masw_ctx* ctx, const double* c_test, int32_t n_c, const double
     }
     MASW_HIP(hipStreamSynchronize(s));
   }
+  return MASW_OK;
+}
+
+int masw_misfit(masw_ctx* ctx, int32_t n_models, const int32_t* lambda_off, const double* C_t, const double* C_e,
+                uint32_t flags, void* stream, double* misfit) {
+  const bool dev = (flags & MASW_DEVICE_PTRS) != 0;
+  if (n_models < 0) return fail(MASW_EINVAL, "n_models must be >= 0");
+  if (n_models > 0 && (!lambda_off || !C_t || !C_e || !misfit)) return fail(MASW_EINVAL, "misfit: null array");
+  if (flags & ~MASW_DEVICE_PTRS) return fail(MASW_EINVAL, "flags: unknown bits");
+  std::vector<int32_t> off;
+  if (!dev && n_models > 0) {
+    off.assign(lambda_off, lambda_off + n_models + 1);
+    if (off[0] != 0) return fail(MASW_EINVAL, "lambda_off must start at 0");
+    for (int m = 0; m < n_models; ++m)
+      if (off[m + 1] < off[m]) return fail(MASW_EINVAL, "lambda_off must be non-decreasing");
+    for (int i = 0; i < off[n_models]; ++i)
+      if (!(std::isfinite(C_e[i]) && C_e[i] > 0.0)) return fail(MASW_EINVAL, "C_e must be finite and > 0");
+  }
+  if (!ctx) return fail(MASW_EINVAL, "ctx: null context");
+  if (n_models == 0) return MASW_OK;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  MASW_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : ctx->stream;
+  if (dev) {
+    // reads and writes only caller memory: no arena claim
+    MASW_HIP(launch_misfit(n_models, lambda_off, C_t, C_e, misfit, s));
+    ctx->last_stream = s;
+    return MASW_OK;
+  }
+  const size_t W = size_t(off[n_models]);
+  MASW_HIP(claim_arena(ctx, s));
+  Bump b{ctx->arena, ctx->sync_size, 0};
+  b.take<Counters>(1);  // keep the counters block of the last call intact
+  int32_t* d_off = b.take<int32_t>(size_t(n_models) + 1);
+  double* d_ct = b.take<double>(W);
+  double* d_ce = b.take<double>(W);
+  double* d_out = b.take<double>(size_t(n_models));
+  if (!b.ok()) return fail(MASW_ENOMEM, "misfit exceeds the HBM budget");
+  MASW_HIP(hipMemcpyAsync(d_off, off.data(), sizeof(int32_t) * (n_models + 1), hipMemcpyHostToDevice, s));
+  if (W) {
+    MASW_HIP(hipMemcpyAsync(d_ct, C_t, sizeof(double) * W, hipMemcpyHostToDevice, s));
+    MASW_HIP(hipMemcpyAsync(d_ce, C_e, sizeof(double) * W, hipMemcpyHostToDevice, s));
+  }
+  MASW_HIP(launch_misfit(n_models, d_off, d_ct, d_ce, d_out, s));
+  MASW_HIP(hipMemcpyAsync(misfit, d_out, sizeof(double) * n_models, hipMemcpyDeviceToHost, s));
+  MASW_HIP(hipStreamSynchronize(s));
+  ctx->last_stream = s;
   return MASW_OK;
 }
 

@@ -155,3 +155,18 @@ def test_serving_calls_validate_without_a_device(lib):
     assert lib.masw_server_stop(None) == M.MASW_EINVAL
     info = M.masw_request_info()
     assert lib.masw_poll(None, 1, None, None, None, None, ctypes.byref(info)) == M.MASW_EINVAL
+
+
+def test_misfit_validates_on_host(lib):
+    off = np.array([0, 2, 3], np.int32)
+    ct = np.array([100.0, 200.0, 300.0])
+    out = np.empty(2)
+    with pytest.raises(M.MaswError) as e:
+        M.masw_misfit(None, off, ct, np.array([100.0, 0.0, 300.0]), 0, None, out)
+    assert e.value.code == M.MASW_EINVAL and "C_e" in str(e.value)
+    with pytest.raises(M.MaswError) as e:
+        M.masw_misfit(None, np.array([0, 3, 2], np.int32), ct, ct, 0, None, out)
+    assert e.value.code == M.MASW_EINVAL and "non-decreasing" in str(e.value)
+    with pytest.raises(M.MaswError) as e:
+        M.masw_misfit(None, off, ct, ct, 0, None, out)
+    assert e.value.code == M.MASW_EINVAL and "ctx" in str(e.value)

@@ -331,3 +331,39 @@ def test_split_on_a_grid_finer_than_fp32(torch_dev, ctx):
     st = ctx.stats()
     print(f"fine grid split stats {st}", flush=True)
     assert st["check_evals"] >= 64 and st["sweep_evals"] > st["useful_evals"] + 512
+
+
+def test_misfit_matches_algorithm_2(torch_dev, ctx):
+    torch, dev = torch_dev
+    wl = WL.batch_case(n_models=16, seed=13)
+    ct, idx, st, cr = dev_batch(torch_dev, ctx, wl.c_test, wl.models, wl.lambdas, M.MASW_PREC_SPLIT)
+    lam_off = M.flatten_models(wl.models, wl.lambdas)[5]
+    rng = np.random.Generator(np.random.PCG64(1))
+    c_e = np.where(np.isfinite(ct), ct, 300.0) * (1.0 + 0.02 * rng.standard_normal(ct.shape[0]))
+    got = np.empty(16)
+    M.masw_misfit(ctx.ctx, lam_off, ct, c_e, 0, None, got)
+    want = np.array([O.misfit(ct[a:b], c_e[a:b]) for a, b in zip(lam_off[:-1], lam_off[1:])])
+    np.testing.assert_allclose(got, want, rtol=1e-12, equal_nan=True)
+    t = lambda x: torch.as_tensor(x, device=dev)
+    got_d = torch.empty(16, dtype=torch.float64, device=dev)
+    M.masw_misfit(ctx.ctx, t(lam_off), t(ct), t(c_e), 0, None, got_d)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(got_d.cpu().numpy(), got)
+
+
+@pytest.mark.parametrize("c_pick", [72.0, 238.0, 256.0])
+def test_uniform_curves(torch_dev, ctx, c_pick):
+    # identical layers over an identical half-space: every pick is the grid
+    # point just above the closed-form Rayleigh speed, and the full sign map's
+    # first change is at the same index
+    wl = WL.uniform_case(c_pick, 50)
+    m, lam, c = wl.models[0], wl.lambdas[0], wl.c_test
+    want = int(np.searchsorted(c, c_pick))          # c[want] == c_pick
+    c_root = c_pick - 0.25
+    for prec in (M.MASW_PREC_FP64, M.MASW_PREC_SPLIT):
+        ct, idx, st, cr = dev_curve(torch_dev, ctx, c, lam, m, prec)
+        assert np.all(idx == want) and np.all(st == 0) and np.all(ct == c_pick)
+        assert np.max(np.abs(cr - c_root) / c_root) < 1e-8
+    sig, _ = ctx.sign_map(c, lam[:3], m, M.MASW_PREC_FP64, want_log=False)
+    for row in sig:
+        assert int(np.nonzero(row[1:] != row[:-1])[0][0]) + 1 == want

@@ -166,6 +166,27 @@ def batch_case(n_models: int = 4096, seed: int = 4,
 
 
 # --------------------------------------------------------------------------
+# "Uniform" curves: every wavelength the same, picks at a chosen velocity.
+# --------------------------------------------------------------------------
+RAYLEIGH_RATIO_QUARTER_POISSON = 0.9194016867619  # c_R / beta at nu = 0.25
+
+
+def uniform_case(c_pick: float, length: int, lam: float = 10.0, n_layers: int = 6) -> Workload:
+    """`length` identical wavelengths over n_layers identical layers on an
+    identical half-space (alpha = sqrt(3) beta, rho = 2000); c_test 50-549.5
+    m/s at 0.5 m/s (1000 values).  The layered model behaves as the
+    half-space, so every wavelength has the same root whatever lam is; beta
+    puts that root a quarter grid step below the grid point c_pick, so the
+    reported velocity (the upper end of the bracket) is c_pick."""
+    beta = (c_pick - 0.25) / RAYLEIGH_RATIO_QUARTER_POISSON
+    N = n_layers
+    m = Model(h=np.full(N, 1.0), alpha=np.full(N + 1, np.sqrt(3.0) * beta),
+              beta=np.full(N + 1, beta), rho=np.full(N + 1, 2000.0))
+    return Workload(f"uniform_c{c_pick:g}_L{length}", [m], [np.full(length, lam)],
+                    uniform_grid(50.0, 0.5, 1000))
+
+
+# --------------------------------------------------------------------------
 # Random-walk chains for the serving workload.
 # --------------------------------------------------------------------------
 @dataclass
