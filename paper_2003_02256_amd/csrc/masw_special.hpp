@@ -52,6 +52,16 @@ constexpr double kInvFact[19] = {
     1.5619206968586225e-16};
 
 // ------------------------------------------------------------------- FP64 --
+// One Horner step p * x + c as a three-operand v_fma_f64.  FP64 coefficients
+// that do not fit in SGPRs are kept in VGPRs across the layer loop; written
+// as __builtin_fma, such a step is compiled into a copy of c followed by an
+// accumulating v_fmac_f64, two VALU slots instead of one.
+__device__ __forceinline__ double horner(double p, double x, double c) {
+  double d;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(p), "v"(x), "v"(c));
+  return d;
+}
+
 __device__ __forceinline__ double rcp(double d) {
   double r = __builtin_amdgcn_rcp(d);
   double e = __builtin_fma(-d, r, 1.0);
@@ -92,22 +102,22 @@ __device__ __forceinline__ void sin2_sincos(double x, double* s2, double* sc) {
   r = __builtin_fma(-k, kPio2_3, r);
   const double r2 = r * r;
   double ps = -kInvFact[15];
-  ps = __builtin_fma(ps, r2, kInvFact[13]);
-  ps = __builtin_fma(ps, r2, -kInvFact[11]);
-  ps = __builtin_fma(ps, r2, kInvFact[9]);
-  ps = __builtin_fma(ps, r2, -kInvFact[7]);
-  ps = __builtin_fma(ps, r2, kInvFact[5]);
-  ps = __builtin_fma(ps, r2, -kInvFact[3]);
+  ps = horner(ps, r2, kInvFact[13]);
+  ps = horner(ps, r2, -kInvFact[11]);
+  ps = horner(ps, r2, kInvFact[9]);
+  ps = horner(ps, r2, -kInvFact[7]);
+  ps = horner(ps, r2, kInvFact[5]);
+  ps = horner(ps, r2, -kInvFact[3]);
   ps = __builtin_fma(ps, r2, 1.0);
   const double sn = r * ps;                         // sin r
   double pc = kInvFact[16];
-  pc = __builtin_fma(pc, r2, -kInvFact[14]);
-  pc = __builtin_fma(pc, r2, kInvFact[12]);
-  pc = __builtin_fma(pc, r2, -kInvFact[10]);
-  pc = __builtin_fma(pc, r2, kInvFact[8]);
-  pc = __builtin_fma(pc, r2, -kInvFact[6]);
-  pc = __builtin_fma(pc, r2, kInvFact[4]);
-  pc = __builtin_fma(pc, r2, -kInvFact[2]);
+  pc = horner(pc, r2, -kInvFact[14]);
+  pc = horner(pc, r2, kInvFact[12]);
+  pc = horner(pc, r2, -kInvFact[10]);
+  pc = horner(pc, r2, kInvFact[8]);
+  pc = horner(pc, r2, -kInvFact[6]);
+  pc = horner(pc, r2, kInvFact[4]);
+  pc = __builtin_fma(pc, r2, -0.5);
   const double cs = __builtin_fma(pc, r2, 1.0);     // cos r
   const bool odd = (int(k) & 1) != 0;
   *s2 = odd ? cs * cs : sn * sn;
