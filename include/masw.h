@@ -135,6 +135,13 @@ typedef struct {
     float sweep_ms;         /* device time of the sweep/re-check/refine kernel,
                                from HIP events on the launch stream            */
     float total_ms;         /* device time of staging + ordering + sweep       */
+    int32_t shared_items;   /* wavelengths run as shared sweeps, which workgroups
+                               that run out of queued work join                */
+    uint32_t shared_stalls; /* shared sweeps abandoned after waiting too long
+                               for a joined round (always 0 unless the device
+                               misbehaves; such wavelengths get
+                               MASW_STATUS_INVALID)                            */
+    uint64_t helper_evals;  /* of sweep_evals, those done by joining workgroups */
 } masw_stats;
 
 /* Create a context on HIP device `device` that may hold up to

@@ -70,7 +70,9 @@ class masw_stats(ctypes.Structure):
     _fields_ = [("useful_evals", ctypes.c_uint64), ("sweep_evals", ctypes.c_uint64),
                 ("check_evals", ctypes.c_uint64), ("refine_evals", ctypes.c_uint64),
                 ("n_lambda", ctypes.c_uint64), ("waves_per_item", ctypes.c_int32),
-                ("workgroups", ctypes.c_int32), ("sweep_ms", ctypes.c_float), ("total_ms", ctypes.c_float)]
+                ("workgroups", ctypes.c_int32), ("sweep_ms", ctypes.c_float), ("total_ms", ctypes.c_float),
+                ("shared_items", ctypes.c_int32), ("shared_stalls", ctypes.c_uint32),
+                ("helper_evals", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -16,6 +16,7 @@ int sweep_blocks_per_cu(int mode, int G);
 int tick_blocks_per_cu(int G);
 hipError_t launch_sweep(int mode, int G, int blocks, hipStream_t s, const SweepArgs& a);
 hipError_t launch_prep(const PrepArgs& a, int single_N, int single_W, hipStream_t s);
+hipError_t launch_coop_init(const CoopInitArgs& a, hipStream_t s);
 hipError_t launch_sign_map(bool fp32, const SignMapArgs& a, hipStream_t s);
 hipError_t launch_admit(const AdmitList* list_dev, int n, int32_t* slot_remaining, hipStream_t s);
 hipError_t launch_tick(int G, int blocks, hipStream_t s, const TickArgs& a);
@@ -52,6 +53,7 @@ struct masw_ctx {
   int cus = 0;
   int blocks_per_cu[2][5] = {};   // [mode][log2 G], G = 1..16
   int forced_waves = 0;           // MASW_WAVES_PER_ITEM override (tuning)
+  bool shared_sweeps = true;      // MASW_SHARED_SWEEPS=0 turns shared sweeps off (tuning)
   std::mutex mu;
   masw_stats last = {};
   bool stats_pending = false;

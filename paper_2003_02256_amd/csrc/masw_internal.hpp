@@ -52,12 +52,28 @@ struct alignas(32) ModelDesc {
 struct alignas(64) Counters {
   uint32_t queue_head;        // next work item
   uint32_t grid_bad;          // nonzero if the c grid failed validation
-  uint32_t pad0[14];
+  uint32_t coop_stall;        // cooperative waits that reached their bound
+  uint32_t pad0[13];
   unsigned long long useful;  // sum of idx + 1
   unsigned long long sweep;   // sweep evaluations
   unsigned long long check;   // FP64 re-check evaluations
   unsigned long long refine;  // refinement evaluations
+  unsigned long long helper;  // sweep evaluations done by joining workgroups
   uint32_t hist[kBuckets];    // work-order histogram, then bucket offsets
+};
+
+// Shared sweep of one work item that idle workgroups may join (queue
+// positions below SweepArgs::n_coop).  The item's grid is cut into rounds of
+// 64 G positions; every workgroup on the item claims rounds from `next`,
+// evaluates them and publishes one summary word per round, and the owning
+// workgroup resolves the summaries in grid order, so the pick does not depend
+// on who evaluated which round.  All fields are accessed with agent-scope
+// atomics.
+struct alignas(16) CoopItem {
+  int32_t next;      // next round to claim
+  int32_t stop;      // rounds after this one are not needed (INT32_MAX until a change is seen; -1 when closed)
+  int32_t resolved;  // rounds resolved in grid order by the owner
+  int32_t rounds;    // rounds in the sweep; 0 before the owner starts, -1 after the shared sweep ends
 };
 
 struct SweepArgs {
@@ -76,6 +92,23 @@ struct SweepArgs {
   int32_t* out_idx;
   int32_t* out_status;
   double* out_cref;  // may be null
+  // Cooperative tail: items at queue positions < n_coop may be joined by
+  // workgroups that find the queue empty.
+  int32_t n_coop;
+  int32_t coop_stride;   // summary words per item (rounds of the longest sweep)
+  CoopItem* coop;        // [n_coop]
+  uint64_t* coop_sum;    // [n_coop * coop_stride] round summaries, 0 = not yet published
+  int32_t* coop_active;  // [gridDim.x] item each workgroup owns in its shared sweep, or -1
+};
+
+// Zero-state of the cooperative arrays (one launch before the sweep).
+struct CoopInitArgs {
+  CoopItem* coop;
+  int32_t n_coop;
+  uint64_t* coop_sum;
+  uint64_t n_sum;
+  int32_t* coop_active;
+  int32_t n_active;
 };
 
 struct PrepArgs {

@@ -11,7 +11,14 @@
 // (Algorithm 1's early exit; the paper's GPU design evaluated every (lambda, c)
 // instead, Section 2.3).  G is chosen by the host: 1 when there are many more
 // items than wavefront slots, up to 16 when a few deep items must fill the chip.
+// When items are few, the deepest of them would still finish long after the
+// rest: those items run as shared sweeps, whose rounds any workgroup that
+// finds the queue empty may claim and evaluate, while the owning workgroup
+// resolves the rounds in grid order.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <type_traits>
 
 #include "masw_internal.hpp"
 #include "masw_math.hpp"
@@ -256,10 +263,11 @@ struct SweepShared {
   int first[G];
   int pair[2];
   int check[6];
+  int coop[6];
 };
 
 struct WorkCount {
-  unsigned long long sweep = 0, check = 0, refine = 0, useful = 0;
+  unsigned long long sweep = 0, check = 0, refine = 0, useful = 0, helper = 0;
 };
 
 // Everything uniform about one item.
@@ -291,6 +299,205 @@ __device__ __forceinline__ void write_missing(const ItemOut& o, int status) {
   }
 }
 
+// ------------------------------------------------- shared (cooperative) sweep --
+// Cross-workgroup state lives in HBM and is read and written with
+// agent-scope atomics only: the L2 caches of the XCDs are not coherent with
+// each other for plain accesses.
+__device__ __forceinline__ int ld_agent(int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(int32_t* p, int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ld_agent(uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+constexpr int kCoopStall = -2;          // a shared sweep gave up waiting (never expected)
+constexpr int kCoopMaxPolls = 1 << 20;  // polls of one round summary (~2 s) before giving up
+constexpr int kCoopWindow = 16;         // rounds a joining workgroup may run ahead of the resolution
+constexpr int kJoinIdle = 32;           // fruitless searches before a joining workgroup leaves
+
+// Summary of one evaluated round, published as a single 64-bit word so that
+// no ordering between stores is needed: bit 63 set once published, bits
+// 32..47 the first change inside the round plus one (0: none), bytes 0..3
+// the sign codes at the round's first and last positions, at the change and
+// just before it.
+struct RoundSum {
+  int s0, sl, sa, pa, f;
+};
+
+__device__ __forceinline__ uint64_t pack_round(int s0, int sl, int sa, int pa, int f) {
+  return (1ull << 63) | (uint64_t(uint32_t(f + 1) & 0xffffu) << 32) | (uint64_t(uint8_t(pa)) << 24) |
+         (uint64_t(uint8_t(sa)) << 16) | (uint64_t(uint8_t(sl)) << 8) | uint64_t(uint8_t(s0));
+}
+
+__device__ __forceinline__ RoundSum unpack_round(uint64_t w) {
+  RoundSum u;
+  u.s0 = int8_t(w & 0xff);
+  u.sl = int8_t((w >> 8) & 0xff);
+  u.sa = int8_t((w >> 16) & 0xff);
+  u.pa = int8_t((w >> 24) & 0xff);
+  u.f = int((w >> 32) & 0xffff) - 1;
+  return u;
+}
+
+// Where one workgroup's shared sweep keeps its state (ci null: not shared).
+struct CoopRef {
+  CoopItem* ci;
+  uint64_t* sum;     // the item's round summaries
+  int32_t* active;   // this workgroup's slot in the list of open shared sweeps
+  int item;          // queue position
+};
+constexpr CoopRef kNoCoop{nullptr, nullptr, nullptr, 0};
+
+// Round rd of an item: positions rd*P .. rd*P+P-1, the first one with no
+// predecessor.  Returns the first change inside the round (uniform); *sl is
+// the sign at the last position (uniform), *sa/*pa the signs at the change
+// and before it, and thread 0's *s0 the sign at the first position.
+template <typename T, int G>
+__device__ __forceinline__ int eval_round(const ItemRef& r, int rd, SweepShared<G>& sh, int* s0, int* sl,
+                                          int* sa, int* pa) {
+  constexpr int P = 64 * G;
+  const int i = rd * P + int(threadIdx.x);
+  int sg = kNoSign;
+  if (i < r.n_c) {
+    if constexpr (sizeof(T) == 8)
+      sg = det_sign<double, false>(r.c64[i], r.k64, r.L64, r.N, nullptr);
+    else
+      sg = det_sign<float, false>(r.c32[i], float(r.k64), r.L32, r.N, nullptr);
+  }
+  *s0 = sg;
+  return round_first_change<G>(sg, kNoSign, sh.last, sh.first, sh.pair, sl, sa, pa);
+}
+
+// The owner's side of a shared sweep over the whole grid: the same first
+// change, and the same signs at it, as a sweep by this workgroup alone
+// (Algorithm 1's scan), while workgroups that join may evaluate any of the
+// rounds.  Thread 0 claims rounds one ahead (the claim's latency overlaps the
+// round), applies each round's summary in grid order with the carried sign
+// of the previous round, and waits only when it has no round of its own left.
+// Returns the change's position, -1 if the grid has none, or kCoopStall.
+template <typename T, int G>
+__device__ int coop_sweep(const ItemRef& r, const CoopRef& co, SweepShared<G>& sh, WorkCount& wc,
+                          Counters* cnt, int* sig, int* prev) {
+  constexpr int P = 64 * G;
+  const int tid = threadIdx.x;
+  const int n_rounds = (r.n_c + P - 1) / P;
+  int claim = 0, resolved = 0, carry = kNoSign, found = -1, fs = 0, fp = 0;
+  int stop = 0x7fffffff;
+  bool done = false;
+  if (tid == 0) {
+    st_agent(&co.ci->rounds, n_rounds);
+    st_agent(co.active, co.item);
+    claim = atomicAdd(&co.ci->next, 1);
+  }
+  for (;;) {
+    if (tid == 0) {
+      sh.coop[0] = claim;
+      sh.coop[1] = stop;
+    }
+    __syncthreads();
+    const int rd = sh.coop[0];
+    const bool eval = rd < n_rounds && rd <= sh.coop[1];
+    __syncthreads();
+    int nclaim = 0x7fffffff, nstop = stop;
+    if (eval) {
+      if (tid == 0) {
+        nclaim = atomicAdd(&co.ci->next, 1);
+        nstop = ld_agent(&co.ci->stop);
+      }
+      int s0, sl, sa = 0, pa = 0;
+      const int f = eval_round<T, G>(r, rd, sh, &s0, &sl, &sa, &pa);
+      wc.sweep += (unsigned long long)min(P, r.n_c - rd * P);
+      if (tid == 0) {
+        if (f >= 0) {
+          atomicMin(&co.ci->stop, rd);
+          stop = min(stop, rd);
+        }
+        if (rd == resolved) {  // next in grid order: apply it here
+          if (rd > 0 && carry != kNoSign && s0 != kNoSign && s0 != carry) {
+            found = rd * P, fs = s0, fp = carry, done = true;
+          } else if (f >= 0) {
+            found = rd * P + f, fs = sa, fp = pa, done = true;
+          } else {
+            carry = sl;
+            ++resolved;
+          }
+        } else {
+          st_agent(&co.sum[rd], pack_round(s0, sl, sa, pa, f));
+        }
+      }
+    } else if (tid == 0) {
+      nstop = ld_agent(&co.ci->stop);
+    }
+    if (tid == 0) {
+      stop = min(stop, nstop);
+      const int bound = stop >= n_rounds ? n_rounds : stop + 1;
+      // Rounds below the owner's next claim that are not resolved yet were
+      // claimed by joining workgroups (or published above).
+      while (!done && resolved < bound && resolved < nclaim) {
+        uint64_t w = ld_agent(&co.sum[resolved]);
+        if (!(w >> 63)) {
+          if (nclaim < bound) break;  // evaluate the own next round first
+          // Bounded wait; after any stall in the launch, no further waiting.
+          const int max_polls = ld_agent(reinterpret_cast<int32_t*>(&cnt->coop_stall)) ? 0 : kCoopMaxPolls;
+          int polls = 0;
+          while (!((w = ld_agent(&co.sum[resolved])) >> 63) && polls < max_polls) {
+            ++polls;
+            __builtin_amdgcn_s_sleep(2);
+          }
+          if (!(w >> 63)) {
+            atomicAdd(&cnt->coop_stall, 1u);
+            found = kCoopStall, done = true;
+            break;
+          }
+        }
+        const RoundSum u = unpack_round(w);
+        const int q = resolved;
+        if (q > 0 && carry != kNoSign && u.s0 != kNoSign && u.s0 != carry) {
+          found = q * P, fs = u.s0, fp = carry, done = true;
+        } else if (u.f >= 0) {
+          found = q * P + u.f, fs = u.sa, fp = u.pa, done = true;
+        } else {
+          carry = u.sl;
+          ++resolved;
+        }
+      }
+      if (!done && resolved >= n_rounds) done = true;  // no change in the grid
+      if (!done && nclaim >= bound && resolved >= bound) {
+        // bound < n_rounds means round `stop` holds a change, which the loop
+        // above must have found; anything else is a broken invariant.
+        atomicAdd(&cnt->coop_stall, 1u);
+        found = kCoopStall, done = true;
+      }
+      if (done) {
+        st_agent(&co.ci->stop, -1);  // close: joining workgroups stop claiming
+        st_agent(&co.ci->rounds, -1);
+        st_agent(co.active, -1);
+      } else {
+        st_agent(&co.ci->resolved, resolved);
+      }
+      sh.coop[2] = done ? 1 : 0;
+      sh.coop[3] = found;
+      sh.coop[4] = fs;
+      sh.coop[5] = fp;
+      claim = nclaim;
+    }
+    __syncthreads();
+    if (sh.coop[2]) {
+      found = sh.coop[3];
+      *sig = sh.coop[4];
+      *prev = sh.coop[5];
+      __syncthreads();
+      return found;
+    }
+  }
+}
+
 // Advance one item by at most `budget` sweep rounds of G*64 positions.  When
 // the first sign change is known (after the FP64 re-check for the split
 // path), refine it in FP64 and write the outputs through wavefront 0, then
@@ -307,7 +514,7 @@ __device__ __forceinline__ void write_missing(const ItemOut& o, int status) {
 // unless FP32 misses an even number of changes between confirmed points.
 template <int MODE, int G>
 __device__ bool run_item(const ItemRef& r, ItemState& st, int budget, SweepShared<G>& sh, WorkCount& wc,
-                         const ItemOut& o) {
+                         const ItemOut& o, const CoopRef& co, Counters* cnt) {
   constexpr int P = 64 * G;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -320,28 +527,41 @@ __device__ bool run_item(const ItemRef& r, ItemState& st, int budget, SweepShare
   if (!fp64) {
     const float k32 = float(r.k64);
     int seg_start = st.seg_start, seg_carry = st.seg_carry;
+    bool shared = co.ci != nullptr;  // the first FP32 pass is a shared sweep
     for (;;) {
       // FP32 sweep for a candidate, from `start` (inside the segment that
       // began at seg_start, whose predecessor's FP64 sign is seg_carry).
       int cand = -1, fp32_before = kNoSign;
-      for (int base = start; base < n_c; base += P) {
-        if (rounds == budget) {
-          st.start = base;
-          st.carry = carry;
-          st.seg_start = seg_start;
-          st.seg_carry = seg_carry;
-          return false;
+      if (shared) {
+        shared = false;
+        int s_c = 0, p_c = 0;
+        cand = coop_sweep<float, G>(r, co, sh, wc, cnt, &s_c, &p_c);
+        if (cand == kCoopStall) {
+          st.done = 1;
+          write_missing<G>(o, MASW_STATUS_INVALID);
+          return true;
         }
-        ++rounds;
-        const int i = base + tid;
-        const int sg = (i < n_c) ? det_sign<float, false>(r.c32[i], k32, r.L32, r.N, nullptr) : kNoSign;
-        int s_c, p_c;
-        const int f = round_first_change<G>(sg, carry, sh.last, sh.first, sh.pair, &carry, &s_c, &p_c);
-        wc.sweep += (unsigned long long)min(P, n_c - base);
-        if (f >= 0) {
-          cand = base + f;
-          fp32_before = p_c;
-          break;
+        if (cand >= 0) fp32_before = p_c;
+      } else {
+        for (int base = start; base < n_c; base += P) {
+          if (rounds == budget) {
+            st.start = base;
+            st.carry = carry;
+            st.seg_start = seg_start;
+            st.seg_carry = seg_carry;
+            return false;
+          }
+          ++rounds;
+          const int i = base + tid;
+          const int sg = (i < n_c) ? det_sign<float, false>(r.c32[i], k32, r.L32, r.N, nullptr) : kNoSign;
+          int s_c, p_c;
+          const int f = round_first_change<G>(sg, carry, sh.last, sh.first, sh.pair, &carry, &s_c, &p_c);
+          wc.sweep += (unsigned long long)min(P, n_c - base);
+          if (f >= 0) {
+            cand = base + f;
+            fp32_before = p_c;
+            break;
+          }
         }
       }
       // FP64 check by wavefront 0 while the others wait: the 64 positions
@@ -399,7 +619,14 @@ __device__ bool run_item(const ItemRef& r, ItemState& st, int budget, SweepShare
       seg_start = start;
     }
   }
-  if (fp64) {
+  if (fp64 && MODE == kModeFP64 && co.ci) {
+    found = coop_sweep<double, G>(r, co, sh, wc, cnt, &sig_f, &prev_f);
+    if (found == kCoopStall) {
+      st.done = 1;
+      write_missing<G>(o, MASW_STATUS_INVALID);
+      return true;
+    }
+  } else if (fp64) {
     for (int base = start; base < n_c; base += P) {
       if (rounds == budget) {
         st.start = base;
@@ -475,15 +702,123 @@ __device__ __forceinline__ void flush_counts(Counters* c, const WorkCount& wc) {
     atomicAdd(&c->check, wc.check);
     atomicAdd(&c->refine, wc.refine);
     atomicAdd(&c->useful, wc.useful);
+    if (wc.helper) atomicAdd(&c->helper, wc.helper);
+  }
+}
+
+// The uniform description of the item at queue position `it`.
+__device__ __forceinline__ ItemRef item_ref(const SweepArgs& a, int it, int* g_out) {
+  const int g = uniform(a.order[it]);
+  const int m = uniform(a.lam_model[g]);
+  const ModelDesc d = a.models[m];
+  ItemRef r;
+  r.N = uniform(d.n_layers);
+  r.n_c = uniform(d.n_c);
+  r.k64 = a.lam_k[g];
+  r.c64 = a.c64 + uniform(d.c_base);
+  r.c32 = a.c32 + uniform(d.c_base);
+  r.L64 = a.layers64 + uniform(d.layer_base);
+  r.L32 = a.layers32 + uniform(d.layer_base);
+  *g_out = g;
+  return r;
+}
+
+// A workgroup that finds the queue empty joins the shared sweeps still open:
+// wavefront 0 looks through the owners' slots (starting at its own, so that
+// joiners spread out) for the sweep with the fewest rounds in flight beyond
+// its owner's resolution, and the workgroup claims and evaluates rounds of it
+// until it runs more than kCoopWindow rounds ahead or the sweep has seen a
+// change.  It leaves when no shared sweep is open, or after kJoinIdle
+// searches that found nothing to join.
+template <int MODE, int G>
+__device__ void join_sweeps(const SweepArgs& a, SweepShared<G>& sh, WorkCount& wc) {
+  using T = typename std::conditional<MODE == kModeFP64, double, float>::type;
+  constexpr int P = 64 * G;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nb = gridDim.x;
+  int idle = 0;
+  for (;;) {
+    if (wave == 0) {
+      int best = -1;
+      bool open = false;
+      for (int k = 0; k < nb && best < 0; k += 64) {
+        int key = 0x7fffffff;  // (rounds in flight << 24) | item, for the helpable ones
+        bool op = false;
+        if (k + lane < nb) {
+          const int it = ld_agent(&a.coop_active[(int(blockIdx.x) + k + lane) % nb]);
+          if (it >= 0 && it < a.n_coop) {
+            CoopItem* ci = a.coop + it;
+            const int rounds = ld_agent(&ci->rounds);
+            const int next = ld_agent(&ci->next);
+            const int stop = ld_agent(&ci->stop);
+            const int res = ld_agent(&ci->resolved);
+            if (rounds > 0) {
+              op = true;
+              const int bound = stop >= rounds ? rounds : stop + 1;
+              if (next < bound && next - res < kCoopWindow) key = (max(next - res, 0) << 24) | it;
+            }
+          }
+        }
+        for (int off = 32; off > 0; off >>= 1) key = min(key, __shfl_xor(key, off, 64));
+        open = open || (__ballot(op) != 0ull);
+        if (key != 0x7fffffff) best = key & 0xffffff;
+      }
+      if (lane == 0) {
+        sh.coop[0] = best;
+        sh.coop[1] = open ? 1 : 0;
+      }
+    }
+    __syncthreads();
+    const int item = sh.coop[0];
+    const bool open = sh.coop[1] != 0;
+    __syncthreads();
+    if (item < 0) {
+      if (!open || ++idle > kJoinIdle) return;
+      __builtin_amdgcn_s_sleep(127);
+      continue;
+    }
+    idle = 0;
+    int g;
+    const ItemRef r = item_ref(a, item, &g);
+    CoopItem* ci = a.coop + item;
+    uint64_t* sum = a.coop_sum + size_t(item) * size_t(a.coop_stride);
+    for (;;) {
+      if (tid == 0) {
+        const int rd = atomicAdd(&ci->next, 1);
+        const int rounds = ld_agent(&ci->rounds);
+        const int stop = ld_agent(&ci->stop);
+        sh.coop[0] = rd;
+        sh.coop[1] = (rounds > 0 && rd < rounds && rd <= stop) ? 1 : 0;
+        sh.coop[2] = ld_agent(&ci->resolved);
+      }
+      __syncthreads();
+      const int rd = sh.coop[0];
+      const bool go = sh.coop[1] != 0;
+      const int res = sh.coop[2];
+      __syncthreads();
+      if (!go) break;
+      int s0, sl, sa = 0, pa = 0;
+      const int f = eval_round<T, G>(r, rd, sh, &s0, &sl, &sa, &pa);
+      const unsigned long long n = (unsigned long long)min(P, r.n_c - rd * P);
+      wc.sweep += n;
+      wc.helper += n;
+      if (tid == 0) {
+        st_agent(&sum[rd], pack_round(s0, sl, sa, pa, f));
+        if (f >= 0) atomicMin(&ci->stop, rd);
+      }
+      if (f >= 0 || rd + 1 - res >= kCoopWindow) break;
+    }
   }
 }
 
 // Batch launch: a persistent grid pulls items from the ordered queue and runs
-// each to completion.
+// each to completion; items at queue positions below n_coop run as shared
+// sweeps that workgroups with an empty queue join.
 template <int MODE, int G>
 __global__ __launch_bounds__(64 * G) void sweep_kernel(SweepArgs a) {
   __shared__ SweepShared<G> sh;
   WorkCount wc;
+  constexpr int P = 64 * G;
   for (;;) {
     if (threadIdx.x == 0) sh.item = (int)atomicAdd(&a.counters->queue_head, 1u);
     __syncthreads();
@@ -491,27 +826,34 @@ __global__ __launch_bounds__(64 * G) void sweep_kernel(SweepArgs a) {
     __syncthreads();
     if (it >= a.n_items) break;
 
-    const int g = uniform(a.order[it]);
-    const int m = uniform(a.lam_model[g]);
-    const ModelDesc d = a.models[m];
-    ItemRef r;
-    r.N = uniform(d.n_layers);
-    r.n_c = uniform(d.n_c);
-    r.k64 = a.lam_k[g];
-    r.c64 = a.c64 + uniform(d.c_base);
-    r.c32 = a.c32 + uniform(d.c_base);
-    r.L64 = a.layers64 + uniform(d.layer_base);
-    r.L32 = a.layers32 + uniform(d.layer_base);
+    int g;
+    const ItemRef r = item_ref(a, it, &g);
     const ItemOut o{a.out_ct + g, a.out_idx + g, a.out_status + g, a.out_cref ? a.out_cref + g : nullptr,
                     a.refine};
     if (!(r.k64 == r.k64)) {  // invalid model, grid or wavelength
       write_missing<G>(o, MASW_STATUS_INVALID);
       continue;
     }
+    CoopRef co{nullptr, nullptr, nullptr, it};
+    if (it < a.n_coop && (r.n_c + P - 1) / P <= a.coop_stride) {
+      co.ci = a.coop + it;
+      co.sum = a.coop_sum + size_t(it) * size_t(a.coop_stride);
+      co.active = a.coop_active + blockIdx.x;
+    }
     ItemState st = item_state_init();
-    run_item<MODE, G>(r, st, 0x7fffffff, sh, wc, o);
+    run_item<MODE, G>(r, st, 0x7fffffff, sh, wc, o, co, a.counters);
   }
+  if (a.n_coop > 0) join_sweeps<MODE, G>(a, sh, wc);
   flush_counts<G>(a.counters, wc);
+}
+
+// Initial state of the shared-sweep arrays.
+__global__ void coop_init_kernel(CoopInitArgs a) {
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  const size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  for (size_t i = t; i < size_t(a.n_coop); i += stride) a.coop[i] = CoopItem{0, 0x7fffffff, 0, 0};
+  for (size_t i = t; i < a.n_sum; i += stride) a.coop_sum[i] = 0ull;
+  for (size_t i = t; i < size_t(a.n_active); i += stride) a.coop_active[i] = -1;
 }
 
 // ------------------------------------------------------------- serving --
@@ -629,9 +971,9 @@ __global__ __launch_bounds__(64 * G) void tick_kernel(TickArgs a) {
       st.done = 1;
       done = true;
     } else if (sd.prec == MASW_PREC_SPLIT) {
-      done = run_item<kModeSplit, G>(r, st, budget, sh, wc, o);
+      done = run_item<kModeSplit, G>(r, st, budget, sh, wc, o, kNoCoop, a.counters);
     } else {
-      done = run_item<kModeFP64, G>(r, st, budget, sh, wc, o);
+      done = run_item<kModeFP64, G>(r, st, budget, sh, wc, o, kNoCoop, a.counters);
     }
     if (threadIdx.x == 0) {
       sd.state[j] = st;
@@ -745,6 +1087,13 @@ hipError_t launch_sweep(int mode, int G, int blocks, hipStream_t s, const SweepA
   if (!f) return hipErrorInvalidValue;
   void* args[] = {const_cast<SweepArgs*>(&a)};
   return hipLaunchKernel(f, dim3(blocks), dim3(64 * G), args, 0, s);
+}
+
+hipError_t launch_coop_init(const CoopInitArgs& a, hipStream_t s) {
+  const uint64_t n = std::max<uint64_t>(a.n_sum, uint64_t(std::max(a.n_coop, a.n_active)));
+  const int blocks = int(std::min<uint64_t>(1024, (n + 255) / 256));
+  hipLaunchKernelGGL(coop_init_kernel, dim3(std::max(blocks, 1)), dim3(256), 0, s, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_prep(const PrepArgs& a, int single_N, int single_W, hipStream_t s) {

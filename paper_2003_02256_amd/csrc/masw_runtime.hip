@@ -257,12 +257,38 @@ int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t fl
   }
   if (!b.ok()) return fail(MASW_ENOMEM, "workspace exceeds the HBM budget");
 
-  MASW_HIP(hipEventRecord(ctx->ev[0], s));
-  MASW_HIP(launch_prep(p, in.single_N, in.single_W, s));
-
   const int mode = prec == MASW_PREC_SPLIT ? 1 : 0;
   int blocks = 1;
   const int G = pick_waves_per_item(ctx, mode, in.n_lam, &blocks);
+
+  // Shared sweeps when items are few enough that the deepest ones decide the
+  // launch time: every item, with one summary word per round of its grid,
+  // if that fits in what is left of the budget.
+  CoopInitArgs ci{};
+  const int64_t stride = (int64_t(in.n_c) + 64 * G - 1) / (64 * G);
+  if (ctx->shared_sweeps && blocks > 1 && in.n_lam > 0 && in.n_lam <= 4 * int64_t(blocks)) {
+    const size_t save = b.off;
+    ci.n_coop = int32_t(in.n_lam);
+    ci.coop = b.take<CoopItem>(size_t(ci.n_coop));
+    ci.n_sum = uint64_t(ci.n_coop) * uint64_t(stride);
+    ci.coop_sum = b.take<uint64_t>(ci.n_sum);
+    ci.n_active = blocks;
+    ci.coop_active = b.take<int32_t>(size_t(blocks));
+    if (!b.ok()) {
+      b.off = save;
+      ci = CoopInitArgs{};
+    }
+  }
+
+  MASW_HIP(hipEventRecord(ctx->ev[0], s));
+  MASW_HIP(launch_prep(p, in.single_N, in.single_W, s));
+  if (ci.n_coop) MASW_HIP(launch_coop_init(ci, s));
+
+  sw.n_coop = ci.n_coop;
+  sw.coop_stride = int32_t(stride);
+  sw.coop = ci.coop;
+  sw.coop_sum = ci.coop_sum;
+  sw.coop_active = ci.coop_active;
   sw.models = p.models;
   sw.layers64 = p.layers64;
   sw.layers32 = p.layers32;
@@ -281,6 +307,7 @@ int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t fl
   ctx->last.n_lambda = uint64_t(in.n_lam);
   ctx->last.waves_per_item = G;
   ctx->last.workgroups = in.n_lam > 0 ? blocks : 0;
+  ctx->last.shared_items = ci.n_coop;
   ctx->stats_pending = true;
   ctx->last_stream = s;
 
@@ -361,6 +388,8 @@ int masw_create(int device, size_t hbm_budget_bytes, masw_ctx** out) {
     const int g = std::atoi(f);
     if (g == 1 || g == 2 || g == 4 || g == 8 || g == 16) ctx->forced_waves = g;
   }
+  if (const char* f = std::getenv("MASW_SHARED_SWEEPS")) ctx->shared_sweeps = std::atoi(f) != 0;
+
   *out = ctx;
   return MASW_OK;
 }
@@ -628,6 +657,8 @@ int masw_get_stats(masw_ctx* ctx, masw_stats* out) {
     ctx->last.sweep_evals = c.sweep;
     ctx->last.check_evals = c.check;
     ctx->last.refine_evals = c.refine;
+    ctx->last.helper_evals = c.helper;
+    ctx->last.shared_stalls = c.coop_stall;
     MASW_HIP(hipEventElapsedTime(&ctx->last.sweep_ms, ctx->ev[1], ctx->ev[2]));
     MASW_HIP(hipEventElapsedTime(&ctx->last.total_ms, ctx->ev[0], ctx->ev[2]));
     ctx->stats_pending = false;

@@ -274,6 +274,73 @@ def test_fine_scale_full_size(torch_dev, ctx, prec):
     print(f"fine-scale prec={prec}: stats {s}", flush=True)
 
 
+# ------------------------------------------------------------- shared sweeps --
+def _context_with_env(**env):
+    """A context created with tuning variables set (they are read at creation)."""
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update({k: str(v) for k, v in env.items()})
+    try:
+        return M.Context(0, 1 << 30)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+@pytest.mark.parametrize("prec", [M.MASW_PREC_FP64, M.MASW_PREC_SPLIT])
+def test_shared_sweeps_equal_unshared(torch_dev, ctx, prec):
+    # With 1000 items on 512 workgroups the deepest items run as shared
+    # sweeps that idle workgroups join; every output must be bitwise the same
+    # as when each item is swept by its own workgroup alone.
+    wl = WL.fine_scale_case()
+    m, lam, c = wl.models[0], wl.lambdas[0], wl.c_test
+    shared = dev_curve(torch_dev, ctx, c, lam, m, prec)
+    s = ctx.stats()
+    print(f"shared prec={prec}: {s}", flush=True)
+    assert s["shared_items"] == len(lam) and s["shared_stalls"] == 0
+    assert s["helper_evals"] > 0
+    plain_ctx = _context_with_env(MASW_SHARED_SWEEPS=0)
+    try:
+        plain = dev_curve(torch_dev, plain_ctx, c, lam, m, prec)
+        sp = plain_ctx.stats()
+    finally:
+        plain_ctx.close()
+    assert sp["shared_items"] == 0 and sp["helper_evals"] == 0
+    for x, y in zip(shared, plain):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_shared_sweeps_one_wavefront_per_item(torch_dev):
+    # G = 1: rounds of 64 velocities, up to ~700 rounds per item, so joining
+    # workgroups evaluate a large share of the rounds; picks must still equal
+    # the oracle's and the unshared run bitwise.
+    g = _golden("fine_scale.json")
+    wl = WL.fine_scale_case()
+    m, c = wl.models[0], wl.c_test
+    sel = np.arange(0, 1000, 4)
+    lam = wl.lambdas[0][sel]
+    runs = []
+    for shared in (1, 0):
+        cx = _context_with_env(MASW_WAVES_PER_ITEM=1, MASW_SHARED_SWEEPS=shared)
+        try:
+            for prec in (M.MASW_PREC_FP64, M.MASW_PREC_SPLIT):
+                runs.append(dev_curve(torch_dev, cx, c, lam, m, prec))
+                st = cx.stats()
+                print(f"G=1 shared={shared} prec={prec}: {st}", flush=True)
+                assert st["waves_per_item"] == 1 and st["shared_stalls"] == 0
+                assert (st["shared_items"] > 0) == bool(shared)
+        finally:
+            cx.close()
+    want = ([g["idx"][i] for i in sel], [g["status"][i] for i in sel], [float(g["c_ref"][i]) for i in sel])
+    compare("G=1 shared fp64", runs[0], *want, lam, c, m)
+    compare("G=1 shared split", runs[1], *want, lam, c, m)
+    for a, b in ((runs[0], runs[2]), (runs[1], runs[3])):
+        for x, y in zip(a, b):
+            np.testing.assert_array_equal(x, y)
+
+
 # ------------------------------------------------------------ batched launch --
 def test_batch_sample_and_split_vs_fp64(torch_dev, ctx):
     g = _golden("batch_sample.json")
