@@ -112,20 +112,24 @@ class DeviceJob:
 
 
 def time_path(job, ctx, prec, steps, warmup):
+    """Wall time per job over `steps` back-to-back jobs on the library's stream,
+    and the mean sweep-kernel and job device times of exactly those launches
+    (HIP events the library records around every launch)."""
     torch, M = job.torch, job.M
     for _ in range(warmup):
         job.run(ctx, prec)
     torch.cuda.synchronize()
-    sweep_ms, total_ms, stats = [], [], None
+    M.masw_get_timing(ctx, reset=True)         # drop the warm-up launches
     t0 = time.perf_counter()
     for _ in range(steps):
         job.run(ctx, prec)
-        stats = M.masw_get_stats(ctx)          # synchronises the stream: one job per step
-        sweep_ms.append(stats["sweep_ms"])
-        total_ms.append(stats["total_ms"])
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / steps
-    return wall, float(np.mean(sweep_ms)), float(np.mean(total_ms)), stats
+    tm = M.masw_get_timing(ctx, reset=True)
+    if tm["launches"] != steps:
+        raise RuntimeError(f"timed {tm['launches']} launches, expected {steps}")
+    stats = M.masw_get_stats(ctx)              # counters of the last job
+    return wall, tm["sweep_ms_sum"] / steps, tm["total_ms_sum"] / steps, stats
 
 
 # ------------------------------------------------------------------ serving --
@@ -385,11 +389,14 @@ def main():
     both = (idx64 == idx32) & (idx64 >= 0)
     root_rel = np.abs(r32[3][both] - r64[3][both]) / r64[3][both]
 
-    # algorithmic flops of one FP64 launch: performed evaluations x F(N)
+    # algorithmic flops of one FP64 launch: the evaluations the method needs
+    # (every grid point up to each pick, plus the refinement) x F(N); rounds
+    # evaluated past a pick, speculatively or to fill a round, are not counted
     n_lay = np.asarray(job.n_layers)[job.lam_model]
     nbar = float(np.average(n_lay, weights=np.where(idx64 >= 0, idx64 + 1, wl.c_test.shape[0])))
     performed64 = st64["sweep_evals"] + st64["check_evals"] + st64["refine_evals"]
-    flops64 = performed64 * flops_per_eval(nbar)
+    algorithmic64 = st64["useful_evals"] + st64["check_evals"] + st64["refine_evals"]
+    flops64 = algorithmic64 * flops_per_eval(nbar)
     achieved = flops64 / (sweep64 * 1e-3) / 1e12
     n_curves = len(wl.models)
     kname = f"sweep_kernel<FP64,G={st64['waves_per_item']}>"
@@ -414,6 +421,7 @@ def main():
         "wavelengths_per_s": wl.n_lambda_total / wall64,
         "useful_evals": useful,
         "performed_evals": performed64,
+        "algorithmic_evals": algorithmic64,
         "first_call_ms": first_call_ms,
         "device_ms_per_step": total64,
         "split": {

@@ -273,6 +273,21 @@ int masw_misfit(masw_ctx *ctx, int32_t n_models, const int32_t *lambda_off,
  * after the stream has been synchronised; this function synchronises). */
 int masw_get_stats(masw_ctx *ctx, masw_stats *out);
 
+/* Device time of the masw_dispersion_curve / masw_dispersion_batch calls
+ * made on ctx since the timing was last reset, from HIP events recorded on
+ * each call's stream (no synchronisation between calls is needed to time
+ * them).  Waits for those calls to finish.  With reset != 0 the sums start
+ * again from zero after being returned.  Calls on other contexts, sign maps
+ * and served requests are not counted. */
+typedef struct {
+    uint64_t launches;    /* calls timed                                        */
+    double sweep_ms_sum;  /* sum of their sweep-kernel durations (ms)           */
+    double total_ms_sum;  /* sum of their staging + ordering + sweep durations  */
+    float sweep_ms_min;   /* shortest and longest sweep-kernel duration (ms);   */
+    float sweep_ms_max;   /* 0 when launches == 0                               */
+} masw_timing;
+int masw_get_timing(masw_ctx *ctx, int reset, masw_timing *out);
+
 /* Static text for an error code. */
 const char *masw_strerror(int code);
 

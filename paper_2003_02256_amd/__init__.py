@@ -78,6 +78,15 @@ class masw_stats(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class masw_timing(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_uint64), ("sweep_ms_sum", ctypes.c_double),
+                ("total_ms_sum", ctypes.c_double), ("sweep_ms_min", ctypes.c_float),
+                ("sweep_ms_max", ctypes.c_float)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class masw_server_opts(ctypes.Structure):
     _fields_ = [("max_layers", ctypes.c_int32), ("max_lambda", ctypes.c_int32), ("max_grid", ctypes.c_int32),
                 ("rounds_per_tick", ctypes.c_int32), ("pool_bytes", ctypes.c_size_t)]
@@ -123,6 +132,7 @@ def library() -> ctypes.CDLL:
             "masw_sign_map": (ctypes.c_int, [vp, vp, i32, vp, i32, ctypes.POINTER(masw_model),
                                              ctypes.c_int, u32, vp, vp, vp]),
             "masw_get_stats": (ctypes.c_int, [vp, ctypes.POINTER(masw_stats)]),
+            "masw_get_timing": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(masw_timing)]),
             "masw_misfit": (ctypes.c_int, [vp, i32, vp, vp, vp, u32, vp, vp]),
             "masw_server_start": (ctypes.c_int, [vp, ctypes.POINTER(masw_server_opts)]),
             "masw_server_stop": (ctypes.c_int, [vp]),
@@ -278,6 +288,12 @@ def masw_get_stats(ctx) -> dict:
     s = masw_stats()
     _check(library().masw_get_stats(ctx, ctypes.byref(s)), "masw_get_stats")
     return s.as_dict()
+
+
+def masw_get_timing(ctx, reset: bool = False) -> dict:
+    t = masw_timing()
+    _check(library().masw_get_timing(ctx, 1 if reset else 0, ctypes.byref(t)), "masw_get_timing")
+    return t.as_dict()
 
 
 def masw_server_start(ctx, max_layers=0, max_lambda=0, max_grid=0, rounds_per_tick=0, pool_bytes=0) -> int:

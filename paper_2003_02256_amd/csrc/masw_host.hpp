@@ -15,8 +15,7 @@ namespace masw {
 int sweep_blocks_per_cu(int mode, int G);
 int tick_blocks_per_cu(int G);
 hipError_t launch_sweep(int mode, int G, int blocks, hipStream_t s, const SweepArgs& a);
-hipError_t launch_prep(const PrepArgs& a, int single_N, int single_W, hipStream_t s);
-hipError_t launch_coop_init(const CoopInitArgs& a, hipStream_t s);
+hipError_t launch_prep(const PrepArgs& a, const CoopInitArgs& ci, int single_N, int single_W, hipStream_t s);
 hipError_t launch_sign_map(bool fp32, const SignMapArgs& a, hipStream_t s);
 hipError_t launch_admit(const AdmitList* list_dev, int n, int32_t* slot_remaining, hipStream_t s);
 hipError_t launch_tick(int G, int blocks, hipStream_t s, const TickArgs& a);
@@ -54,10 +53,24 @@ struct masw_ctx {
   int blocks_per_cu[2][5] = {};   // [mode][log2 G], G = 1..16
   int forced_waves = 0;           // MASW_WAVES_PER_ITEM override (tuning)
   bool shared_sweeps = true;      // MASW_SHARED_SWEEPS=0 turns shared sweeps off (tuning)
+  int shared_window = 8;          // MASW_SHARED_WINDOW: joiners' look-ahead in rounds (tuning)
   std::mutex mu;
   masw_stats last = {};
   bool stats_pending = false;
   masw::Counters* counters = nullptr;  // arena offset 0
-  hipEvent_t ev[3] = {};          // start, sweep start, sweep end
+  // HIP events of the last kTimingSlots synchronous calls (start, sweep
+  // start, sweep end), so that back-to-back calls can be timed without a
+  // synchronisation per call; a slot is resolved into the running sums when
+  // it is reused or when the timing is read.
+  struct TimingSlot {
+    hipEvent_t ev[3] = {};
+    bool pending = false;
+    float sweep_ms = 0.f, total_ms = 0.f;
+  };
+  static constexpr int kTimingSlots = 64;
+  TimingSlot tslot[kTimingSlots];
+  int tslot_next = 0;
+  int tslot_last = -1;
+  masw_timing timing = {};
   masw::Server* server = nullptr; // serving loop, if started
 };

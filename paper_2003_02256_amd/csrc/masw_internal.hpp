@@ -23,6 +23,8 @@ constexpr int kNoSign = 0x7f;        // "no predecessor" marker in the sign scan
 constexpr int kNaNSign = 2;          // sign code of a NaN determinant
 constexpr int kBuckets = 256;        // work-order buckets
 constexpr double kRefineRel = 1e-9;  // refinement bracket width / c_hi
+constexpr int kPrepThreads = 256;    // threads per staging block
+constexpr int kLamBlock = 1024;      // wavelengths sorted by one staging block
 
 template <typename T>
 struct alignas(8 * sizeof(T)) LayerRec {
@@ -32,7 +34,9 @@ struct alignas(8 * sizeof(T)) LayerRec {
   T mh;   // mu / mu_ref
   T h;    // thickness (0 for the half-space record)
   T aux;   // half-space record: mu_ref (Pa); 0 otherwise
-  T pad1, pad2;
+  T zb;    // depth of the layer's bottom (m), for the work-order key of the
+           // batch staging; 0 in served requests, which are not reordered
+  T pad2;
 };
 using LayerRec64 = LayerRec<double>;
 using LayerRec32 = LayerRec<float>;
@@ -99,6 +103,7 @@ struct SweepArgs {
   CoopItem* coop;        // [n_coop]
   uint64_t* coop_sum;    // [n_coop * coop_stride] round summaries, 0 = not yet published
   int32_t* coop_active;  // [gridDim.x] item each workgroup owns in its shared sweep, or -1
+  int32_t coop_window;   // rounds a joining workgroup may run ahead of the owner's resolution
 };
 
 // Zero-state of the cooperative arrays (one launch before the sweep).
@@ -135,6 +140,7 @@ struct PrepArgs {
   int32_t* order;
   int32_t n_lam;
   Counters* counters;
+  uint32_t* grid_flags;  // [ceil(n_c / kPrepThreads)] 1 where a block of the grid failed its checks
 };
 
 // Where one item's search stands.  The batch kernels keep it in registers;

@@ -93,54 +93,55 @@ __global__ void zero_counters_kernel(Counters* c) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
 }
 
-// Grid checks (strictly increasing, finite, > 0) and the FP32 copy of the grid.
-__global__ void prep_grid_kernel(const double* __restrict__ c_in, int n_c, double* __restrict__ c64,
-                                 float* __restrict__ c32, Counters* counters) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_c) return;
-  const double c = c_in[i];
-  if (c64 != c_in) c64[i] = c;
-  c32[i] = float(c);
-  bool ok = (c > 0.0) && (c < __builtin_inf());
-  if (i + 1 < n_c) ok = ok && (c < c_in[i + 1]);
-  if (!ok) atomicOr(&counters->grid_bad, 1u);
-}
-
-// One thread per model: validation and the per-layer coefficient records.
-// With a.layer_off == nullptr the batch is a single model of
+// Validation and per-layer records of model m by one wavefront, one layer
+// per lane.  With a.layer_off == nullptr the batch is a single model of
 // single_N layers and single_W wavelengths.
-__global__ void prep_models_kernel(PrepArgs a, int single_N, int single_W) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= a.n_models) return;
+__device__ void build_model(const PrepArgs& a, int m, int single_N, int single_W) {
+  const int lane = threadIdx.x & 63;
   const int lo = a.layer_off ? a.layer_off[m] : 0;
   const int hi = a.layer_off ? a.layer_off[m + 1] : single_N;
   const int N = hi - lo;
   const int rec0 = lo + m;  // records and alpha/beta/rho entries of model m
-  bool ok = (N >= 0) && (N <= MASW_MAX_LAYERS) && (a.counters->grid_bad == 0u);
+  bool ok = (N >= 0) && (N <= MASW_MAX_LAYERS);
   if (ok) {
-    for (int j = 0; j <= N; ++j) {
+    bool lok = true;
+    for (int j = lane; j <= N; j += 64) {
       const double al = a.alpha[rec0 + j], be = a.beta[rec0 + j], rh = a.rho[rec0 + j];
       const bool finite = (al < __builtin_inf()) && (rh < __builtin_inf());
-      ok = ok && finite && (be > 0.0) && (al > be) && (rh > 0.0);
+      lok = lok && finite && (be > 0.0) && (al > be) && (rh > 0.0);
       if (j < N) {
         const double h = a.h[lo + j];
-        ok = ok && (h > 0.0) && (h < __builtin_inf());
+        lok = lok && (h > 0.0) && (h < __builtin_inf());
       }
     }
+    ok = __ballot(!lok) == 0ull;
   }
-  ModelDesc d;
-  d.n_layers = ok ? N : 0;
-  d.layer_base = rec0;
-  d.c_base = 0;
-  d.n_c = a.n_c;
-  d.lam_base = a.lambda_off ? a.lambda_off[m] : 0;
-  d.n_lam = a.lambda_off ? (a.lambda_off[m + 1] - a.lambda_off[m]) : single_W;
-  d.valid = ok ? 1 : 0;
-  d.pad = 0;
-  a.models[m] = d;
+  if (lane == 0) {
+    ModelDesc d;
+    d.n_layers = ok ? N : 0;
+    d.layer_base = rec0;
+    d.c_base = 0;
+    d.n_c = a.n_c;
+    d.lam_base = a.lambda_off ? a.lambda_off[m] : 0;
+    d.n_lam = a.lambda_off ? (a.lambda_off[m + 1] - a.lambda_off[m]) : single_W;
+    d.valid = ok ? 1 : 0;
+    d.pad = 0;
+    a.models[m] = d;
+  }
   if (!ok) return;
   const double mu_ref = a.rho[rec0 + N] * a.beta[rec0 + N] * a.beta[rec0 + N];
-  for (int j = 0; j <= N; ++j) {
+  double z0 = 0.0;  // depth of the top of this 64-layer chunk
+  for (int j0 = 0; j0 <= N; j0 += 64) {
+    const int j = j0 + lane;
+    // depth of each layer's bottom: inclusive prefix sum over the chunk
+    double z = (j < N) ? a.h[lo + j] : 0.0;
+    for (int off = 1; off < 64; off <<= 1) {
+      const double up = __shfl_up(z, off, 64);
+      if (lane >= off) z += up;
+    }
+    z += z0;
+    z0 = __shfl(z, 63, 64);
+    if (j > N) continue;
     const double al = a.alpha[rec0 + j], be = a.beta[rec0 + j], rh = a.rho[rec0 + j];
     LayerRec64 r;
     r.ia2 = 1.0 / (al * al);
@@ -149,18 +150,60 @@ __global__ void prep_models_kernel(PrepArgs a, int single_N, int single_W) {
     r.mh = rh * be * be / mu_ref;
     r.h = (j < N) ? a.h[lo + j] : 0.0;
     r.aux = (j == N) ? mu_ref : 0.0;
-    r.pad1 = r.pad2 = 0.0;
+    r.zb = z;
+    r.pad2 = 0.0;
     a.layers64[rec0 + j] = r;
-    LayerRec32 s;
-    s.ia2 = float(r.ia2);
-    s.ib2 = float(r.ib2);
-    s.rh = float(r.rh);
-    s.mh = float(r.mh);
-    s.h = float(r.h);
-    s.aux = float(mu_ref);
-    s.pad1 = s.pad2 = 0.0f;
-    a.layers32[rec0 + j] = s;
+    LayerRec32 q;
+    q.ia2 = float(r.ia2);
+    q.ib2 = float(r.ib2);
+    q.rh = float(r.rh);
+    q.mh = float(r.mh);
+    q.h = float(r.h);
+    q.aux = float(mu_ref);
+    q.zb = float(z);
+    q.pad2 = 0.0f;
+    a.layers32[rec0 + j] = q;
   }
+}
+
+// The front of the staging, one launch:
+//  * blocks [0, nb_grid): grid checks (finite, > 0, strictly increasing) and
+//    the FP32 copy; each block writes its own flag, so nothing needs clearing
+//    first;
+//  * the next nb_models blocks: validation and layer records, one wavefront
+//    per model;
+//  * the last nb_clear blocks: the counters and the shared-sweep state.
+__global__ __launch_bounds__(kPrepThreads) void prep_front_kernel(PrepArgs a, CoopInitArgs ci, int nb_grid,
+                                                                  int nb_models, int nb_clear, int single_N,
+                                                                  int single_W) {
+  const int b = blockIdx.x;
+  if (b < nb_grid) {
+    const int i = b * kPrepThreads + int(threadIdx.x);
+    int bad = 0;
+    if (i < a.n_c) {
+      const double c = a.c_in[i];
+      if (a.c64 != a.c_in) a.c64[i] = c;
+      a.c32[i] = float(c);
+      bool ok = (c > 0.0) && (c < __builtin_inf());
+      if (i + 1 < a.n_c) ok = ok && (c < a.c_in[i + 1]);
+      bad = ok ? 0 : 1;
+    }
+    bad = __syncthreads_or(bad);
+    if (threadIdx.x == 0) a.grid_flags[b] = bad ? 1u : 0u;
+    return;
+  }
+  if (b < nb_grid + nb_models) {
+    const int m = (b - nb_grid) * (kPrepThreads / 64) + int(threadIdx.x >> 6);
+    if (m < a.n_models) build_model(a, m, single_N, single_W);
+    return;
+  }
+  const size_t t = size_t(b - nb_grid - nb_models) * kPrepThreads + threadIdx.x;
+  const size_t stride = size_t(nb_clear) * kPrepThreads;
+  uint32_t* cw = reinterpret_cast<uint32_t*>(a.counters);
+  for (size_t i = t; i < sizeof(Counters) / sizeof(uint32_t); i += stride) cw[i] = 0u;
+  for (size_t i = t; i < size_t(ci.n_coop); i += stride) ci.coop[i] = CoopItem{0, 0x7fffffff, 0, 0};
+  for (size_t i = t; i < ci.n_sum; i += stride) ci.coop_sum[i] = 0ull;
+  for (size_t i = t; i < size_t(ci.n_active); i += stride) ci.coop_active[i] = -1;
 }
 
 // One thread per wavelength: k, its model, and the work-order key.  The
@@ -168,12 +211,28 @@ __global__ void prep_models_kernel(PrepArgs a, int single_N, int single_W) {
 // Rayleigh wave samples roughly the top third of a wavelength); the cost is
 // that depth times N+1.  Longer wavelengths see faster material and search
 // deeper (Section 3.2's observation behind the modular partition), so the key
-// orders them first.
-__global__ void prep_lambda_kernel(PrepArgs a) {
+// orders them first.  The key only orders the work, so the grid index is
+// interpolated between kBuckets grid samples staged in LDS.  A launch of one
+// block (at most kLamBlock wavelengths) also finishes the counting sort in
+// LDS; otherwise the histogram goes to the counters for order_scan_kernel and
+// order_scatter_kernel.
+__global__ __launch_bounds__(kLamBlock) void prep_lambda_kernel(PrepArgs a, int nb_grid) {
   __shared__ uint32_t s_hist[kBuckets];
-  for (int i = threadIdx.x; i < kBuckets; i += blockDim.x) s_hist[i] = 0u;
-  __syncthreads();
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ uint32_t s_scan[kBuckets];
+  __shared__ double s_c[kBuckets];
+  const int t = threadIdx.x;
+  const int ns = min(kBuckets, a.n_c);  // grid samples: c at index (s * (n_c - 1)) / (ns - 1)
+  for (int i = t; i < kBuckets; i += blockDim.x) {
+    s_hist[i] = 0u;
+    if (i < ns) s_c[i] = a.c64[ns > 1 ? int((int64_t(i) * (a.n_c - 1)) / (ns - 1)) : 0];
+  }
+  int bad = 0;
+  for (int i = t; i < nb_grid; i += blockDim.x) bad |= int(a.grid_flags[i]);
+  bad = __syncthreads_or(bad);
+  if (blockIdx.x == 0 && t == 0) a.counters->grid_bad = bad ? 1u : 0u;
+  const int g = blockIdx.x * blockDim.x + t;
+  int key = 0;
+  uint32_t rank = 0;
   if (g < a.n_lam) {
     int m = 0;
     if (a.lambda_off) {  // last m with lambda_off[m] <= g
@@ -186,36 +245,54 @@ __global__ void prep_lambda_kernel(PrepArgs a) {
     }
     const double lam = a.lambda[g];
     const ModelDesc d = a.models[m];
-    const bool ok = d.valid && (lam > 0.0) && (lam < __builtin_inf());
+    const bool ok = !bad && d.valid && (lam > 0.0) && (lam < __builtin_inf());
     a.lam_model[g] = m;
     a.lam_k[g] = ok ? (2.0 * M_PI / lam) : __builtin_nan("");
-    int key = kBuckets - 1;
+    key = kBuckets - 1;
     if (ok) {
       const LayerRec64* L = a.layers64 + d.layer_base;
-      double z = 0.0, beta = 0.0;
-      int j = 0;
-      for (; j < d.n_layers; ++j) {
-        z += L[j].h;
-        if (z >= lam * (1.0 / 3.0)) break;
-      }
-      beta = 1.0 / ::sqrt(L[j].ib2);
-      const double c_est = 0.9 * beta;
-      int lo = 0, hi = d.n_c;  // first index with c >= c_est
-      const double* c = a.c64 + d.c_base;
+      int lo = 0, hi = d.n_layers;  // first layer whose bottom reaches lambda / 3
+      const double z3 = lam * (1.0 / 3.0);
       while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        if (c[mid] < c_est) lo = mid + 1; else hi = mid;
+        if (L[mid].zb < z3) lo = mid + 1; else hi = mid;
       }
-      const double cost = double(d.n_layers + 1) * double(lo + 64);
-      const int b = min(kBuckets - 1, max(0, int(8.0 * ::log2(cost))));
-      key = kBuckets - 1 - b;
+      const double c_est = 0.9 / ::sqrt(L[lo].ib2);
+      double pos = 0.0;  // interpolated grid index of c_est
+      if (ns > 1 && c_est > s_c[0]) {
+        int sl = 0, sh = ns - 1;  // last sample below c_est
+        while (sh - sl > 1) {
+          const int mid = (sl + sh) >> 1;
+          if (s_c[mid] < c_est) sl = mid; else sh = mid;
+        }
+        const double step = double(a.n_c - 1) / double(ns - 1);
+        const double span = s_c[sl + 1] - s_c[sl];
+        const double f = span > 0.0 ? min(1.0, (c_est - s_c[sl]) / span) : 0.0;
+        pos = (double(sl) + f) * step;
+      }
+      const double cost = double(d.n_layers + 1) * (pos + 64.0);
+      const int bk = min(kBuckets - 1, max(0, int(8.0 * ::log2(cost))));
+      key = kBuckets - 1 - bk;
     }
     a.lam_bucket[g] = uint8_t(key);
-    atomicAdd(&s_hist[key], 1u);
+    rank = atomicAdd(&s_hist[key], 1u);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < kBuckets; i += blockDim.x)
-    if (s_hist[i]) atomicAdd(&a.counters->hist[i], s_hist[i]);
+  if (gridDim.x > 1) {
+    for (int i = t; i < kBuckets; i += blockDim.x)
+      if (s_hist[i]) atomicAdd(&a.counters->hist[i], s_hist[i]);
+    return;
+  }
+  // one block: exclusive prefix sum of the histogram, then the scatter
+  if (t < kBuckets) s_scan[t] = s_hist[t];
+  __syncthreads();
+  for (int off = 1; off < kBuckets; off <<= 1) {
+    const uint32_t v = (t < kBuckets && t >= off) ? s_scan[t - off] : 0u;
+    __syncthreads();
+    if (t < kBuckets) s_scan[t] += v;
+    __syncthreads();
+  }
+  if (g < a.n_lam) a.order[s_scan[key] - s_hist[key] + rank] = g;
 }
 
 // Exclusive prefix sum of the histogram, in place (one block of kBuckets).
@@ -318,7 +395,6 @@ __device__ __forceinline__ void st_agent(uint64_t* p, uint64_t v) {
 
 constexpr int kCoopStall = -2;          // a shared sweep gave up waiting (never expected)
 constexpr int kCoopMaxPolls = 1 << 20;  // polls of one round summary (~2 s) before giving up
-constexpr int kCoopWindow = 16;         // rounds a joining workgroup may run ahead of the resolution
 constexpr int kJoinIdle = 32;           // fruitless searches before a joining workgroup leaves
 
 // Summary of one evaluated round, published as a single 64-bit word so that
@@ -727,7 +803,7 @@ __device__ __forceinline__ ItemRef item_ref(const SweepArgs& a, int it, int* g_o
 // wavefront 0 looks through the owners' slots (starting at its own, so that
 // joiners spread out) for the sweep with the fewest rounds in flight beyond
 // its owner's resolution, and the workgroup claims and evaluates rounds of it
-// until it runs more than kCoopWindow rounds ahead or the sweep has seen a
+// until it runs more than coop_window rounds ahead or the sweep has seen a
 // change.  It leaves when no shared sweep is open, or after kJoinIdle
 // searches that found nothing to join.
 template <int MODE, int G>
@@ -755,7 +831,7 @@ __device__ void join_sweeps(const SweepArgs& a, SweepShared<G>& sh, WorkCount& w
             if (rounds > 0) {
               op = true;
               const int bound = stop >= rounds ? rounds : stop + 1;
-              if (next < bound && next - res < kCoopWindow) key = (max(next - res, 0) << 24) | it;
+              if (next < bound && next - res < a.coop_window) key = (max(next - res, 0) << 24) | it;
             }
           }
         }
@@ -806,7 +882,7 @@ __device__ void join_sweeps(const SweepArgs& a, SweepShared<G>& sh, WorkCount& w
         st_agent(&sum[rd], pack_round(s0, sl, sa, pa, f));
         if (f >= 0) atomicMin(&ci->stop, rd);
       }
-      if (f >= 0 || rd + 1 - res >= kCoopWindow) break;
+      if (f >= 0 || rd + 1 - res >= a.coop_window) break;
     }
   }
 }
@@ -847,14 +923,6 @@ __global__ __launch_bounds__(64 * G) void sweep_kernel(SweepArgs a) {
   flush_counts<G>(a.counters, wc);
 }
 
-// Initial state of the shared-sweep arrays.
-__global__ void coop_init_kernel(CoopInitArgs a) {
-  const size_t stride = size_t(gridDim.x) * blockDim.x;
-  const size_t t = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  for (size_t i = t; i < size_t(a.n_coop); i += stride) a.coop[i] = CoopItem{0, 0x7fffffff, 0, 0};
-  for (size_t i = t; i < a.n_sum; i += stride) a.coop_sum[i] = 0ull;
-  for (size_t i = t; i < size_t(a.n_active); i += stride) a.coop_active[i] = -1;
-}
 
 // ------------------------------------------------------------- serving --
 // Precompute of newly admitted requests: one workgroup per request validates
@@ -905,7 +973,7 @@ __global__ __launch_bounds__(256) void admit_kernel(const AdmitList* __restrict_
       r.mh = rh * be * be / mu_ref;
       r.h = (j < N) ? h[j] : 0.0;
       r.aux = (j == N) ? mu_ref : 0.0;
-      r.pad1 = r.pad2 = 0.0;
+      r.zb = r.pad2 = 0.0;
       d.L64[j] = r;
       LayerRec32 q;
       q.ia2 = float(r.ia2);
@@ -914,7 +982,7 @@ __global__ __launch_bounds__(256) void admit_kernel(const AdmitList* __restrict_
       q.mh = float(r.mh);
       q.h = float(r.h);
       q.aux = float(mu_ref);
-      q.pad1 = q.pad2 = 0.0f;
+      q.zb = q.pad2 = 0.0f;
       d.L32[j] = q;
     }
   }
@@ -1089,24 +1157,22 @@ hipError_t launch_sweep(int mode, int G, int blocks, hipStream_t s, const SweepA
   return hipLaunchKernel(f, dim3(blocks), dim3(64 * G), args, 0, s);
 }
 
-hipError_t launch_coop_init(const CoopInitArgs& a, hipStream_t s) {
-  const uint64_t n = std::max<uint64_t>(a.n_sum, uint64_t(std::max(a.n_coop, a.n_active)));
-  const int blocks = int(std::min<uint64_t>(1024, (n + 255) / 256));
-  hipLaunchKernelGGL(coop_init_kernel, dim3(std::max(blocks, 1)), dim3(256), 0, s, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_prep(const PrepArgs& a, int single_N, int single_W, hipStream_t s) {
-  hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(256), 0, s, a.counters);
-  hipLaunchKernelGGL(prep_grid_kernel, dim3((a.n_c + 255) / 256), dim3(256), 0, s, a.c_in, a.n_c,
-                     a.c64, a.c32, a.counters);
-  hipLaunchKernelGGL(prep_models_kernel, dim3((a.n_models + 127) / 128), dim3(128), 0, s, a,
-                     single_N, single_W);
+hipError_t launch_prep(const PrepArgs& a, const CoopInitArgs& ci, int single_N, int single_W, hipStream_t s) {
+  const int nb_grid = (a.n_c + kPrepThreads - 1) / kPrepThreads;
+  const int nb_models = (a.n_models + kPrepThreads / 64 - 1) / (kPrepThreads / 64);
+  const uint64_t n_clear = std::max<uint64_t>(ci.n_sum, uint64_t(std::max(ci.n_coop, ci.n_active)));
+  const int nb_clear = int(std::max<uint64_t>(1, std::min<uint64_t>(512, (n_clear + kPrepThreads - 1) / kPrepThreads)));
+  hipLaunchKernelGGL(prep_front_kernel, dim3(nb_grid + nb_models + nb_clear), dim3(kPrepThreads), 0, s, a, ci,
+                     nb_grid, nb_models, nb_clear, single_N, single_W);
   if (a.n_lam > 0) {
-    const int nb = (a.n_lam + 255) / 256;
-    hipLaunchKernelGGL(prep_lambda_kernel, dim3(nb), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(kBuckets), 0, s, a.counters);
-    hipLaunchKernelGGL(order_scatter_kernel, dim3(nb), dim3(256), 0, s, a);
+    if (a.n_lam <= kLamBlock) {
+      hipLaunchKernelGGL(prep_lambda_kernel, dim3(1), dim3(kLamBlock), 0, s, a, nb_grid);
+    } else {
+      const int nb = (a.n_lam + kPrepThreads - 1) / kPrepThreads;
+      hipLaunchKernelGGL(prep_lambda_kernel, dim3(nb), dim3(kPrepThreads), 0, s, a, nb_grid);
+      hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(kBuckets), 0, s, a.counters);
+      hipLaunchKernelGGL(order_scatter_kernel, dim3(nb), dim3(kPrepThreads), 0, s, a);
+    }
   }
   return hipGetLastError();
 }

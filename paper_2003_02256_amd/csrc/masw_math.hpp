@@ -199,7 +199,7 @@ __device__ __forceinline__ LayerRec<T> load_rec(const LayerRec<T>* L, int j) {
   r.mh = p->mh;
   r.h = p->h;
   r.aux = p->aux;
-  r.pad1 = r.pad2 = T(0);
+  r.zb = r.pad2 = T(0);
   return r;
 }
 

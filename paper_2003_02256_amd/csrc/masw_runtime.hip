@@ -115,11 +115,15 @@ struct Inputs {
   int64_t n_lam = 0;           // sum W_m
 };
 
+// Blocks of the grid check, one flag each.
+size_t grid_blocks(int64_t n_c) { return size_t((n_c + kPrepThreads - 1) / kPrepThreads); }
+
 // Total device bytes of one call's workspace.
 size_t workspace_bytes(const Inputs& in, bool stage_inputs, bool stage_outputs) {
   Bump b{nullptr, ~size_t(0), 0};
   const size_t R = size_t(in.n_layers_total + in.n_models);
   b.take<Counters>(1);
+  b.take<uint32_t>(grid_blocks(in.n_c));
   b.take<ModelDesc>(size_t(in.n_models));
   b.take<LayerRec64>(R);
   b.take<LayerRec32>(R);
@@ -173,6 +177,22 @@ int pick_waves_per_item(masw_ctx* ctx, int mode, int64_t n_items, int* blocks) {
   return G;
 }
 
+// Waits for a timed call's last event and adds its durations to the sums.
+hipError_t resolve_timing(masw_ctx* ctx, masw_ctx::TimingSlot& T) {
+  hipError_t e = hipEventSynchronize(T.ev[2]);
+  if (e == hipSuccess) e = hipEventElapsedTime(&T.sweep_ms, T.ev[1], T.ev[2]);
+  if (e == hipSuccess) e = hipEventElapsedTime(&T.total_ms, T.ev[0], T.ev[2]);
+  if (e != hipSuccess) return e;
+  T.pending = false;
+  masw_timing& t = ctx->timing;
+  t.sweep_ms_min = t.launches ? std::min(t.sweep_ms_min, T.sweep_ms) : T.sweep_ms;
+  t.sweep_ms_max = t.launches ? std::max(t.sweep_ms_max, T.sweep_ms) : T.sweep_ms;
+  t.sweep_ms_sum += T.sweep_ms;
+  t.total_ms_sum += T.total_ms;
+  ++t.launches;
+  return hipSuccess;
+}
+
 // Shared body of the curve and batch calls.
 int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t flags, void* stream,
                const masw_outputs* out) {
@@ -189,6 +209,7 @@ int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t fl
   const size_t R = size_t(in.n_layers_total + in.n_models);
   PrepArgs p{};
   p.counters = b.take<Counters>(1);
+  p.grid_flags = b.take<uint32_t>(grid_blocks(in.n_c));
   p.models = b.take<ModelDesc>(size_t(in.n_models));
   p.layers64 = b.take<LayerRec64>(R);
   p.layers32 = b.take<LayerRec32>(R);
@@ -280,15 +301,19 @@ int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t fl
     }
   }
 
-  MASW_HIP(hipEventRecord(ctx->ev[0], s));
-  MASW_HIP(launch_prep(p, in.single_N, in.single_W, s));
-  if (ci.n_coop) MASW_HIP(launch_coop_init(ci, s));
+  const int ts = ctx->tslot_next;
+  masw_ctx::TimingSlot& T = ctx->tslot[ts];
+  if (T.pending) MASW_HIP(resolve_timing(ctx, T));
+  ctx->tslot_next = (ts + 1) % masw_ctx::kTimingSlots;
+  MASW_HIP(hipEventRecord(T.ev[0], s));
+  MASW_HIP(launch_prep(p, ci, in.single_N, in.single_W, s));
 
   sw.n_coop = ci.n_coop;
   sw.coop_stride = int32_t(stride);
   sw.coop = ci.coop;
   sw.coop_sum = ci.coop_sum;
   sw.coop_active = ci.coop_active;
+  sw.coop_window = ctx->shared_window;
   sw.models = p.models;
   sw.layers64 = p.layers64;
   sw.layers32 = p.layers32;
@@ -300,9 +325,11 @@ int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t fl
   sw.n_items = int32_t(in.n_lam);
   sw.refine = (flags & MASW_NO_REFINE) ? 0 : 1;
   sw.counters = p.counters;
-  MASW_HIP(hipEventRecord(ctx->ev[1], s));
+  MASW_HIP(hipEventRecord(T.ev[1], s));
   if (in.n_lam > 0) MASW_HIP(launch_sweep(mode, G, blocks, s, sw));
-  MASW_HIP(hipEventRecord(ctx->ev[2], s));
+  MASW_HIP(hipEventRecord(T.ev[2], s));
+  T.pending = true;
+  ctx->tslot_last = ts;
   ctx->last = masw_stats{};
   ctx->last.n_lambda = uint64_t(in.n_lam);
   ctx->last.waves_per_item = G;
@@ -366,8 +393,9 @@ int masw_create(int device, size_t hbm_budget_bytes, masw_ctx** out) {
   auto cleanup = [&](int code, const std::string& msg) {
     if (ctx->arena) (void)hipFree(ctx->arena);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
-    for (auto& e : ctx->ev)
-      if (e) (void)hipEventDestroy(e);
+    for (auto& t : ctx->tslot)
+      for (auto& e : t.ev)
+        if (e) (void)hipEventDestroy(e);
     delete ctx;
     return fail(code, msg);
   };
@@ -376,8 +404,9 @@ int masw_create(int device, size_t hbm_budget_bytes, masw_ctx** out) {
     return cleanup(MASW_EDEVICE, "cannot query compute units");
   if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess)
     return cleanup(MASW_EDEVICE, "hipStreamCreate failed");
-  for (auto& e : ctx->ev)
-    if (hipEventCreate(&e) != hipSuccess) return cleanup(MASW_EDEVICE, "hipEventCreate failed");
+  for (auto& t : ctx->tslot)
+    for (auto& e : t.ev)
+      if (hipEventCreate(&e) != hipSuccess) return cleanup(MASW_EDEVICE, "hipEventCreate failed");
   if (hipMalloc(&ctx->arena, budget) != hipSuccess) return cleanup(MASW_ENOMEM, "cannot allocate the HBM budget");
   ctx->arena_size = budget;
   ctx->sync_size = budget;
@@ -389,6 +418,10 @@ int masw_create(int device, size_t hbm_budget_bytes, masw_ctx** out) {
     if (g == 1 || g == 2 || g == 4 || g == 8 || g == 16) ctx->forced_waves = g;
   }
   if (const char* f = std::getenv("MASW_SHARED_SWEEPS")) ctx->shared_sweeps = std::atoi(f) != 0;
+  if (const char* f = std::getenv("MASW_SHARED_WINDOW")) {
+    const int w = std::atoi(f);
+    if (w >= 1 && w <= 1024) ctx->shared_window = w;
+  }
 
   *out = ctx;
   return MASW_OK;
@@ -405,8 +438,9 @@ void masw_destroy(masw_ctx* ctx) {
   if (ctx->last_stream && ctx->last_stream != ctx->stream) (void)hipStreamSynchronize(ctx->last_stream);
   if (ctx->arena) (void)hipFree(ctx->arena);
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
-  for (auto& e : ctx->ev)
-    if (e) (void)hipEventDestroy(e);
+  for (auto& t : ctx->tslot)
+    for (auto& e : t.ev)
+      if (e) (void)hipEventDestroy(e);
   delete ctx;
 }
 
@@ -540,6 +574,7 @@ int masw_sign_map(masw_ctx* ctx, const double* c_test, int32_t n_c, const double
   const size_t R = size_t(model->n_layers + 1);
   PrepArgs p{};
   p.counters = b.take<Counters>(1);
+  p.grid_flags = b.take<uint32_t>(grid_blocks(n_c));
   p.models = b.take<ModelDesc>(1);
   p.layers64 = b.take<LayerRec64>(R);
   p.layers32 = b.take<LayerRec32>(R);
@@ -573,7 +608,7 @@ int masw_sign_map(masw_ctx* ctx, const double* c_test, int32_t n_c, const double
     log_dst = log_abs_det ? b.take<double>(cells) : nullptr;
   }
   if (!b.ok()) return fail(MASW_ENOMEM, "sign map exceeds the HBM budget");
-  MASW_HIP(launch_prep(p, model->n_layers, n_lambda, s));
+  MASW_HIP(launch_prep(p, CoopInitArgs{}, model->n_layers, n_lambda, s));
   SignMapArgs a{};
   a.models = p.models;
   a.layers64 = p.layers64;
@@ -659,11 +694,29 @@ int masw_get_stats(masw_ctx* ctx, masw_stats* out) {
     ctx->last.refine_evals = c.refine;
     ctx->last.helper_evals = c.helper;
     ctx->last.shared_stalls = c.coop_stall;
-    MASW_HIP(hipEventElapsedTime(&ctx->last.sweep_ms, ctx->ev[1], ctx->ev[2]));
-    MASW_HIP(hipEventElapsedTime(&ctx->last.total_ms, ctx->ev[0], ctx->ev[2]));
+    if (ctx->tslot_last >= 0) {
+      masw_ctx::TimingSlot& T = ctx->tslot[ctx->tslot_last];
+      if (T.pending) MASW_HIP(resolve_timing(ctx, T));
+      ctx->last.sweep_ms = T.sweep_ms;
+      ctx->last.total_ms = T.total_ms;
+    }
     ctx->stats_pending = false;
   }
   *out = ctx->last;
+  return MASW_OK;
+}
+
+int masw_get_timing(masw_ctx* ctx, int reset, masw_timing* out) {
+  if (!ctx || !out) return fail(MASW_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  MASW_HIP(hipSetDevice(ctx->device));
+  // resolve in call order: the oldest pending slot follows the newest one
+  for (int k = 0; k < masw_ctx::kTimingSlots; ++k) {
+    masw_ctx::TimingSlot& T = ctx->tslot[(ctx->tslot_next + k) % masw_ctx::kTimingSlots];
+    if (T.pending) MASW_HIP(resolve_timing(ctx, T));
+  }
+  *out = ctx->timing;
+  if (reset) ctx->timing = masw_timing{};
   return MASW_OK;
 }
 

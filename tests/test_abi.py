@@ -170,3 +170,9 @@ def test_misfit_validates_on_host(lib):
     with pytest.raises(M.MaswError) as e:
         M.masw_misfit(None, off, ct, ct, 0, None, out)
     assert e.value.code == M.MASW_EINVAL and "ctx" in str(e.value)
+
+
+def test_timing_rejects_null_arguments(lib):
+    out = M.masw_timing()
+    assert lib.masw_get_timing(None, 0, ctypes.byref(out)) == M.MASW_EINVAL
+    assert lib.masw_get_timing(None, 1, None) == M.MASW_EINVAL

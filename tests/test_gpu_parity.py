@@ -341,6 +341,32 @@ def test_shared_sweeps_one_wavefront_per_item(torch_dev):
             np.testing.assert_array_equal(x, y)
 
 
+def test_timing_of_back_to_back_calls(torch_dev, ctx):
+    # calls issued without synchronising in between are each timed by the
+    # library's events; outputs of the last call are those of a single call
+    wl = WL.two_layer_case()
+    m, lam, c = wl.models[0], wl.lambdas[0], wl.c_test
+    want = dev_curve(torch_dev, ctx, c, lam, m, M.MASW_PREC_FP64)
+    torch, dev = torch_dev
+    t = lambda x: torch.as_tensor(np.ascontiguousarray(x, np.float64), device=dev)
+    args = (t(c), t(lam), t(m.h), t(m.alpha), t(m.beta), t(m.rho))
+    W = len(lam)
+    out = (torch.empty(W, dtype=torch.float64, device=dev), torch.empty(W, dtype=torch.int32, device=dev),
+           torch.empty(W, dtype=torch.int32, device=dev), torch.empty(W, dtype=torch.float64, device=dev))
+    M.masw_get_timing(ctx.ctx, reset=True)
+    n = 100  # more than the library's 64 event slots
+    for _ in range(n):
+        M.masw_dispersion_curve(ctx.ctx, *args, M.MASW_PREC_FP64, 0, None, *out)
+    tm = M.masw_get_timing(ctx.ctx, reset=True)
+    assert tm["launches"] == n
+    assert 0.0 < tm["sweep_ms_min"] <= tm["sweep_ms_max"]
+    assert tm["sweep_ms_min"] * n <= tm["sweep_ms_sum"] + 1e-9 <= tm["total_ms_sum"] + 1e-6
+    assert M.masw_get_timing(ctx.ctx)["launches"] == 0
+    torch.cuda.synchronize()
+    for x, y in zip(want, (o.cpu().numpy() for o in out)):
+        np.testing.assert_array_equal(x, y)
+
+
 # ------------------------------------------------------------ batched launch --
 def test_batch_sample_and_split_vs_fp64(torch_dev, ctx):
     g = _golden("batch_sample.json")
