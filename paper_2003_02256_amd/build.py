@@ -14,6 +14,9 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libmasw.so")
+# test-only probe of the device special functions (tests/test_gpu_special.py)
+PROBE_SRC = os.path.join(ROOT, "tests", "special_probe.hip")
+PROBE_LIB = os.path.join(ROOT, "tests", "libspecial_probe.so")
 
 SOURCES = ["masw_kernels.hip", "masw_runtime.hip", "masw_server.hip"]
 HEADERS = ["masw_internal.hpp", "masw_math.hpp", "masw_special.hpp", "masw_host.hpp"]
@@ -34,18 +37,23 @@ def hipcc() -> str:
     return exe
 
 
-def build(verbose: bool = False) -> str:
-    """Always recompiles; returns the library path."""
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC,
-           *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp]
+def _compile(sources, out, verbose):
+    tmp = out + ".tmp"
+    cmd = [hipcc(), *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, *sources, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libmasw.so")
-    os.replace(tmp, LIB)
+        raise RuntimeError(f"hipcc failed building {os.path.basename(out)}")
+    os.replace(tmp, out)
+
+
+def build(verbose: bool = False) -> str:
+    """Always recompiles the library and the test probe; returns the library path."""
+    _compile([os.path.join(CSRC, s) for s in SOURCES], LIB, verbose)
+    if os.path.exists(PROBE_SRC):
+        _compile([PROBE_SRC], PROBE_LIB, verbose)
     return LIB
 
 

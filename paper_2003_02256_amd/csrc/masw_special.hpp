@@ -2,22 +2,28 @@
 // kernels use, in FP64 and FP32.  Written from the mathematics:
 //
 //  * reciprocal and reciprocal square root: the hardware estimate
-//    (v_rcp / v_rsq; about 2^-23 relative in FP64) refined by Newton's
-//    iteration, two steps in FP64 (error squares per step), none in FP32
-//    (the FP32 estimates are already within 1 ulp);
+//    (v_rcp / v_rsq, within 2^-21 relative in FP64) and, in FP64, one
+//    third-order correction: with e the estimate's residual (1 - d r, or
+//    1 - x y^2), 1/d = r (1 + e + e^2 + ...) and 1/sqrt(x) = y (1 + e/2 +
+//    3e^2/8 + ...), so keeping the terms through e^2 leaves an error of order
+//    e^3, far below the rounding; FP32 uses the estimates as they are (within
+//    1 ulp);
 //  * expm1(-y), y >= 0: Cody and Waite's additive range reduction
 //    y = n ln2 + r with ln2 split in two parts (the high part has enough
-//    trailing zero bits that n * hi is exact), |r| <= ln2/2, the Taylor
-//    series of expm1 at 0, and expm1(-y) = 2^-n expm1(-r) + (2^-n - 1);
+//    trailing zero bits that n * hi is exact), |r| <= ln2/2, a polynomial for
+//    expm1 on that interval, and expm1(-y) = 2^-n expm1(-r) + (2^-n - 1);
 //  * sin^2(x) and sin(x) cos(x), x >= 0: Cody and Waite reduction by pi/2
-//    (pi/2 in three parts), |r| <= pi/4, the Taylor series of sin and cos,
-//    and the quadrant parity (sin^2 x = sin^2 r or cos^2 r,
+//    (pi/2 in three parts), |r| <= pi/4, polynomials for sin and cos on that
+//    interval, and the quadrant parity (sin^2 x = sin^2 r or cos^2 r,
 //    sin x cos x = +- sin r cos r).
 //
-// Taylor degrees are the smallest whose first omitted term is below half an
-// ulp over the reduced range: expm1 to z^13/13! (FP64) or z^8/8! (FP32); sin
-// to r^15/15! (r^9/9!); cos to r^16/16! (r^10/10!).  Every step is an explicit
-// fused multiply-add, so the rounding is fixed by the source.
+// The polynomials keep the first Taylor terms exact (expm1 z = z + z^2/2 +
+// z^3 w(z), sin r = r + r^3 q(r^2), cos r = 1 - r^2/2 + r^4 v(r^2)) and
+// take w, q and v from Chebyshev interpolation on the reduced interval
+// (near-minimax), of the lowest degree that keeps the evaluated result
+// within about 2 units of the last place: w of degree 9 (FP64) or 3 (FP32),
+// q and v of degree 5 (FP64) or 2 (FP32).  Every step is an explicit fused
+// multiply-add, so the rounding is fixed by the source.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -43,13 +49,21 @@ constexpr float kPio2_2F = -4.371138828673793e-08f;
 constexpr float kPio2_3F = -1.7151245100058819e-15f;
 constexpr float kTwoOverPiF = 0.63661977f;
 
-// 1/k!, correctly rounded
-constexpr double kInvFact[19] = {
-    1.0, 1.0, 0.5, 0.16666666666666666, 0.041666666666666664, 0.008333333333333333,
-    0.001388888888888889, 0.0001984126984126984, 2.48015873015873e-05, 2.7557319223985893e-06,
-    2.755731922398589e-07, 2.505210838544172e-08, 2.08767569878681e-09, 1.6059043836821613e-10,
-    1.1470745597729725e-11, 7.647163731819816e-13, 4.779477332387385e-14, 2.8114572543455206e-15,
-    1.5619206968586225e-16};
+// Polynomial coefficients, highest degree first (Chebyshev interpolants of
+// w(z) = (expm1 z - z - z^2/2)/z^3 on |z| <= ln2/2, q(u) = (sin r/r - 1)/u
+// and v(u) = ((cos r - 1)/u + 1/2)/u on 0 <= u = r^2 <= (pi/4)^2).
+constexpr double kExpm1W[10] = {2.091122972975856e-09, 2.5100375832561234e-08, 2.755728298405588e-07,
+                                2.7557268480310024e-06, 2.4801587317135164e-05, 0.00019841269863040545,
+                                0.0013888888888886554, 0.008333333333330065, 0.041666666666666664,
+                                0.16666666666666669};
+constexpr double kSinQ[6] = {1.5918129294866608e-10, -2.5051131845003624e-08, 2.755731610255244e-06,
+                             -0.00019841269836758574, 0.008333333333330948, -0.16666666666666666};
+constexpr double kCosV[6] = {-1.1382632425521717e-11, 2.08761462684032e-09, -2.7557317271729793e-07,
+                             2.480158729876569e-05, -0.0013888888888887398, 0.041666666666666664};
+constexpr float kExpm1WF[4] = {0.001391871366649866f, 0.008357199840247631f, 0.04166662320494652f,
+                               0.16666631400585175f};
+constexpr float kSinQF[3] = {-0.00019587890710681677f, 0.008332747966051102f, -0.166666641831398f};
+constexpr float kCosVF[3] = {2.454794230288826e-05f, -0.001388830249197781f, 0.0416666641831398f};
 
 // ------------------------------------------------------------------- FP64 --
 // One Horner step p * x + c as a three-operand v_fma_f64.  FP64 coefficients
@@ -63,21 +77,16 @@ __device__ __forceinline__ double horner(double p, double x, double c) {
 }
 
 __device__ __forceinline__ double rcp(double d) {
-  double r = __builtin_amdgcn_rcp(d);
-  double e = __builtin_fma(-d, r, 1.0);
-  r = __builtin_fma(r, e, r);
-  e = __builtin_fma(-d, r, 1.0);
-  return __builtin_fma(r, e, r);
+  const double r = __builtin_amdgcn_rcp(d);
+  const double e = __builtin_fma(-d, r, 1.0);           // 1 - d r
+  return __builtin_fma(r, __builtin_fma(e, e, e), r);   // r (1 + e + e^2)
 }
 
 // 1/sqrt(x) for a positive normal x.
 __device__ __forceinline__ double rsqrt(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  const double hx = 0.5 * x;
-  double e = __builtin_fma(-hx * y, y, 0.5);  // (1 - x y^2) / 2
-  y = __builtin_fma(y, e, y);
-  e = __builtin_fma(-hx * y, y, 0.5);
-  return __builtin_fma(y, e, y);
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = __builtin_fma(-(x * y), y, 1.0);     // 1 - x y^2
+  return __builtin_fma(y * e, __builtin_fma(e, 0.375, 0.5), y);  // y (1 + e/2 + 3e^2/8)
 }
 
 // expm1(-y) for finite y >= 0.
@@ -86,9 +95,10 @@ __device__ __forceinline__ double expm1_neg(double y) {
   double r = __builtin_fma(-n, kLn2Hi, y);
   r = __builtin_fma(-n, kLn2Lo, r);
   const double z = -r;
-  double p = kInvFact[13];
+  double w = kExpm1W[0];
 #pragma unroll
-  for (int k = 12; k >= 1; --k) p = __builtin_fma(p, z, kInvFact[k]);
+  for (int k = 1; k < 10; ++k) w = __builtin_fma(w, z, kExpm1W[k]);
+  const double p = __builtin_fma(__builtin_fma(w, z, 0.5), z, 1.0);
   const double em = z * p;                          // expm1(-r)
   const double s = __builtin_ldexp(1.0, -int(n));   // 2^-n (0 once it underflows)
   return __builtin_fma(s, em, s - 1.0);
@@ -101,24 +111,14 @@ __device__ __forceinline__ void sin2_sincos(double x, double* s2, double* sc) {
   r = __builtin_fma(-k, kPio2_2, r);
   r = __builtin_fma(-k, kPio2_3, r);
   const double r2 = r * r;
-  double ps = -kInvFact[15];
-  ps = horner(ps, r2, kInvFact[13]);
-  ps = horner(ps, r2, -kInvFact[11]);
-  ps = horner(ps, r2, kInvFact[9]);
-  ps = horner(ps, r2, -kInvFact[7]);
-  ps = horner(ps, r2, kInvFact[5]);
-  ps = horner(ps, r2, -kInvFact[3]);
-  ps = __builtin_fma(ps, r2, 1.0);
-  const double sn = r * ps;                         // sin r
-  double pc = kInvFact[16];
-  pc = horner(pc, r2, -kInvFact[14]);
-  pc = horner(pc, r2, kInvFact[12]);
-  pc = horner(pc, r2, -kInvFact[10]);
-  pc = horner(pc, r2, kInvFact[8]);
-  pc = horner(pc, r2, -kInvFact[6]);
-  pc = horner(pc, r2, kInvFact[4]);
-  pc = __builtin_fma(pc, r2, -0.5);
-  const double cs = __builtin_fma(pc, r2, 1.0);     // cos r
+  double q = kSinQ[0];
+#pragma unroll
+  for (int j = 1; j < 6; ++j) q = horner(q, r2, kSinQ[j]);
+  const double sn = __builtin_fma(r * r2, q, r);    // sin r
+  double v = kCosV[0];
+#pragma unroll
+  for (int j = 1; j < 6; ++j) v = horner(v, r2, kCosV[j]);
+  const double cs = __builtin_fma(__builtin_fma(v, r2, -0.5), r2, 1.0);  // cos r
   const bool odd = (int(k) & 1) != 0;
   *s2 = odd ? cs * cs : sn * sn;
   *sc = odd ? -(sn * cs) : sn * cs;
@@ -134,9 +134,10 @@ __device__ __forceinline__ float expm1_neg(float y) {
   float r = __builtin_fmaf(-n, kLn2HiF, y);
   r = __builtin_fmaf(-n, kLn2LoF, r);
   const float z = -r;
-  float p = float(kInvFact[8]);
+  float w = kExpm1WF[0];
 #pragma unroll
-  for (int k = 7; k >= 1; --k) p = __builtin_fmaf(p, z, float(kInvFact[k]));
+  for (int k = 1; k < 4; ++k) w = __builtin_fmaf(w, z, kExpm1WF[k]);
+  const float p = __builtin_fmaf(__builtin_fmaf(w, z, 0.5f), z, 1.0f);
   const float em = z * p;
   const float s = __builtin_ldexpf(1.0f, -int(n));
   return __builtin_fmaf(s, em, s - 1.0f);
@@ -148,18 +149,14 @@ __device__ __forceinline__ void sin2_sincos(float x, float* s2, float* sc) {
   r = __builtin_fmaf(-k, kPio2_2F, r);
   r = __builtin_fmaf(-k, kPio2_3F, r);
   const float r2 = r * r;
-  float ps = float(kInvFact[9]);
-  ps = __builtin_fmaf(ps, r2, -float(kInvFact[7]));
-  ps = __builtin_fmaf(ps, r2, float(kInvFact[5]));
-  ps = __builtin_fmaf(ps, r2, -float(kInvFact[3]));
-  ps = __builtin_fmaf(ps, r2, 1.0f);
-  const float sn = r * ps;
-  float pc = -float(kInvFact[10]);
-  pc = __builtin_fmaf(pc, r2, float(kInvFact[8]));
-  pc = __builtin_fmaf(pc, r2, -float(kInvFact[6]));
-  pc = __builtin_fmaf(pc, r2, float(kInvFact[4]));
-  pc = __builtin_fmaf(pc, r2, -float(kInvFact[2]));
-  const float cs = __builtin_fmaf(pc, r2, 1.0f);
+  float q = kSinQF[0];
+  q = __builtin_fmaf(q, r2, kSinQF[1]);
+  q = __builtin_fmaf(q, r2, kSinQF[2]);
+  const float sn = __builtin_fmaf(r * r2, q, r);
+  float v = kCosVF[0];
+  v = __builtin_fmaf(v, r2, kCosVF[1]);
+  v = __builtin_fmaf(v, r2, kCosVF[2]);
+  const float cs = __builtin_fmaf(__builtin_fmaf(v, r2, -0.5f), r2, 1.0f);
   const bool odd = (int(k) & 1) != 0;
   *s2 = odd ? cs * cs : sn * sn;
   *sc = odd ? -(sn * cs) : sn * cs;
