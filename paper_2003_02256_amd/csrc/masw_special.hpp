@@ -91,16 +91,16 @@ __device__ __forceinline__ double rsqrt(double x) {
 
 // expm1(-y) for finite y >= 0.
 __device__ __forceinline__ double expm1_neg(double y) {
-  const double n = __builtin_rint(y * kInvLn2);
-  double r = __builtin_fma(-n, kLn2Hi, y);
-  r = __builtin_fma(-n, kLn2Lo, r);
+  const double m = __builtin_rint(y * -kInvLn2);  // -n
+  double r = __builtin_fma(m, kLn2Hi, y);
+  r = __builtin_fma(m, kLn2Lo, r);
   const double z = -r;
   double w = kExpm1W[0];
 #pragma unroll
   for (int k = 1; k < 10; ++k) w = __builtin_fma(w, z, kExpm1W[k]);
   const double p = __builtin_fma(__builtin_fma(w, z, 0.5), z, 1.0);
   const double em = z * p;                          // expm1(-r)
-  const double s = __builtin_ldexp(1.0, -int(n));   // 2^-n (0 once it underflows)
+  const double s = __builtin_ldexp(1.0, int(m));    // 2^-n (0 once it underflows)
   return __builtin_fma(s, em, s - 1.0);
 }
 
@@ -130,16 +130,16 @@ __device__ __forceinline__ float rcp(float d) { return __builtin_amdgcn_rcpf(d);
 __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
 
 __device__ __forceinline__ float expm1_neg(float y) {
-  const float n = __builtin_rintf(y * kInvLn2F);
-  float r = __builtin_fmaf(-n, kLn2HiF, y);
-  r = __builtin_fmaf(-n, kLn2LoF, r);
+  const float m = __builtin_rintf(y * -kInvLn2F);  // -n
+  float r = __builtin_fmaf(m, kLn2HiF, y);
+  r = __builtin_fmaf(m, kLn2LoF, r);
   const float z = -r;
   float w = kExpm1WF[0];
 #pragma unroll
   for (int k = 1; k < 4; ++k) w = __builtin_fmaf(w, z, kExpm1WF[k]);
   const float p = __builtin_fmaf(__builtin_fmaf(w, z, 0.5f), z, 1.0f);
   const float em = z * p;
-  const float s = __builtin_ldexpf(1.0f, -int(n));
+  const float s = __builtin_ldexpf(1.0f, int(m));
   return __builtin_fmaf(s, em, s - 1.0f);
 }
 
