@@ -18,7 +18,9 @@
  * memory before it returns and keeps no caller pointer after the call,
  * except that with MASW_DEVICE_PTRS the kernels may still run on `stream`
  * after the call returns (synchronise `stream` before reading outputs or
- * reusing inputs).  A NULL `stream` means the context's own stream.
+ * reusing inputs).  `stream` is a hipStream_t; NULL is the device's default
+ * (null) stream, as everywhere in HIP, so device-pointer work issued on the
+ * default stream by the caller is ordered with the library's.
  *
  * Errors.  Every function returning int returns MASW_OK (0) or a negative
  * MASW_E* code; nothing aborts or throws across the ABI.  Argument checks

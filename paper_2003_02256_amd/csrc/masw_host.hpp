@@ -44,8 +44,8 @@ void server_destroy(Server* s);
 
 struct masw_ctx {
   int device = -1;
-  hipStream_t stream = nullptr;   // the context's own stream (default priority)
-  hipStream_t last_stream = nullptr;
+  hipStream_t last_stream = nullptr;  // stream of the last synchronous call (may be the null stream)
+  bool last_valid = false;
   char* arena = nullptr;
   size_t arena_size = 0;          // whole HBM budget
   size_t sync_size = 0;           // front part used by the synchronous calls

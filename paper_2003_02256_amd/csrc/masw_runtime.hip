@@ -79,7 +79,7 @@ constexpr size_t kAlign = 256;
 // other than the previous call's first waits for that stream, so the previous
 // call's kernels are done with the memory.
 hipError_t claim_arena(masw_ctx* ctx, hipStream_t s) {
-  if (ctx->last_stream && ctx->last_stream != s) return hipStreamSynchronize(ctx->last_stream);
+  if (ctx->last_valid && ctx->last_stream != s) return hipStreamSynchronize(ctx->last_stream);
   return hipSuccess;
 }
 
@@ -197,7 +197,7 @@ hipError_t resolve_timing(masw_ctx* ctx, masw_ctx::TimingSlot& T) {
 int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t flags, void* stream,
                const masw_outputs* out) {
   const bool dev = (flags & MASW_DEVICE_PTRS) != 0;
-  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : ctx->stream;
+  hipStream_t s = static_cast<hipStream_t>(stream);  // NULL: the default stream
   const size_t need = workspace_bytes(in, !dev, !dev);
   if (need > ctx->sync_size)
     return fail(MASW_ENOMEM, "request needs " + std::to_string(need) + " B of device memory, budget is " +
@@ -337,6 +337,7 @@ int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t fl
   ctx->last.shared_items = ci.n_coop;
   ctx->stats_pending = true;
   ctx->last_stream = s;
+  ctx->last_valid = true;
 
   if (!dev) {
     const size_t W = size_t(in.n_lam);
@@ -392,7 +393,6 @@ int masw_create(int device, size_t hbm_budget_bytes, masw_ctx** out) {
   ctx->device = device;
   auto cleanup = [&](int code, const std::string& msg) {
     if (ctx->arena) (void)hipFree(ctx->arena);
-    if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
     for (auto& t : ctx->tslot)
       for (auto& e : t.ev)
         if (e) (void)hipEventDestroy(e);
@@ -402,8 +402,6 @@ int masw_create(int device, size_t hbm_budget_bytes, masw_ctx** out) {
   if (hipSetDevice(device) != hipSuccess) return cleanup(MASW_EDEVICE, "hipSetDevice failed");
   if (hipDeviceGetAttribute(&ctx->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
     return cleanup(MASW_EDEVICE, "cannot query compute units");
-  if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess)
-    return cleanup(MASW_EDEVICE, "hipStreamCreate failed");
   for (auto& t : ctx->tslot)
     for (auto& e : t.ev)
       if (hipEventCreate(&e) != hipSuccess) return cleanup(MASW_EDEVICE, "hipEventCreate failed");
@@ -434,10 +432,8 @@ void masw_destroy(masw_ctx* ctx) {
     ctx->server = nullptr;
   }
   (void)hipSetDevice(ctx->device);
-  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-  if (ctx->last_stream && ctx->last_stream != ctx->stream) (void)hipStreamSynchronize(ctx->last_stream);
+  if (ctx->last_valid) (void)hipStreamSynchronize(ctx->last_stream);
   if (ctx->arena) (void)hipFree(ctx->arena);
-  if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
   for (auto& t : ctx->tslot)
     for (auto& e : t.ev)
       if (e) (void)hipEventDestroy(e);
@@ -497,7 +493,7 @@ int masw_dispersion_batch(masw_ctx* ctx, const double* c_test, int32_t n_c, cons
   if (dev) {
     if ((rc = check_common(ctx, prec, flags))) return rc;
     MASW_HIP(hipSetDevice(ctx->device));
-    hipStream_t s = stream ? static_cast<hipStream_t>(stream) : ctx->stream;
+    hipStream_t s = static_cast<hipStream_t>(stream);  // NULL: the default stream
     MASW_HIP(hipMemcpyAsync(loff.data(), batch->layer_off, sizeof(int32_t) * loff.size(), hipMemcpyDeviceToHost, s));
     MASW_HIP(hipMemcpyAsync(woff.data(), batch->lambda_off, sizeof(int32_t) * woff.size(), hipMemcpyDeviceToHost, s));
     MASW_HIP(hipStreamSynchronize(s));
@@ -556,7 +552,7 @@ int masw_sign_map(masw_ctx* ctx, const double* c_test, int32_t n_c, const double
   if (n_lambda > 0 && !sigma) return fail(MASW_EINVAL, "sigma: null pointer");
   if ((rc = check_common(ctx, prec, flags))) return rc;
   std::lock_guard<std::mutex> lock(ctx->mu);
-  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : ctx->stream;
+  hipStream_t s = static_cast<hipStream_t>(stream);  // NULL: the default stream
   Inputs in;
   in.n_models = 1;
   in.single_N = model->n_layers;
@@ -623,6 +619,7 @@ int masw_sign_map(masw_ctx* ctx, const double* c_test, int32_t n_c, const double
   ctx->stats_pending = false;
   ctx->last = masw_stats{};
   ctx->last_stream = s;
+  ctx->last_valid = true;
   if (!dev) {
     if (cells) {
       MASW_HIP(hipMemcpyAsync(sigma, sig_dst, cells, hipMemcpyDeviceToHost, s));
@@ -652,11 +649,12 @@ int masw_misfit(masw_ctx* ctx, int32_t n_models, const int32_t* lambda_off, cons
   if (n_models == 0) return MASW_OK;
   std::lock_guard<std::mutex> lock(ctx->mu);
   MASW_HIP(hipSetDevice(ctx->device));
-  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : ctx->stream;
+  hipStream_t s = static_cast<hipStream_t>(stream);  // NULL: the default stream
   if (dev) {
     // reads and writes only caller memory: no arena claim
     MASW_HIP(launch_misfit(n_models, lambda_off, C_t, C_e, misfit, s));
     ctx->last_stream = s;
+    ctx->last_valid = true;
     return MASW_OK;
   }
   const size_t W = size_t(off[n_models]);
@@ -677,6 +675,7 @@ int masw_misfit(masw_ctx* ctx, int32_t n_models, const int32_t* lambda_off, cons
   MASW_HIP(hipMemcpyAsync(misfit, d_out, sizeof(double) * n_models, hipMemcpyDeviceToHost, s));
   MASW_HIP(hipStreamSynchronize(s));
   ctx->last_stream = s;
+  ctx->last_valid = true;
   return MASW_OK;
 }
 
@@ -685,7 +684,7 @@ int masw_get_stats(masw_ctx* ctx, masw_stats* out) {
   std::lock_guard<std::mutex> lock(ctx->mu);
   if (ctx->stats_pending) {
     MASW_HIP(hipSetDevice(ctx->device));
-    if (ctx->last_stream) MASW_HIP(hipStreamSynchronize(ctx->last_stream));
+    if (ctx->last_valid) MASW_HIP(hipStreamSynchronize(ctx->last_stream));
     Counters c;
     MASW_HIP(hipMemcpy(&c, ctx->counters, sizeof(Counters), hipMemcpyDeviceToHost));
     ctx->last.useful_evals = c.useful;

@@ -354,8 +354,7 @@ int masw_server_start(masw_ctx* ctx, const masw_server_opts* opts) {
   if (region + (size_t(16) << 20) > ctx->arena_size)
     return fail(MASW_ENOMEM, "serving pool leaves less than 16 MiB of the budget for synchronous calls");
   MASW_HIP(hipSetDevice(ctx->device));
-  MASW_HIP(hipStreamSynchronize(ctx->stream));
-  if (ctx->last_stream) MASW_HIP(hipStreamSynchronize(ctx->last_stream));  // no call still uses the tail
+  if (ctx->last_valid) MASW_HIP(hipStreamSynchronize(ctx->last_stream));  // no call still uses the tail
 
   Server* s = new Server();
   s->ctx = ctx;

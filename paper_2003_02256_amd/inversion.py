@@ -1,0 +1,171 @@
+"""Random-walk Metropolis inversion over the batched curve and misfit calls.
+
+The method needs many dispersion curves: an inversion compares the curves of
+many candidate models with the experimental one (Section 2.1; Algorithm 2
+gives the misfit of one model), and quantifying uncertainty needs more of
+them still.  This client runs a population of chains.  At every step each
+chain proposes a perturbed model.  All proposals go through one batched
+dispersion-curve launch and one misfit launch on the device
+(`masw_dispersion_batch`, `masw_misfit`), and only the misfits come back to
+the host.  Each chain then accepts its proposal with the Metropolis rule for
+the target density exp(-misfit / temperature).
+
+The chain logic (`perturb`, `metropolis_accept`, `run_chains`) is plain host
+code; `DeviceEvaluator` is the only part that touches the GPU, and any
+callable that maps a list of models to their misfits can stand in for it.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Callable, List, Sequence
+
+import numpy as np
+
+from . import (MASW_NO_REFINE, MASW_PREC_SPLIT, flatten_models, masw_dispersion_batch, masw_misfit)
+
+
+@dataclass
+class LayeredModel:
+    """N finite layers over a half-space (h: [N]; alpha, beta, rho: [N+1])."""
+
+    h: np.ndarray
+    alpha: np.ndarray
+    beta: np.ndarray
+    rho: np.ndarray
+
+    @property
+    def n_layers(self) -> int:
+        return int(self.h.shape[0])
+
+    def copy(self) -> "LayeredModel":
+        return LayeredModel(self.h.copy(), self.alpha.copy(), self.beta.copy(), self.rho.copy())
+
+
+def perturb(rng: np.random.Generator, m, step: float) -> LayeredModel:
+    """Proposal: every beta_j and h_j times (1 + step N(0, 1)), each layer
+    keeping its alpha/beta ratio (its Poisson ratio) and its density.  Draw
+    order: beta[N+1], then h[N]."""
+    ratio = np.asarray(m.alpha, np.float64) / np.asarray(m.beta, np.float64)
+    beta = np.asarray(m.beta, np.float64) * (1.0 + step * rng.standard_normal(len(m.beta)))
+    h = np.asarray(m.h, np.float64) * (1.0 + step * rng.standard_normal(len(m.h)))
+    beta = np.maximum(beta, 1.0)
+    h = np.maximum(h, 1e-3)
+    return LayeredModel(h, ratio * beta, beta, np.asarray(m.rho, np.float64).copy())
+
+
+def metropolis_accept(rng: np.random.Generator, current: np.ndarray, proposed: np.ndarray,
+                      temperature: float) -> np.ndarray:
+    """Accept where log u < -(proposed - current) / temperature, u ~ U(0, 1):
+    always when the misfit does not grow; never when the proposal's misfit
+    is NaN (a curve with no sign change).  One uniform per chain."""
+    u = rng.uniform(size=current.shape[0])
+    with np.errstate(invalid="ignore", over="ignore"):
+        delta = (proposed - current) / temperature
+        ok = np.isfinite(proposed) & ((delta <= 0.0) | (np.log(np.maximum(u, 1e-300)) < -delta))
+        # a chain stuck on a NaN misfit moves to any finite proposal
+        ok |= ~np.isfinite(current) & np.isfinite(proposed)
+    return ok
+
+
+@dataclass
+class ChainResult:
+    best_models: List[LayeredModel]
+    best_misfit: np.ndarray          # [chains]
+    final_misfit: np.ndarray         # [chains]
+    start_misfit: np.ndarray         # [chains]
+    accepted: np.ndarray             # [chains] accepted proposals
+    iterations: int
+    trace: np.ndarray = field(repr=False, default=None)  # [iterations + 1, chains] current misfit
+
+    @property
+    def acceptance_rate(self) -> float:
+        return float(self.accepted.sum()) / float(max(1, self.accepted.size * self.iterations))
+
+
+def run_chains(evaluate: Callable[[Sequence], np.ndarray], start: Sequence, iterations: int,
+               step: float = 0.02, temperature: float = 0.01, seed: int = 0) -> ChainResult:
+    """Advance len(start) chains `iterations` steps.  `evaluate(models)`
+    returns the misfit of each model (NaN allowed).  Draw order per step:
+    every chain's proposal (perturb) in chain order, then one uniform per
+    chain (metropolis_accept)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cur = [LayeredModel(np.asarray(m.h, np.float64).copy(), np.asarray(m.alpha, np.float64).copy(),
+                        np.asarray(m.beta, np.float64).copy(), np.asarray(m.rho, np.float64).copy())
+           for m in start]
+    mis = np.asarray(evaluate(cur), np.float64).copy()
+    best = [m.copy() for m in cur]
+    best_mis = mis.copy()
+    accepted = np.zeros(len(cur), np.int64)
+    trace = np.empty((iterations + 1, len(cur)))
+    trace[0] = mis
+    start_mis = mis.copy()
+    for it in range(iterations):
+        prop = [perturb(rng, m, step) for m in cur]
+        pm = np.asarray(evaluate(prop), np.float64)
+        ok = metropolis_accept(rng, mis, pm, temperature)
+        for c in np.nonzero(ok)[0]:
+            cur[c] = prop[c]
+            mis[c] = pm[c]
+            accepted[c] += 1
+            if not (best_mis[c] <= pm[c]):  # also replaces a NaN best
+                best[c] = prop[c].copy()
+                best_mis[c] = pm[c]
+        trace[it + 1] = mis
+    return ChainResult(best, best_mis, mis.copy(), start_mis, accepted, iterations, trace)
+
+
+class DeviceEvaluator:
+    """Misfits of many models against one experimental curve on the GPU.
+
+    All models share the test-velocity grid and the wavelengths of the
+    experimental curve C_e.  One call flattens the models, runs the batched
+    sweep with device-resident outputs (C_t only: the misfit uses the grid
+    velocity of each pick, so the root refinement is skipped), reduces the
+    misfits on the device and copies back only the misfits."""
+
+    def __init__(self, ctx, c_test, lambdas, C_e, prec: int = MASW_PREC_SPLIT, device: str = "cuda:0"):
+        import torch
+
+        self.torch = torch
+        self.ctx = ctx
+        self.dev = torch.device(device)
+        self.prec = prec
+        self.lam = np.ascontiguousarray(lambdas, np.float64)
+        self.C_e = np.ascontiguousarray(C_e, np.float64)
+        if self.C_e.shape != self.lam.shape:
+            raise ValueError("C_e and lambdas must have the same length")
+        self.c = torch.as_tensor(np.ascontiguousarray(c_test, np.float64), device=self.dev)
+        self._ce_dev = {}  # chains -> tiled C_e on the device
+        self.models_evaluated = 0
+
+    def __call__(self, models: Sequence) -> np.ndarray:
+        torch, dev = self.torch, self.dev
+        n = len(models)
+        arrs = flatten_models(models, [self.lam] * n)
+        d = [torch.as_tensor(x, device=dev) for x in arrs]
+        W = int(arrs[-1].shape[0])
+        f64, i32 = torch.float64, torch.int32
+        ct = torch.empty(W, dtype=f64, device=dev)
+        idx = torch.empty(W, dtype=i32, device=dev)
+        st = torch.empty(W, dtype=i32, device=dev)
+        masw_dispersion_batch(self.ctx, self.c, *d, self.prec, MASW_NO_REFINE, None, ct, idx, st, None)
+        if n not in self._ce_dev:
+            self._ce_dev[n] = torch.as_tensor(np.tile(self.C_e, n), device=dev)
+        mis = torch.empty(n, dtype=f64, device=dev)
+        masw_misfit(self.ctx, d[5], ct, self._ce_dev[n], 0, None, mis)
+        self.models_evaluated += n
+        return mis.cpu().numpy()
+
+
+def synthetic_curve(C_t: np.ndarray, rel_noise: float, seed: int = 0) -> np.ndarray:
+    """An experimental curve stand-in: a model's C_t times (1 + rel_noise N(0, 1))."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.asarray(C_t, np.float64) * (1.0 + rel_noise * rng.standard_normal(len(C_t)))
+
+
+def misfit_scale(C_e: np.ndarray, dc: float) -> float:
+    """The misfit of an error of one grid step dc at every wavelength,
+    mean(dc / C_e): a natural unit for the temperature."""
+    C_e = np.asarray(C_e, np.float64)
+    return float(np.mean(dc / C_e)) if C_e.size else math.nan

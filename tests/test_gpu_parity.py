@@ -367,6 +367,32 @@ def test_timing_of_back_to_back_calls(torch_dev, ctx):
         np.testing.assert_array_equal(x, y)
 
 
+def test_default_stream_orders_device_calls(torch_dev, ctx):
+    # A NULL stream is the device's default stream: device-pointer work that
+    # torch issues there (input copies, the read-back) is ordered with the
+    # library's kernels, with no explicit synchronisation in between.
+    torch, dev = torch_dev
+    wl = WL.two_layer_case()
+    m, lam, c = wl.models[0], wl.lambdas[0], wl.c_test
+    want = dev_curve(torch_dev, ctx, c, lam, m, M.MASW_PREC_FP64)
+    t = lambda x: torch.as_tensor(np.ascontiguousarray(x, np.float64), device=dev)
+    W = len(lam)
+    for rep in range(5):
+        out = (torch.full((W,), -7.0, dtype=torch.float64, device=dev), torch.full((W,), -7, dtype=torch.int32, device=dev),
+               torch.full((W,), -7, dtype=torch.int32, device=dev), torch.full((W,), -7.0, dtype=torch.float64, device=dev))
+        M.masw_dispersion_curve(ctx.ctx, t(c), t(lam), t(m.h), t(m.alpha), t(m.beta), t(m.rho),
+                                M.MASW_PREC_FP64, 0, None, *out)
+        got = [o.cpu().numpy() for o in out]   # default-stream copies, no synchronize
+        for x, y in zip(want, got):
+            np.testing.assert_array_equal(x, y)
+        arrs = M.flatten_models([m, m], [lam, lam])
+        d = [torch.as_tensor(a, device=dev) for a in arrs]
+        ce = torch.as_tensor(np.tile(want[0], 2), device=dev)
+        mis = torch.full((2,), -7.0, dtype=torch.float64, device=dev)
+        M.masw_misfit(ctx.ctx, d[5], ce, ce, 0, None, mis)
+        assert mis.cpu().tolist() == [0.0, 0.0]
+
+
 # ------------------------------------------------------------ batched launch --
 def test_batch_sample_and_split_vs_fp64(torch_dev, ctx):
     g = _golden("batch_sample.json")
