@@ -283,6 +283,64 @@ def uniform_bench(M, torch, a):
 
 
 # ------------------------------------------------------------- cpu baseline --
+def chains_bench(M, torch, a):
+    """Inversion chains (paper_2003_02256_amd/inversion.py): 256 random-walk
+    Metropolis chains on one synthetic site (a 15-layer base of the serving
+    recipe, its split-path curve plus 0.5% noise as C_e), every step one
+    batched sweep of all proposals plus one device misfit launch."""
+    import workloads as WL
+    from paper_2003_02256_amd import inversion as I
+    base = WL.chain_bases(64, seed=5)
+    site = next(b for b in base if b.model.n_layers == 15)
+    c = WL.serving_grid()
+    ctx_obj = M.Context(0, 2 << 30)
+    ctx = ctx_obj.ctx
+    ev0 = I.DeviceEvaluator(ctx, c, site.lambdas, np.ones(len(site.lambdas)))
+    ct = torch.empty(len(site.lambdas), dtype=torch.float64, device=ev0.dev)
+    idx = torch.empty(len(site.lambdas), dtype=torch.int32, device=ev0.dev)
+    st = torch.empty_like(idx)
+    t = lambda x: torch.as_tensor(np.ascontiguousarray(x, np.float64), device=ev0.dev)
+    m = site.model
+    M.masw_dispersion_curve(ctx, t(c), t(site.lambdas), t(m.h), t(m.alpha), t(m.beta), t(m.rho),
+                            M.MASW_PREC_FP64, M.MASW_NO_REFINE, None, ct, idx, st, None)
+    C_e = I.synthetic_curve(ct.cpu().numpy(), 0.005, seed=6)
+    useful = [0]
+
+    class Counting(I.DeviceEvaluator):
+        def __call__(self, models):
+            out = super().__call__(models)
+            useful[0] += M.masw_get_stats(ctx)["useful_evals"]
+            return out
+    ev = Counting(ctx, c, site.lambdas, C_e)
+    rng = np.random.Generator(np.random.PCG64(8))
+    start = [I.perturb(rng, m, 0.1) for _ in range(256)]
+    T = I.misfit_scale(C_e, float(c[1] - c[0]))
+    I.run_chains(ev, start[:8], max(1, a.warmup), step=0.02, temperature=T, seed=1)  # warm-up
+    useful[0] = 0
+    ev.models_evaluated = 0
+    M.masw_get_timing(ctx, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = I.run_chains(ev, start, a.steps, step=0.02, temperature=T, seed=9)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tm = M.masw_get_timing(ctx, reset=True)
+    ctx_obj.close()
+    steps = a.steps + 1  # the start models are evaluated too
+    print(json.dumps({
+        "metric": METRIC, "value": useful[0] / wall, "unit": "det evals/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": wall / steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 sweep + f64 re-check", "data": "synthetic",
+        "config": {"workload": "inversion_chains_256x15layers", "chains": 256, "n_layers": 15,
+                   "wavelengths": int(len(site.lambdas)), "n_c": int(c.shape[0])},
+        "models_per_s": ev.models_evaluated / wall,
+        "sweep_ms_per_step": tm["sweep_ms_sum"] / max(1, tm["launches"]),
+        "acceptance": res.acceptance_rate,
+        "mean_misfit_start": float(np.nanmean(res.start_misfit)),
+        "mean_misfit_best": float(np.nanmean(res.best_misfit)),
+    }), flush=True)
+
+
 def _oracle_point(args):
     import oracle as O
     lam, c, model = args
@@ -330,7 +388,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="fine_scale",
-                    choices=["fine_scale", "two_layer", "batch", "serving", "uniform"])
+                    choices=["fine_scale", "two_layer", "batch", "serving", "uniform", "chains"])
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="measured seconds of the serving trace")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target CPU work of the oracle sample")
@@ -363,6 +421,9 @@ def main():
         return
     if a.workload == "uniform":
         uniform_bench(M, torch, a)
+        return
+    if a.workload == "chains":
+        chains_bench(M, torch, a)
         return
     dev = torch.device("cuda:0")
     wl = make_workload(a.workload)

@@ -11,8 +11,9 @@ the host.  Each chain then accepts its proposal with the Metropolis rule for
 the target density exp(-misfit / temperature).
 
 The chain logic (`perturb`, `metropolis_accept`, `run_chains`) is plain host
-code; `DeviceEvaluator` is the only part that touches the GPU, and any
-callable that maps a list of models to their misfits can stand in for it.
+code on arrays with one row per chain; `DeviceEvaluator` is the only part
+that touches the GPU, and any callable that maps a Population (or a list of
+models) to their misfits can stand in for it.
 """
 from __future__ import annotations
 
@@ -22,7 +23,7 @@ from typing import Callable, List, Sequence
 
 import numpy as np
 
-from . import (MASW_NO_REFINE, MASW_PREC_SPLIT, flatten_models, masw_dispersion_batch, masw_misfit)
+from . import MASW_NO_REFINE, MASW_PREC_SPLIT, masw_dispersion_batch, masw_misfit
 
 
 @dataclass
@@ -69,6 +70,34 @@ def metropolis_accept(rng: np.random.Generator, current: np.ndarray, proposed: n
 
 
 @dataclass
+class Population:
+    """Models of equal layer count, one per row: h [C, N]; alpha, beta, rho
+    [C, N+1].  Indexing and iteration give LayeredModel views."""
+
+    h: np.ndarray
+    alpha: np.ndarray
+    beta: np.ndarray
+    rho: np.ndarray
+
+    def __len__(self) -> int:
+        return int(self.beta.shape[0])
+
+    def __getitem__(self, i: int) -> LayeredModel:
+        return LayeredModel(self.h[i], self.alpha[i], self.beta[i], self.rho[i])
+
+    def __iter__(self):
+        return (self[i] for i in range(len(self)))
+
+    @staticmethod
+    def stack(models: Sequence) -> "Population":
+        n = {int(np.asarray(m.h).shape[0]) for m in models}
+        if len(n) > 1:
+            raise ValueError("all models must have the same number of layers")
+        f = lambda name: np.stack([np.asarray(getattr(m, name), np.float64) for m in models])
+        return Population(f("h"), f("alpha"), f("beta"), f("rho"))
+
+
+@dataclass
 class ChainResult:
     best_models: List[LayeredModel]
     best_misfit: np.ndarray          # [chains]
@@ -85,34 +114,41 @@ class ChainResult:
 
 def run_chains(evaluate: Callable[[Sequence], np.ndarray], start: Sequence, iterations: int,
                step: float = 0.02, temperature: float = 0.01, seed: int = 0) -> ChainResult:
-    """Advance len(start) chains `iterations` steps.  `evaluate(models)`
-    returns the misfit of each model (NaN allowed).  Draw order per step:
-    every chain's proposal (perturb) in chain order, then one uniform per
-    chain (metropolis_accept)."""
+    """Advance len(start) chains `iterations` steps.  The start models must
+    share their layer count.  `evaluate(population)` returns the misfit of
+    each model of a Population (NaN allowed).  A proposal is `perturb`'s,
+    drawn for all chains at once; draw order per step: beta [chains, N+1],
+    then h [chains, N], then one uniform per chain (metropolis_accept)."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    cur = [LayeredModel(np.asarray(m.h, np.float64).copy(), np.asarray(m.alpha, np.float64).copy(),
-                        np.asarray(m.beta, np.float64).copy(), np.asarray(m.rho, np.float64).copy())
-           for m in start]
+    cur = Population.stack(start)
+    ratio = cur.alpha / cur.beta
     mis = np.asarray(evaluate(cur), np.float64).copy()
-    best = [m.copy() for m in cur]
+    best = Population(cur.h.copy(), cur.alpha.copy(), cur.beta.copy(), cur.rho.copy())
     best_mis = mis.copy()
     accepted = np.zeros(len(cur), np.int64)
     trace = np.empty((iterations + 1, len(cur)))
     trace[0] = mis
     start_mis = mis.copy()
     for it in range(iterations):
-        prop = [perturb(rng, m, step) for m in cur]
+        beta = np.maximum(cur.beta * (1.0 + step * rng.standard_normal(cur.beta.shape)), 1.0)
+        h = np.maximum(cur.h * (1.0 + step * rng.standard_normal(cur.h.shape)), 1e-3)
+        prop = Population(h, ratio * beta, beta, cur.rho)
         pm = np.asarray(evaluate(prop), np.float64)
         ok = metropolis_accept(rng, mis, pm, temperature)
-        for c in np.nonzero(ok)[0]:
-            cur[c] = prop[c]
-            mis[c] = pm[c]
-            accepted[c] += 1
-            if not (best_mis[c] <= pm[c]):  # also replaces a NaN best
-                best[c] = prop[c].copy()
-                best_mis[c] = pm[c]
+        rows = ok[:, None]
+        cur = Population(np.where(rows, prop.h, cur.h), np.where(rows, prop.alpha, cur.alpha),
+                         np.where(rows, prop.beta, cur.beta), cur.rho)
+        mis = np.where(ok, pm, mis)
+        accepted += ok
+        better = ok & ~(best_mis <= pm)  # also replaces a NaN best
+        if better.any():
+            b = better[:, None]
+            best = Population(np.where(b, prop.h, best.h), np.where(b, prop.alpha, best.alpha),
+                              np.where(b, prop.beta, best.beta), best.rho)
+            best_mis = np.where(better, pm, best_mis)
         trace[it + 1] = mis
-    return ChainResult(best, best_mis, mis.copy(), start_mis, accepted, iterations, trace)
+    best_models = [LayeredModel(m.h.copy(), m.alpha.copy(), m.beta.copy(), m.rho.copy()) for m in best]
+    return ChainResult(best_models, best_mis, mis.copy(), start_mis, accepted, iterations, trace)
 
 
 class DeviceEvaluator:
@@ -136,24 +172,33 @@ class DeviceEvaluator:
         if self.C_e.shape != self.lam.shape:
             raise ValueError("C_e and lambdas must have the same length")
         self.c = torch.as_tensor(np.ascontiguousarray(c_test, np.float64), device=self.dev)
-        self._ce_dev = {}  # chains -> tiled C_e on the device
+        self._per_n = {}  # chains -> (lambda_off, lam, C_e) tiled on the device
         self.models_evaluated = 0
 
-    def __call__(self, models: Sequence) -> np.ndarray:
+    def _tiled(self, n: int):
+        if n not in self._per_n:
+            W = self.lam.shape[0]
+            t = lambda x: self.torch.as_tensor(np.ascontiguousarray(x), device=self.dev)
+            self._per_n[n] = (t(np.arange(n + 1, dtype=np.int32) * np.int32(W)), t(np.tile(self.lam, n)),
+                              t(np.tile(self.C_e, n)))
+        return self._per_n[n]
+
+    def __call__(self, models) -> np.ndarray:
         torch, dev = self.torch, self.dev
-        n = len(models)
-        arrs = flatten_models(models, [self.lam] * n)
-        d = [torch.as_tensor(x, device=dev) for x in arrs]
-        W = int(arrs[-1].shape[0])
+        pop = models if isinstance(models, Population) else Population.stack(list(models))
+        n, N = len(pop), int(pop.h.shape[1])
+        lam_off, lam, ce = self._tiled(n)
+        t = lambda x: torch.as_tensor(np.ascontiguousarray(x, np.float64).ravel(), device=dev)
+        layer_off = torch.as_tensor(np.arange(n + 1, dtype=np.int32) * np.int32(N), device=dev)
+        W = int(lam.shape[0])
         f64, i32 = torch.float64, torch.int32
         ct = torch.empty(W, dtype=f64, device=dev)
         idx = torch.empty(W, dtype=i32, device=dev)
         st = torch.empty(W, dtype=i32, device=dev)
-        masw_dispersion_batch(self.ctx, self.c, *d, self.prec, MASW_NO_REFINE, None, ct, idx, st, None)
-        if n not in self._ce_dev:
-            self._ce_dev[n] = torch.as_tensor(np.tile(self.C_e, n), device=dev)
+        masw_dispersion_batch(self.ctx, self.c, layer_off, t(pop.h), t(pop.alpha), t(pop.beta), t(pop.rho),
+                              lam_off, lam, self.prec, MASW_NO_REFINE, None, ct, idx, st, None)
         mis = torch.empty(n, dtype=f64, device=dev)
-        masw_misfit(self.ctx, d[5], ct, self._ce_dev[n], 0, None, mis)
+        masw_misfit(self.ctx, lam_off, ct, ce, 0, None, mis)
         self.models_evaluated += n
         return mis.cpu().numpy()
 

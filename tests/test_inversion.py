@@ -80,3 +80,20 @@ def test_synthetic_curve_and_scale():
     noisy = I.synthetic_curve(ct, 0.01, seed=3)
     assert np.all(np.abs(noisy / ct - 1.0) < 0.06)
     assert I.misfit_scale(ct, 0.5) == pytest.approx(np.mean(0.5 / ct))
+
+
+def test_population_and_zero_step():
+    truth = _model()
+    pop = I.Population.stack([truth, truth.copy()])
+    assert len(pop) == 2 and pop.h.shape == (2, 2) and pop.beta.shape == (2, 3)
+    np.testing.assert_array_equal(list(pop)[1].beta, truth.beta)
+    short = WL.Model(truth.h[:1], truth.alpha[:2], truth.beta[:2], truth.rho[:2])
+    with pytest.raises(ValueError):
+        I.Population.stack([truth, short])
+    # with a zero step every proposal is the current model: always accepted,
+    # nothing changes
+    ev = _beta_misfit(truth.beta * 1.1)
+    r = I.run_chains(ev, [truth, truth], 5, step=0.0, temperature=0.01, seed=1)
+    assert r.accepted.tolist() == [5, 5]
+    np.testing.assert_array_equal(r.trace, np.full((6, 2), ev([truth])[0]))
+    np.testing.assert_array_equal(r.best_models[0].beta, truth.beta)
