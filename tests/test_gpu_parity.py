@@ -230,6 +230,56 @@ def test_many_layers(torch_dev, ctx):
         compare(f"N=120 prec={prec}", dev_curve(torch_dev, ctx, c, lam, m, prec), *want, lam, c, m)
 
 
+def test_maximum_layer_count_identical_stack(torch_dev, ctx):
+    # MASW_MAX_LAYERS identical layers on an identical half-space behave as
+    # the half-space (the pinned reduction of the oracle), so every
+    # wavelength has the homogeneous Rayleigh root, here at nu = 1/4.
+    N = M.MASW_MAX_LAYERS
+    beta = 300.0
+    m = WL.Model(np.full(N, 0.25), np.full(N + 1, math.sqrt(3) * beta), np.full(N + 1, beta),
+                 np.full(N + 1, 1900.0))
+    c = WL.uniform_grid(200.0, 0.05, 2401)
+    lam = np.array([0.5, 5.0, 60.0, 400.0])
+    cR = beta * math.sqrt(2 - 2 / math.sqrt(3))
+    for prec in (M.MASW_PREC_FP64, M.MASW_PREC_SPLIT):
+        ct, idx, st, cr = dev_curve(torch_dev, ctx, c, lam, m, prec)
+        assert np.all(st == 0), (prec, st)
+        assert np.all(c[idx - 1] < cR) and np.all(cR <= c[idx]), (prec, idx)
+        assert np.max(np.abs(cr - cR) / cR) < 1e-8, (prec, cr)
+
+
+def test_layer_count_above_maximum_is_rejected(torch_dev, ctx):
+    N = M.MASW_MAX_LAYERS + 1
+    m = WL.Model(np.full(N, 1.0), np.full(N + 1, 500.0), np.full(N + 1, 300.0), np.full(N + 1, 1900.0))
+    c = WL.uniform_grid(200.0, 0.5, 100)
+    with pytest.raises(M.MaswError) as e:
+        dev_curve(torch_dev, ctx, c, np.array([5.0]), m, M.MASW_PREC_FP64)
+    assert e.value.code == M.MASW_EINVAL
+
+
+def test_grid_of_two_to_the_24_points(torch_dev, ctx):
+    # A 16.8 M-point grid at 1e-5 m/s, far finer than FP32 resolves near
+    # 140 m/s: picks must bracket the oracle's root and the refined roots
+    # agree with it; a root beyond the grid gives NOT_FOUND.
+    wl = WL.two_layer_case()
+    m = wl.models[0]
+    c = WL.uniform_grid(50.0, 1e-5, 1 << 24)
+    lam = np.array([1.0, 4.0, 40.0])
+    coarse = O.dispersion_curve(lam, wl.c_test, m)
+    for prec in (M.MASW_PREC_FP64, M.MASW_PREC_SPLIT):
+        ct, idx, st, cr = dev_curve(torch_dev, ctx, c, lam, m, prec)
+        for w, p in enumerate(coarse):
+            root = p.c_ref
+            if root > c[-1]:
+                assert idx[w] == -1 and st[w] == O.STATUS_NOT_FOUND, (prec, w)
+                continue
+            assert st[w] == 0, (prec, w, st[w])
+            tol = 2e-9 * root
+            assert c[idx[w] - 1] < root + tol and root - tol <= c[idx[w]], (prec, w, idx[w], root)
+            assert abs(cr[w] - root) <= 1e-6 * root, (prec, w, cr[w], root)
+        print(f"2^24 grid prec={prec}: idx {idx.tolist()} stats {ctx.stats()}", flush=True)
+
+
 def test_low_velocity_layer_models(torch_dev, ctx):
     rng = np.random.Generator(np.random.PCG64(33))
     c = WL.uniform_grid(50.0, 0.05, 8001)
