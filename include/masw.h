@@ -30,8 +30,12 @@
  * per-wavelength status.  masw_last_error() describes the last failure of the
  * calling thread.
  *
- * Threads.  A context may be used by one thread at a time; calls on one
- * context are serialised by an internal mutex.
+ * Threads.  Calls on one context are serialised by an internal mutex, so a
+ * context may be shared by threads.  While a server runs, masw_submit,
+ * masw_poll, masw_wait and masw_server_get_stats may be called from any
+ * number of threads at once (a waiting thread does not block submitters).
+ * masw_server_stop and masw_destroy must not overlap any other call on
+ * the context.
  */
 #ifndef MASW_H
 #define MASW_H
@@ -234,7 +238,8 @@ typedef struct {
 int masw_server_start(masw_ctx *ctx, const masw_server_opts *opts);
 
 /* Finish every submitted request, then stop the loop and release the pool.
- * Results not yet collected are discarded. */
+ * Results not yet collected are discarded.  No other call on ctx may be in
+ * progress (in particular no masw_wait). */
 int masw_server_stop(masw_ctx *ctx);
 
 /* Queue one request.  Arguments as masw_dispersion_curve with host pointers;
