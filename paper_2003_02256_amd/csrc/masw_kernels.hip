@@ -928,10 +928,10 @@ __global__ __launch_bounds__(64 * G) void sweep_kernel(SweepArgs a) {
 // Precompute of newly admitted requests: one workgroup per request validates
 // the model and grid, writes the layer records, k per wavelength and the FP32
 // grid, and resets the item states.
-__global__ __launch_bounds__(256) void admit_kernel(const AdmitList* __restrict__ list,
-                                                    int32_t* slot_remaining) {
-  __shared__ int s_bad;
-  __shared__ double s_mu_ref;
+constexpr int kAdmitThreads = 1024;
+
+__global__ __launch_bounds__(kAdmitThreads) void admit_kernel(const AdmitList* __restrict__ list,
+                                                              int32_t* slot_remaining) {
   const int b = blockIdx.x;
   if (b >= list->n) return;
   const SlotDesc d = list->desc[b];
@@ -942,27 +942,24 @@ __global__ __launch_bounds__(256) void admit_kernel(const AdmitList* __restrict_
   const double* rho = beta + (N + 1);
   const double* lam = rho + (N + 1);
   const double* c = lam + W;
-  if (threadIdx.x == 0) {
-    s_bad = (N < 0 || N > MASW_MAX_LAYERS) ? 1 : 0;
-    s_mu_ref = rho[N] * beta[N] * beta[N];
-  }
-  __syncthreads();
-  for (int j = threadIdx.x; j <= N; j += blockDim.x) {
+  // Each thread checks its share; one block-wide OR at the end.
+  int bad = (N < 0 || N > MASW_MAX_LAYERS) ? 1 : 0;
+  for (int j = threadIdx.x; !bad && j <= N; j += blockDim.x) {
     const double al = alpha[j], be = beta[j], rh = rho[j];
     bool ok = (al < __builtin_inf()) && (rh < __builtin_inf()) && (be > 0.0) && (al > be) && (rh > 0.0);
     if (j < N) ok = ok && (h[j] > 0.0) && (h[j] < __builtin_inf());
-    if (!ok) atomicOr(&s_bad, 1);
+    bad |= ok ? 0 : 1;
   }
+#pragma unroll 4
   for (int i = threadIdx.x; i < n_c; i += blockDim.x) {
     const double ci = c[i];
     bool ok = (ci > 0.0) && (ci < __builtin_inf());
     if (i + 1 < n_c) ok = ok && (ci < c[i + 1]);
-    if (!ok) atomicOr(&s_bad, 1);
+    bad |= ok ? 0 : 1;
     d.c32[i] = float(ci);
   }
-  __syncthreads();
-  const bool valid = (s_bad == 0);
-  const double mu_ref = s_mu_ref;
+  const bool valid = __syncthreads_or(bad) == 0;
+  const double mu_ref = valid ? rho[N] * beta[N] * beta[N] : 0.0;
   if (valid) {
     for (int j = threadIdx.x; j <= N; j += blockDim.x) {
       const double al = alpha[j], be = beta[j], rh = rho[j];
@@ -999,8 +996,11 @@ __global__ __launch_bounds__(256) void admit_kernel(const AdmitList* __restrict_
 // at most desc->budget sweep rounds (then its re-check and refinement if its
 // change was found).  The last item of a request to finish raises the
 // request's completion flag in pinned host memory.
+// With G = 8 the kernel is held to 128 VGPRs (4 wavefronts per SIMD), so two
+// workgroups fit on a CU, as for the batch sweep.
 template <int G>
-__global__ __launch_bounds__(64 * G) void tick_kernel(TickArgs a) {
+__global__ __launch_bounds__(64 * G) __attribute__((amdgpu_waves_per_eu(G >= 8 ? 4 : 1)))
+void tick_kernel(TickArgs a) {
   __shared__ SweepShared<G> sh;
   WorkCount wc;
   const TickDesc* __restrict__ D = a.desc;
@@ -1196,7 +1196,7 @@ int tick_blocks_per_cu(int G) {
 
 hipError_t launch_admit(const AdmitList* list_dev, int n, int32_t* slot_remaining, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(admit_kernel, dim3(n), dim3(256), 0, s, list_dev, slot_remaining);
+  hipLaunchKernelGGL(admit_kernel, dim3(n), dim3(kAdmitThreads), 0, s, list_dev, slot_remaining);
   return hipGetLastError();
 }
 
