@@ -17,7 +17,7 @@ int tick_blocks_per_cu(int G);
 hipError_t launch_sweep(int mode, int G, int blocks, hipStream_t s, const SweepArgs& a);
 hipError_t launch_prep(const PrepArgs& a, const CoopInitArgs& ci, int single_N, int single_W, hipStream_t s);
 hipError_t launch_sign_map(bool fp32, const SignMapArgs& a, hipStream_t s);
-hipError_t launch_admit(const AdmitList* list_dev, int n, int32_t* slot_remaining, hipStream_t s);
+hipError_t launch_admit(const AdmitList* list_dev, int n, int max_raw, int32_t* slot_remaining, hipStream_t s);
 hipError_t launch_tick(int G, int blocks, hipStream_t s, const TickArgs& a);
 hipError_t launch_misfit(int n_models, const int32_t* lambda_off, const double* c_t, const double* c_e,
                          double* out, hipStream_t s);

@@ -188,10 +188,15 @@ struct TickDesc {
   SlotDesc slot[kMaxSlots];
 };
 
+// Requests admitted in one tick.  The list and the requests' raw inputs
+// travel in one host-to-device copy; src[b] is where request b's raw inputs
+// (h, alpha, beta, rho, lambda, c) landed, and the admit kernel moves them
+// into the request's pool block (desc[b].raw).
 struct AdmitList {
   int32_t n;
   int32_t slot[kMaxAdmit];
   SlotDesc desc[kMaxAdmit];
+  const double* src[kMaxAdmit];
 };
 
 struct TickArgs {

@@ -925,38 +925,40 @@ __global__ __launch_bounds__(64 * G) void sweep_kernel(SweepArgs a) {
 
 
 // ------------------------------------------------------------- serving --
-// Precompute of newly admitted requests: one workgroup per request validates
-// the model and grid, writes the layer records, k per wavelength and the FP32
-// grid, and resets the item states.
-constexpr int kAdmitThreads = 1024;
+// Precompute of newly admitted requests.  Block (b, y) moves chunk y of
+// request b's raw inputs from the staging copy into the request's pool block,
+// with the FP32 copy of the grid part; block (b, 0) also checks the model and
+// writes its layer records, the k values and the item states.  The host has
+// already checked every value at submit, so an invalid model here (never
+// expected) only marks its wavelengths invalid.
+constexpr int kAdmitChunk = 1024;
 
-__global__ __launch_bounds__(kAdmitThreads) void admit_kernel(const AdmitList* __restrict__ list,
-                                                              int32_t* slot_remaining) {
+__global__ __launch_bounds__(kAdmitChunk) void admit_kernel(const AdmitList* __restrict__ list,
+                                                            int32_t* slot_remaining) {
   const int b = blockIdx.x;
   if (b >= list->n) return;
   const SlotDesc d = list->desc[b];
+  const double* __restrict__ src = list->src[b];
   const int N = d.N, W = d.W, n_c = d.n_c;
-  const double* h = d.raw;
+  const int c_off = N + 3 * (N + 1) + W;
+  const int i = int(blockIdx.y) * kAdmitChunk + int(threadIdx.x);
+  if (i < c_off + n_c) {
+    const double v = src[i];
+    const_cast<double*>(d.raw)[i] = v;
+    if (i >= c_off) d.c32[i - c_off] = float(v);
+  }
+  if (blockIdx.y != 0) return;
+  const double* h = src;
   const double* alpha = h + N;
   const double* beta = alpha + (N + 1);
   const double* rho = beta + (N + 1);
   const double* lam = rho + (N + 1);
-  const double* c = lam + W;
-  // Each thread checks its share; one block-wide OR at the end.
   int bad = (N < 0 || N > MASW_MAX_LAYERS) ? 1 : 0;
   for (int j = threadIdx.x; !bad && j <= N; j += blockDim.x) {
     const double al = alpha[j], be = beta[j], rh = rho[j];
     bool ok = (al < __builtin_inf()) && (rh < __builtin_inf()) && (be > 0.0) && (al > be) && (rh > 0.0);
     if (j < N) ok = ok && (h[j] > 0.0) && (h[j] < __builtin_inf());
     bad |= ok ? 0 : 1;
-  }
-#pragma unroll 4
-  for (int i = threadIdx.x; i < n_c; i += blockDim.x) {
-    const double ci = c[i];
-    bool ok = (ci > 0.0) && (ci < __builtin_inf());
-    if (i + 1 < n_c) ok = ok && (ci < c[i + 1]);
-    bad |= ok ? 0 : 1;
-    d.c32[i] = float(ci);
   }
   const bool valid = __syncthreads_or(bad) == 0;
   const double mu_ref = valid ? rho[N] * beta[N] * beta[N] : 0.0;
@@ -1194,9 +1196,10 @@ int tick_blocks_per_cu(int G) {
   return n;
 }
 
-hipError_t launch_admit(const AdmitList* list_dev, int n, int32_t* slot_remaining, hipStream_t s) {
+hipError_t launch_admit(const AdmitList* list_dev, int n, int max_raw, int32_t* slot_remaining, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(admit_kernel, dim3(n), dim3(kAdmitThreads), 0, s, list_dev, slot_remaining);
+  const int chunks = std::max(1, (max_raw + kAdmitChunk - 1) / kAdmitChunk);
+  hipLaunchKernelGGL(admit_kernel, dim3(n, chunks), dim3(kAdmitChunk), 0, s, list_dev, slot_remaining);
   return hipGetLastError();
 }
 

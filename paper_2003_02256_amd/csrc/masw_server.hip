@@ -4,9 +4,10 @@
 // repeats ticks:
 //   1. admission: while a slot is free and the request's device footprint
 //      fits the serving pool (a first-fit allocator over the context's HBM
-//      budget), stage its raw inputs into the pool (H2D from pinned staging)
-//      and queue it for the admit kernel, which validates it and writes its
-//      layer records, k values, FP32 grid and item states on the device;
+//      budget), pack its raw inputs into pinned staging behind the tick's
+//      admit list; one H2D copy moves both, and the admit kernel moves each
+//      request's inputs into its pool block and writes its layer records, k
+//      values, FP32 grid and item states on the device;
 //   2. one replay of a captured hipGraph (copy of the tick descriptor, a
 //      kernel that clears the counters, the tick kernel), chosen among four
 //      graphs by the number of wavefronts per wavelength;
@@ -137,18 +138,19 @@ struct Server {
   char* pool = nullptr;
   size_t pool_size = 0;
   TickDesc* desc_dev = nullptr;
-  AdmitList* admit_dev = nullptr;
+  AdmitList* admit_dev = nullptr;   // head of the device staging area
   int32_t* remaining_dev = nullptr;
   Counters* counters_dev = nullptr;
   // pinned host memory
   TickDesc* desc_host = nullptr;
-  AdmitList* admit_host = nullptr;
+  AdmitList* admit_host = nullptr;  // head of the pinned staging area
   double* out_ct = nullptr;
   double* out_cref = nullptr;
   int32_t* out_idx = nullptr;
   int32_t* out_status = nullptr;
   int32_t* host_done = nullptr;
-  char* staging = nullptr;
+  char* staging = nullptr;          // pinned: admit list, then raw inputs
+  char* staging_dev = nullptr;      // device copy of the same
   size_t staging_size = 0;
   // one captured tick per G = 1, 2, 4, 8
   hipGraph_t graph[4] = {};
@@ -190,10 +192,9 @@ void Server::run() {
     if (stop && pending.empty() && resident == 0) break;
 
     // 1. admission
-    int n_admit = 0;
-    size_t staged = 0;
+    int n_admit = 0, max_raw = 0;
+    size_t staged = align_up(sizeof(AdmitList));
     bool waited = false;
-    std::vector<std::pair<size_t, size_t>> copies;  // (staging offset, pool offset, via slot desc)
     while (!pending.empty() && n_admit < kMaxAdmit && resident < kMaxSlots) {
       Request* r = pending.front();
       const Layout L = layout_of(r->N, r->W, r->n_c);
@@ -231,7 +232,8 @@ void Server::run() {
       desc_host->slot[slot] = d;
       admit_host->slot[n_admit] = slot;
       admit_host->desc[n_admit] = d;
-      copies.emplace_back(staged, off + L.raw);
+      admit_host->src[n_admit] = reinterpret_cast<const double*>(staging_dev + staged);
+      max_raw = std::max(max_raw, int(r->raw.size()));
       staged += align_up(raw_bytes);
       ++n_admit;
     }
@@ -258,14 +260,8 @@ void Server::run() {
     // 2. device work, in stream order
     const uint64_t t0 = now_ns();
     hipError_t e = hipSuccess;
-    for (size_t i = 0; i < copies.size() && e == hipSuccess; ++i) {
-      const Request* r = slot_req[admit_host->slot[i]];
-      e = hipMemcpyAsync(pool + copies[i].second, staging + copies[i].first, r->raw.size() * sizeof(double),
-                         hipMemcpyHostToDevice, stream);
-    }
-    if (e == hipSuccess && n_admit > 0)
-      e = hipMemcpyAsync(admit_dev, admit_host, sizeof(AdmitList), hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess && n_admit > 0) e = launch_admit(admit_dev, n_admit, remaining_dev, stream);
+    if (n_admit > 0) e = hipMemcpyAsync(staging_dev, staging, staged, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && n_admit > 0) e = launch_admit(admit_dev, n_admit, max_raw, remaining_dev, stream);
     if (e == hipSuccess && units > 0) e = hipGraphLaunch(exec[pick_graph(units)], stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     const uint64_t t1 = now_ns();
@@ -308,7 +304,7 @@ void Server::release_all() {
   for (auto& g : graph)
     if (g) (void)hipGraphDestroy(g);
   if (stream) (void)hipStreamDestroy(stream);
-  for (void* p : {static_cast<void*>(desc_host), static_cast<void*>(admit_host), static_cast<void*>(out_ct),
+  for (void* p : {static_cast<void*>(desc_host), static_cast<void*>(out_ct),
                   static_cast<void*>(out_cref), static_cast<void*>(out_idx), static_cast<void*>(out_status),
                   static_cast<void*>(host_done), static_cast<void*>(staging)})
     if (p) (void)hipHostFree(p);
@@ -348,7 +344,11 @@ int masw_server_start(masw_ctx* ctx, const masw_server_opts* opts) {
   std::lock_guard<std::mutex> lock(ctx->mu);
   if (ctx->server) return fail(MASW_EBUSY, "server already running");
   if (o.pool_bytes == 0) o.pool_bytes = ctx->arena_size / 2;
-  const size_t fixed = align_up(sizeof(TickDesc)) + align_up(sizeof(AdmitList)) +
+  // staging: the admit list, then room for a few of the largest requests' raw inputs
+  const size_t staging_size =
+      align_up(sizeof(AdmitList)) +
+      align_up(sizeof(double) * (size_t(4) * (o.max_layers + 1) + o.max_lambda + o.max_grid)) * 8;
+  const size_t fixed = align_up(sizeof(TickDesc)) + staging_size +
                        align_up(sizeof(int32_t) * kMaxSlots) + align_up(sizeof(Counters));
   const size_t region = align_up(o.pool_bytes) + fixed;
   if (region + (size_t(16) << 20) > ctx->arena_size)
@@ -364,8 +364,9 @@ int masw_server_start(masw_ctx* ctx, const masw_server_opts* opts) {
   char* p = s->region;
   s->desc_dev = reinterpret_cast<TickDesc*>(p);
   p += align_up(sizeof(TickDesc));
+  s->staging_dev = p;
   s->admit_dev = reinterpret_cast<AdmitList*>(p);
-  p += align_up(sizeof(AdmitList));
+  p += staging_size;
   s->remaining_dev = reinterpret_cast<int32_t*>(p);
   p += align_up(sizeof(int32_t) * kMaxSlots);
   s->counters_dev = reinterpret_cast<Counters*>(p);
@@ -381,9 +382,8 @@ int masw_server_start(masw_ctx* ctx, const masw_server_opts* opts) {
   };
   const size_t n_out = size_t(kMaxSlots) * size_t(o.max_lambda);
   // room to stage a few of the largest requests per tick
-  s->staging_size = align_up(sizeof(double) * (size_t(4) * (o.max_layers + 1) + o.max_lambda + o.max_grid)) * 8;
+  s->staging_size = staging_size;
   if (hipHostMalloc(reinterpret_cast<void**>(&s->desc_host), sizeof(TickDesc), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void**>(&s->admit_host), sizeof(AdmitList), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&s->out_ct), sizeof(double) * n_out, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&s->out_cref), sizeof(double) * n_out, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&s->out_idx), sizeof(int32_t) * n_out, hipHostMallocDefault) != hipSuccess ||
@@ -392,6 +392,7 @@ int masw_server_start(masw_ctx* ctx, const masw_server_opts* opts) {
       hipHostMalloc(reinterpret_cast<void**>(&s->staging), s->staging_size, hipHostMallocDefault) != hipSuccess)
     return bail("hipHostMalloc failed for the serving buffers");
   std::memset(s->desc_host, 0, sizeof(TickDesc));
+  s->admit_host = reinterpret_cast<AdmitList*>(s->staging);
   std::memset(s->admit_host, 0, sizeof(AdmitList));
   std::memset(s->host_done, 0, sizeof(int32_t) * kMaxSlots);
   if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess)
