@@ -181,7 +181,9 @@ struct TickDesc {
   int32_t n_active;              // active slots in this tick
   int32_t n_units;               // sum of their W
   int32_t budget;                // sweep rounds per item per tick
-  int32_t pad;
+  uint32_t base;                 // queue counter at the start of this tick: the
+                                 // counter is never cleared, each tick takes
+                                 // exactly n_units + (workgroups) from it
   int32_t active[kMaxSlots];     // slot ids
   int32_t prefix[kMaxSlots + 1]; // prefix sums of W over `active`
   int32_t pad2[3];

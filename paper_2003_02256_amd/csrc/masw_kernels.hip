@@ -87,12 +87,6 @@ __device__ __forceinline__ int wave_first_change(int sg, int* sig_at, int* prev_
 }
 
 // ------------------------------------------------------------- staging --
-__global__ void zero_counters_kernel(Counters* c) {
-  uint32_t* p = reinterpret_cast<uint32_t*>(c);
-  const int n = sizeof(Counters) / sizeof(uint32_t);
-  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
-}
-
 // Validation and per-layer records of model m by one wavefront, one layer
 // per lane.  With a.layer_off == nullptr the batch is a single model of
 // single_N layers and single_W wavelengths.
@@ -1009,8 +1003,10 @@ void tick_kernel(TickArgs a) {
   const int n_units = D->n_units;
   const int n_active = D->n_active;
   const int budget = D->budget;
+  const uint32_t base = D->base;
   for (;;) {
-    if (threadIdx.x == 0) sh.item = (int)atomicAdd(&a.counters->queue_head, 1u);
+    // every workgroup ends with exactly one claim at or beyond n_units
+    if (threadIdx.x == 0) sh.item = int(atomicAdd(&a.counters->queue_head, 1u) - base);
     __syncthreads();
     const int u = uniform(sh.item);
     __syncthreads();
@@ -1203,10 +1199,7 @@ hipError_t launch_admit(const AdmitList* list_dev, int n, int max_raw, int32_t* 
   return hipGetLastError();
 }
 
-// Clears the tick's queue head and counters (a kernel, not a memset, so that
-// the graph holding it replays correctly).
 hipError_t launch_tick(int G, int blocks, hipStream_t s, const TickArgs& a) {
-  hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(256), 0, s, a.counters);
   const void* f = tick_symbol(G);
   if (!f) return hipErrorInvalidValue;
   void* args[] = {const_cast<TickArgs*>(&a)};

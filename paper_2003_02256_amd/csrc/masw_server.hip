@@ -8,9 +8,10 @@
 //      admit list; one H2D copy moves both, and the admit kernel moves each
 //      request's inputs into its pool block and writes its layer records, k
 //      values, FP32 grid and item states on the device;
-//   2. one replay of a captured hipGraph (copy of the tick descriptor, a
-//      kernel that clears the counters, the tick kernel), chosen among four
-//      graphs by the number of wavefronts per wavelength;
+//   2. one replay of a captured hipGraph (copy of the tick descriptor, the
+//      tick kernel), chosen among four graphs by the number of wavefronts per
+//      wavelength; the descriptor carries the tick's start value of the
+//      queue counter, which is never cleared;
 //   3. harvest: requests whose last wavelength finished in this tick (a flag
 //      the kernel writes to pinned memory) have their results, already in
 //      pinned memory, copied out; their slot and memory are released.
@@ -156,6 +157,8 @@ struct Server {
   hipGraph_t graph[4] = {};
   hipGraphExec_t exec[4] = {};
   int bpc[4] = {};
+  int blocks[4] = {};
+  uint32_t queue_base = 0;  // value of the tick queue counter at the next tick
   // host state
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -253,6 +256,8 @@ void Server::run() {
     desc_host->n_active = n_active;
     desc_host->n_units = units;
     desc_host->budget = opt.rounds_per_tick;
+    desc_host->base = queue_base;
+    const int gi = units > 0 ? pick_graph(units) : 0;
     stats.resident = uint32_t(resident);
     stats.max_resident = std::max(stats.max_resident, uint32_t(resident));
     lk.unlock();
@@ -262,7 +267,10 @@ void Server::run() {
     hipError_t e = hipSuccess;
     if (n_admit > 0) e = hipMemcpyAsync(staging_dev, staging, staged, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess && n_admit > 0) e = launch_admit(admit_dev, n_admit, max_raw, remaining_dev, stream);
-    if (e == hipSuccess && units > 0) e = hipGraphLaunch(exec[pick_graph(units)], stream);
+    if (e == hipSuccess && units > 0) {
+      e = hipGraphLaunch(exec[gi], stream);
+      queue_base += uint32_t(units) + uint32_t(blocks[gi]);  // one final claim per workgroup
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     const uint64_t t1 = now_ns();
 
@@ -397,6 +405,10 @@ int masw_server_start(masw_ctx* ctx, const masw_server_opts* opts) {
   std::memset(s->host_done, 0, sizeof(int32_t) * kMaxSlots);
   if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess)
     return bail("hipStreamCreate failed");
+  // the tick counters start at zero once; ticks never clear them (TickDesc::base)
+  if (hipMemsetAsync(s->counters_dev, 0, sizeof(Counters), s->stream) != hipSuccess ||
+      hipStreamSynchronize(s->stream) != hipSuccess)
+    return bail("clearing the tick counters failed");
 
   TickArgs ta{};
   ta.desc = s->desc_dev;
@@ -418,6 +430,7 @@ int masw_server_start(masw_ctx* ctx, const masw_server_opts* opts) {
     const int G = 1 << gi;
     s->bpc[gi] = tick_blocks_per_cu(G);
     const int blocks = ctx->cus * std::max(1, s->bpc[gi]);
+    s->blocks[gi] = blocks;
     if (hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
       return bail("hipStreamBeginCapture failed");
     hipError_t e = hipMemcpyAsync(s->desc_dev, s->desc_host, sizeof(TickDesc), hipMemcpyHostToDevice, s->stream);
