@@ -49,11 +49,15 @@ def flops_per_eval(n_layers: float) -> float:
 # of the kernel sources the counters were taken on, the workload and the
 # launch, so a changed kernel reports null until it is measured again.
 MEASURED_TRAFFIC = {
-    ("d4d13b2f24793d33", "fine_scale_N20_1000lam_115001c", "sweep_kernel<FP64,G=8>"):
-        5625.59 * 1024 * 2.000 + 2638.45 * 1024 * 1.000,
-    ("d4d13b2f24793d33", "batch_4096models_19001c", "sweep_kernel<FP64,G=1>"):
-        266556.0 * 1024 * 2.000 + 147701.0 * 1024 * 1.000,
+    ("59b0a567499c12a6", "fine_scale_N20_1000lam_115001c", "sweep_kernel<FP64,G=8>"):
+        5798.11 * 1024 * 2.000 + 2621.02 * 1024 * 1.000,
+    ("59b0a567499c12a6", "batch_4096models_19001c", "sweep_kernel<FP64,G=1>"):
+        266247.0 * 1024 * 2.000 + 147513.0 * 1024 * 1.000,
 }
+
+# (timed steps, warm-up steps) per workload when the command line gives none.
+DEFAULT_STEPS = {"fine_scale": (200, 50), "two_layer": (200, 50), "batch": (5, 1), "uniform": (20, 3),
+                 "chains": (20, 3)}
 
 KERNEL_SOURCES = ["masw_internal.hpp", "masw_math.hpp", "masw_special.hpp", "masw_kernels.hip"]
 
@@ -385,8 +389,8 @@ def cpu_baseline(wl, target_s: float, workers: int):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default: per workload)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed warm-up steps (default: per workload)")
     ap.add_argument("--workload", default="fine_scale",
                     choices=["fine_scale", "two_layer", "batch", "serving", "uniform", "chains"])
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="measured seconds of the serving trace")
@@ -396,6 +400,11 @@ def main():
                     help="only run a plain device-to-device copy of MIB MiB three times (the reference "
                          "for scaling HBM counter readings) and exit")
     a = ap.parse_args()
+    # Defaults: at least ~0.3 s of warm-up and timed work for the short jobs,
+    # so that the GPU clock has left its idle state before the timed steps.
+    steps, warmup = DEFAULT_STEPS.get(a.workload, (20, 3))
+    a.steps = steps if a.steps is None else a.steps
+    a.warmup = warmup if a.warmup is None else a.warmup
     if a.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported (the dispersion path has no "
               f"cross-GPU exchange and this build runs on a single MI355X)", file=sys.stderr)
