@@ -383,3 +383,139 @@ def test_noise_band_only_at_the_root():
     assert O.in_noise_band(3.0, cR, m)
     assert not O.in_noise_band(3.0, cR + 0.01, m)
     assert not O.in_noise_band(3.0, cR - 0.01, m)
+
+
+# ---------------------------------------------------------------------------
+# P10: the propagator secular function and the zero/pole classification
+# (oracle/propagator.py), against the equations of motion, the Rayleigh
+# function, a 30-digit propagator and the stiffness formulation
+# ---------------------------------------------------------------------------
+from oracle import propagator as PR  # noqa: E402
+
+
+def test_propagator_system_is_the_scaled_psv_system():
+    # A of the oracle = the physical system in zeta = k z with tractions
+    # divided by k mu_ref: T^-1 (A_phys / k) T, T = diag(1, 1, k mu_ref, k mu_ref).
+    k, c, alpha, beta, rho, mu_ref = 0.7, 180.0, 420.0, 210.0, 1850.0, 2000.0 * 450.0 ** 2
+    T = np.diag([1.0, 1.0, k * mu_ref, k * mu_ref])
+    want = np.linalg.inv(T) @ (psv_system(k, c, alpha, beta, rho) / k) @ T
+    got = PR.system_matrix(c, alpha, beta, rho, mu_ref)
+    assert np.allclose(got, want, rtol=1e-13, atol=1e-13 * np.abs(want).max())
+
+
+@pytest.mark.parametrize("c", [40.0, 150.0, 299.0])
+def test_propagator_decaying_pair_are_eigenvectors(c):
+    alpha, beta, rho = 560.0, 300.0, 1950.0
+    A = PR.system_matrix(c, alpha, beta, rho, rho * beta ** 2)
+    V = PR.decaying_pair(c, alpha, beta)
+    r, s = math.sqrt(1 - (c / alpha) ** 2), math.sqrt(1 - (c / beta) ** 2)
+    assert np.allclose(A @ V[:, 0], -r * V[:, 0], atol=1e-13)
+    assert np.allclose(A @ V[:, 1], -s * V[:, 1], atol=1e-13)
+
+
+def test_propagator_halfspace_is_the_rayleigh_function():
+    # N = 0: F is a positive multiple of 4 r s - (2 - g)^2, whose root is the
+    # closed-form Rayleigh speed.
+    alpha, beta = 700.0, 400.0
+    m = halfspace_model(alpha, beta, 2000.0)
+    for c in np.linspace(50.0, 399.0, 41):
+        r, s, g = math.sqrt(1 - (c / alpha) ** 2), math.sqrt(1 - (c / beta) ** 2), (c / beta) ** 2
+        want = np.sign(4 * r * s - (2 - g) ** 2)
+        assert PR._sgn(PR.secular(1.3, c, m)) == want
+    cR = rayleigh_speed(alpha, beta)
+    c_test = WL.uniform_grid(300.0, 0.5, 180)
+    idx = int(np.searchsorted(c_test, cR))
+    cls, c_sec = PR.classify(2.0, c_test, idx, m)
+    assert cls == PR.PICK_MODE
+    assert abs(c_sec - cR) / cR < 1e-11
+
+
+def _sign_changes(values):
+    s = np.sign(np.asarray(values, np.float64))
+    return [i for i in range(1, len(s)) if s[i] != s[i - 1]]
+
+
+def test_propagator_zeros_match_mpmath_propagator():
+    # Same brackets of sign change, and the same roots, as the 30-digit
+    # propagator determinant det(P_tu + H P_uu), which uses no orthonormalisation.
+    mp.mp.dps = 30
+    rng = np.random.Generator(np.random.PCG64(21))
+    m = WL.increasing_profile(rng, 3)
+    beta_hs = float(m.beta[-1])
+    for lam in (2.0, 15.0):
+        k = 2 * math.pi / lam
+        cs = np.linspace(0.55 * float(m.beta[0]), 0.995 * beta_hs, 90)
+        ours = _sign_changes([PR.secular(k, c, m) for c in cs])
+        ref = _sign_changes([float(mp_secular(k, c, m)) for c in cs])
+        assert ours == ref and ours
+        i = ours[0]
+        cls, c_sec = PR.classify(lam, cs, i, m)
+        assert cls == PR.PICK_MODE
+        want = mp_root(k, cs[i - 1], cs[i], m, steps=44)
+        assert abs(c_sec - want) / want < 1e-11
+
+
+def test_stiffness_and_propagator_sign_relation():
+    # det K = F x (positive) / prod_j D_j: sign(det K) prod sign(D_j) sign(F)
+    # is one constant below the half-space's S velocity, at every wavelength,
+    # including short ones where the layer propagators grow by e^(k h).
+    wl = WL.fine_scale_case()
+    m = wl.models[0]
+    cs = wl.c_test[::1500]
+    cs = cs[cs < m.beta[-1]]
+    vals = set()
+    for lam in (1.0, 12.0, 100.0):
+        k = 2 * math.pi / lam
+        sK = O.det_sign(k, cs, m)
+        for c, sk in zip(cs, sK):
+            sD = (-1) ** bin(O.pole_mask(k, c, m)).count("1")
+            vals.add(int(sk) * sD * PR._sgn(PR.secular(k, c, m)))
+    assert vals == {1}
+
+
+def test_classification_separates_modes_from_poles():
+    # Along a 1 m wavelength's grid the stiffness determinant changes sign at
+    # modes and at layer resonances (poles).  The propagator classes every
+    # change as the stiffness denominators do, and the mode roots of the two
+    # formulations agree.
+    wl = WL.fine_scale_case()
+    m, lam = wl.models[0], 1.0
+    k = 2 * math.pi / lam
+    cs = WL.uniform_grid(100.0, 2.0, 150)
+    changes = _sign_changes(O.det_sign(k, cs, m))[:6]
+    seen = set()
+    for i in changes:
+        pole = O.pole_mask(k, cs[i - 1], m) != O.pole_mask(k, cs[i], m)
+        cls, c_sec = PR.classify(lam, cs, i, m, rel_tol=1e-11)
+        assert cls == (PR.PICK_POLE if pole else PR.PICK_MODE)
+        seen.add(cls)
+        if cls == PR.PICK_MODE:
+            c_ref = O.bisect_root(k, float(cs[i - 1]), float(cs[i]), m, rel_tol=1e-11)
+            assert abs(c_sec - c_ref) / c_ref < 1e-10
+    assert seen == {PR.PICK_MODE, PR.PICK_POLE}
+
+
+def test_classification_edge_cases():
+    m = halfspace_model(700.0, 400.0, 2000.0)
+    c_test = WL.uniform_grid(300.0, 1.0, 200)
+    assert PR.classify(1.0, c_test, 0, m)[0] == PR.PICK_NONE
+    assert PR.classify(1.0, c_test, -1, m)[0] == PR.PICK_NONE
+    assert PR.classify(1.0, c_test, 100, m)[0] == PR.PICK_LEAKY      # c_test[100] = 400 = beta
+    assert PR.classify(1.0, c_test, 10, m)[0] == PR.PICK_POLE        # no root in [309, 310]
+
+
+def test_sign_relation_holds_across_a_thick_layer():
+    # k h = 250 across the first layer: its P and SV solutions grow apart by
+    # e^(k h (r - s)) ~ e^70 in one crossing, more than FP64 can hold, so the
+    # relation holds only if each layer is crossed in short steps.
+    m = WL.Model(np.array([20.0, 4.0]), np.array([380.0, 560.0, 950.0]),
+                 np.array([200.0, 300.0, 500.0]), np.array([1800.0, 1900.0, 2000.0]))
+    lam = 0.5
+    k = 2 * math.pi / lam
+    cs = np.linspace(60.0, 199.0, 40)
+    sK = O.det_sign(k, cs, m)
+    vals = set()
+    for c, sk in zip(cs, sK):
+        sD = (-1) ** bin(O.pole_mask(k, c, m)).count("1")
+        vals.add(int(sk) * sD * PR._sgn(PR.secular(k, c, m)))
+    assert vals == {1}
