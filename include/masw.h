@@ -276,6 +276,55 @@ int masw_misfit(masw_ctx *ctx, int32_t n_models, const int32_t *lambda_off,
                 const double *C_t, const double *C_e, uint32_t flags, void *stream,
                 double *misfit);
 
+/* ------------------------------------------------ zero/pole classification --
+ * Algorithm 1 (Section 2.1) reports the first grid interval where
+ * sign(det K) changes.  det K of the stiffness formulation is the dispersion
+ * function divided by the layer denominators D_j, so a change can be a zero
+ * (a surface-wave mode) or a pole (a resonance of one layer with both faces
+ * fixed; MASW_FLAG_POLE marks it from the D_j).  masw_classify_picks decides
+ * which with an independent formulation that has no denominators: the
+ * Haskell-Thomson propagator of the P-SV equations of motion.  The
+ * half-space's two solutions that decay with depth are carried up to the
+ * surface, and F(c) = the determinant of their two tractions there vanishes
+ * exactly at the modes.  Each layer is crossed in steps of at most one unit
+ * of k dz max(|r|, |s|) (r^2 = 1 - c^2/alpha^2, s^2 = 1 - c^2/beta^2), with
+ * the pair re-orthonormalised after each step; that divides F by a positive
+ * factor, so its sign and zeros are unchanged. */
+enum {
+    MASW_PICK_MODE = 0,       /* F changes sign between c_test[idx-1] and
+                                 c_test[idx] (a zero counts as a sign)        */
+    MASW_PICK_POLE = 1,       /* F has the same sign at both ends: no mode in
+                                 the bracket, so a sign change of det K there
+                                 is a pole                                    */
+    MASW_PICK_LEAKY = 2,      /* c_test[idx] >= the half-space's beta: F is
+                                 not real there; not classified               */
+    MASW_PICK_NONE = 3,       /* idx < 1 or idx >= n_c: no bracket (takes
+                                 precedence over the other classes)           */
+    MASW_PICK_UNRESOLVED = 4, /* a layer needs more than 65536 steps
+                                 (k h max(|r|, |s|) > 65536), or F is not
+                                 finite                                       */
+    MASW_PICK_INVALID = 5     /* the model, wavelength or bracket failed
+                                 device validation                            */
+};
+
+/* Classify the sign change at grid index idx[w] of every wavelength w of a
+ * batch (layout as masw_dispersion_batch; idx is typically that call's idx
+ * output, or any index whose bracket holds a sign change of a sign map).
+ * pick_class[w] = MASW_PICK_*.  c_sec[w] = for MASW_PICK_MODE, the root of F
+ * in the bracket (multisection to a bracket no wider than
+ * 1e-12 c_test[idx[w]], midpoint), else NaN; c_sec may be NULL.
+ * c_test: [n_c] as masw_dispersion_curve.  idx, pick_class: int32
+ * [lambda_off[n_models]]; c_sec: double [lambda_off[n_models]].  Host
+ * pointers are validated (models, wavelengths, grid) and the call is
+ * synchronous; with MASW_DEVICE_PTRS every array is a device pointer, the
+ * call is stream-ordered after reading the two offset arrays, and invalid
+ * values give MASW_PICK_INVALID.  Only MASW_DEVICE_PTRS is accepted in
+ * flags. */
+int masw_classify_picks(masw_ctx *ctx, const double *c_test, int32_t n_c,
+                        const masw_batch *batch, const int32_t *idx,
+                        uint32_t flags, void *stream,
+                        int32_t *pick_class, double *c_sec);
+
 /* Counters of the last completed call on ctx (for MASW_DEVICE_PTRS calls,
  * after the stream has been synchronised; this function synchronises). */
 int masw_get_stats(masw_ctx *ctx, masw_stats *out);

@@ -57,7 +57,7 @@ c_test[idx]]):
                 sign change of det K there is a pole;
     PICK_LEAKY  c_test[idx] >= the half-space's beta: the decaying pair is
                 not real there, no classification;
-    PICK_NONE   idx < 1 (no bracket).
+    PICK_NONE   idx < 1 or idx >= len(c_test) (no bracket).
 
 Pins: tests/test_oracle_pins.py checks A against the physical P-SV system,
 the pair above against A's eigenvectors, F against the Rayleigh function of a
@@ -136,7 +136,7 @@ def _sgn(v: float) -> int:
 
 def classify(lam: float, c_test: np.ndarray, idx: int, model, rel_tol: float = 1e-12) -> Tuple[int, float]:
     """(class, c_sec) of the sign change at grid index idx (module header)."""
-    if idx < 1:
+    if idx < 1 or idx >= len(c_test):
         return PICK_NONE, float("nan")
     lo, hi = float(c_test[idx - 1]), float(c_test[idx])
     if hi >= model.beta[model.n_layers]:

@@ -32,6 +32,13 @@ MASW_STATUS_INVALID = 2
 MASW_STATUS_NAN = 3
 MASW_FLAG_POLE = 0x100
 
+MASW_PICK_MODE = 0
+MASW_PICK_POLE = 1
+MASW_PICK_LEAKY = 2
+MASW_PICK_NONE = 3
+MASW_PICK_UNRESOLVED = 4
+MASW_PICK_INVALID = 5
+
 MASW_PREC_FP64 = 0
 MASW_PREC_SPLIT = 1
 
@@ -134,6 +141,8 @@ def library() -> ctypes.CDLL:
             "masw_get_stats": (ctypes.c_int, [vp, ctypes.POINTER(masw_stats)]),
             "masw_get_timing": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(masw_timing)]),
             "masw_misfit": (ctypes.c_int, [vp, i32, vp, vp, vp, u32, vp, vp]),
+            "masw_classify_picks": (ctypes.c_int, [vp, vp, i32, ctypes.POINTER(masw_batch), vp, u32, vp,
+                                                   vp, vp]),
             "masw_server_start": (ctypes.c_int, [vp, ctypes.POINTER(masw_server_opts)]),
             "masw_server_stop": (ctypes.c_int, [vp]),
             "masw_submit": (ctypes.c_int, [vp, vp, i32, vp, i32, ctypes.POINTER(masw_model), ctypes.c_int,
@@ -275,6 +284,25 @@ def masw_sign_map(ctx, c_test, lam, h, alpha, beta, rho, prec: int, flags: int, 
         _ptr(sigma, np.int8), _ptr(log_abs_det, np.float64)), "masw_sign_map")
 
 
+def masw_classify_picks(ctx, c_test, layer_off, h, alpha, beta, rho, lambda_off, lam, idx,
+                        flags: int, stream, pick_class, c_sec=None) -> int:
+    """Marshals to the C function (zero/pole class of the change at idx)."""
+    fl = flags | _device_flag(c_test, layer_off, h, alpha, beta, rho, lambda_off, lam, idx, pick_class, c_sec)
+    b = masw_batch()
+    b.n_models = int(layer_off.shape[0]) - 1
+    b.layer_off = ctypes.cast(_ptr(layer_off, np.int32), _ip)
+    b.h = ctypes.cast(_ptr(h, np.float64), _dp)
+    b.alpha = ctypes.cast(_ptr(alpha, np.float64), _dp)
+    b.beta = ctypes.cast(_ptr(beta, np.float64), _dp)
+    b.rho = ctypes.cast(_ptr(rho, np.float64), _dp)
+    b.lambda_off = ctypes.cast(_ptr(lambda_off, np.int32), _ip)
+    b.lambda_ = ctypes.cast(_ptr(lam, np.float64), _dp)
+    return _check(library().masw_classify_picks(
+        ctx, _ptr(c_test, np.float64), int(c_test.shape[0]), ctypes.byref(b), _ptr(idx, np.int32), fl,
+        _stream(stream, fl & MASW_DEVICE_PTRS), _ptr(pick_class, np.int32), _ptr(c_sec, np.float64)),
+        "masw_classify_picks")
+
+
 def masw_misfit(ctx, lambda_off, C_t, C_e, flags: int, stream, misfit) -> int:
     """Marshals to the C function (Algorithm 2 per model)."""
     fl = flags | _device_flag(lambda_off, C_t, C_e, misfit)
@@ -391,6 +419,17 @@ class Context:
         out = (np.empty(W), np.empty(W, np.int32), np.empty(W, np.int32), np.empty(W))
         masw_dispersion_batch(self.ctx, np.ascontiguousarray(c_test, np.float64), *arrs, prec, flags, None, *out)
         return out
+
+    def classify(self, c_test, models, lambdas, idx):
+        """Host arrays in, host arrays out: (pick_class, c_sec), flattened over
+        all wavelengths, for the bracket indices idx (flattened likewise)."""
+        arrs = flatten_models(models, lambdas)
+        W = int(arrs[-1].shape[0])
+        cls = np.empty(W, np.int32)
+        sec = np.empty(W)
+        masw_classify_picks(self.ctx, np.ascontiguousarray(c_test, np.float64), *arrs,
+                            np.ascontiguousarray(idx, np.int32), 0, None, cls, sec)
+        return cls, sec
 
     def sign_map(self, c_test, lam, model, prec=MASW_PREC_FP64, want_log=True):
         W, n_c = int(np.asarray(lam).shape[0]), int(np.asarray(c_test).shape[0])

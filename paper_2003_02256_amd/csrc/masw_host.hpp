@@ -22,6 +22,26 @@ hipError_t launch_tick(int G, int blocks, hipStream_t s, const TickArgs& a);
 hipError_t launch_misfit(int n_models, const int32_t* lambda_off, const double* c_t, const double* c_e,
                          double* out, hipStream_t s);
 
+// Device arrays of a zero/pole classification (masw_classify.hip), laid out
+// as masw_batch plus the bracket indices and the two outputs.
+struct ClassifyArgs {
+  int32_t n_models = 0;
+  const int32_t* layer_off = nullptr;
+  const double* h = nullptr;
+  const double* alpha = nullptr;
+  const double* beta = nullptr;
+  const double* rho = nullptr;
+  const int32_t* lambda_off = nullptr;
+  const double* lambda = nullptr;
+  const double* c = nullptr;
+  int32_t n_c = 0;
+  const int32_t* idx = nullptr;
+  int32_t* cls = nullptr;
+  double* c_sec = nullptr;  // may be null
+  int64_t n_lam = 0;
+};
+hipError_t launch_classify(const ClassifyArgs& a, hipStream_t s);
+
 // Records `msg` as the calling thread's last error and returns `code`.
 int fail(int code, const std::string& msg);
 

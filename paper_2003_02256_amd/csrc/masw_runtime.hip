@@ -679,6 +679,100 @@ int masw_misfit(masw_ctx* ctx, int32_t n_models, const int32_t* lambda_off, cons
   return MASW_OK;
 }
 
+int masw_classify_picks(masw_ctx* ctx, const double* c_test, int32_t n_c, const masw_batch* batch,
+                        const int32_t* idx, uint32_t flags, void* stream, int32_t* pick_class, double* c_sec) {
+  const bool dev = (flags & MASW_DEVICE_PTRS) != 0;
+  int rc;
+  if (flags & ~MASW_DEVICE_PTRS) return fail(MASW_EINVAL, "flags: unknown bits");
+  if (dev && !ctx) return fail(MASW_EINVAL, "ctx: null context");
+  if (!batch) return fail(MASW_EINVAL, "batch: null pointer");
+  if ((rc = check_grid(c_test, n_c, !dev))) return rc;
+  if (batch->n_models < 1) return fail(MASW_EINVAL, "batch: n_models must be >= 1");
+  if (!batch->layer_off || !batch->lambda_off || !batch->alpha || !batch->beta || !batch->rho || !batch->lambda)
+    return fail(MASW_EINVAL, "batch: null array");
+  const size_t n_off = size_t(batch->n_models) + 1;
+  std::vector<int32_t> loff(n_off), woff(n_off);
+  hipStream_t s = static_cast<hipStream_t>(stream);  // NULL: the default stream
+  if (dev) {
+    MASW_HIP(hipSetDevice(ctx->device));
+    MASW_HIP(hipMemcpyAsync(loff.data(), batch->layer_off, sizeof(int32_t) * n_off, hipMemcpyDeviceToHost, s));
+    MASW_HIP(hipMemcpyAsync(woff.data(), batch->lambda_off, sizeof(int32_t) * n_off, hipMemcpyDeviceToHost, s));
+    MASW_HIP(hipStreamSynchronize(s));
+  } else {
+    std::memcpy(loff.data(), batch->layer_off, sizeof(int32_t) * n_off);
+    std::memcpy(woff.data(), batch->lambda_off, sizeof(int32_t) * n_off);
+  }
+  if (loff[0] != 0 || woff[0] != 0) return fail(MASW_EINVAL, "batch: offsets must start at 0");
+  for (int m = 0; m < batch->n_models; ++m) {
+    const int32_t N = loff[m + 1] - loff[m];
+    if (N < 0 || N > MASW_MAX_LAYERS) return fail(MASW_EINVAL, "batch: layer_off must be non-decreasing, N <= MASW_MAX_LAYERS");
+    if (woff[m + 1] < woff[m]) return fail(MASW_EINVAL, "batch: lambda_off must be non-decreasing");
+  }
+  const int64_t L = loff[batch->n_models];
+  const int64_t W = woff[batch->n_models];
+  const int64_t R = L + batch->n_models;  // alpha/beta/rho entries
+  if (L > 0 && !batch->h) return fail(MASW_EINVAL, "batch: null h");
+  if (W > 0 && (!idx || !pick_class)) return fail(MASW_EINVAL, "idx and pick_class required");
+  if (!dev) {
+    for (int m = 0; m < batch->n_models; ++m) {
+      const int32_t N = loff[m + 1] - loff[m];
+      const int64_t r0 = int64_t(loff[m]) + m;
+      if ((rc = check_model_values(N, batch->h + loff[m], batch->alpha + r0, batch->beta + r0, batch->rho + r0,
+                                   ("batch model " + std::to_string(m)).c_str())))
+        return rc;
+    }
+    if ((rc = check_lambda(batch->lambda, int32_t(W), true))) return rc;
+  }
+  if (!ctx) return fail(MASW_EINVAL, "ctx: null context");
+  if (W == 0) return MASW_OK;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  MASW_HIP(hipSetDevice(ctx->device));
+  ClassifyArgs a;
+  a.n_models = batch->n_models;
+  a.n_c = n_c;
+  a.n_lam = W;
+  if (dev) {
+    a.layer_off = batch->layer_off; a.h = batch->h; a.alpha = batch->alpha; a.beta = batch->beta;
+    a.rho = batch->rho; a.lambda_off = batch->lambda_off; a.lambda = batch->lambda; a.c = c_test;
+    a.idx = idx; a.cls = pick_class; a.c_sec = c_sec;
+    MASW_HIP(launch_classify(a, s));
+    ctx->last_stream = s;
+    ctx->last_valid = true;
+    return MASW_OK;
+  }
+  MASW_HIP(claim_arena(ctx, s));
+  Bump b{ctx->arena, ctx->sync_size, 0};
+  b.take<Counters>(1);  // keep the counters block of the last call intact
+  int32_t* d_loff = b.take<int32_t>(n_off);
+  int32_t* d_woff = b.take<int32_t>(n_off);
+  double* d_h = b.take<double>(size_t(L));
+  double* d_abr = b.take<double>(size_t(R) * 3);
+  double* d_lam = b.take<double>(size_t(W));
+  double* d_c = b.take<double>(size_t(n_c));
+  int32_t* d_idx = b.take<int32_t>(size_t(W));
+  int32_t* d_cls = b.take<int32_t>(size_t(W));
+  double* d_sec = b.take<double>(size_t(W));
+  if (!b.ok()) return fail(MASW_ENOMEM, "classification exceeds the HBM budget");
+  MASW_HIP(hipMemcpyAsync(d_loff, loff.data(), sizeof(int32_t) * n_off, hipMemcpyHostToDevice, s));
+  MASW_HIP(hipMemcpyAsync(d_woff, woff.data(), sizeof(int32_t) * n_off, hipMemcpyHostToDevice, s));
+  if (L) MASW_HIP(hipMemcpyAsync(d_h, batch->h, sizeof(double) * L, hipMemcpyHostToDevice, s));
+  MASW_HIP(hipMemcpyAsync(d_abr, batch->alpha, sizeof(double) * R, hipMemcpyHostToDevice, s));
+  MASW_HIP(hipMemcpyAsync(d_abr + R, batch->beta, sizeof(double) * R, hipMemcpyHostToDevice, s));
+  MASW_HIP(hipMemcpyAsync(d_abr + 2 * R, batch->rho, sizeof(double) * R, hipMemcpyHostToDevice, s));
+  MASW_HIP(hipMemcpyAsync(d_lam, batch->lambda, sizeof(double) * W, hipMemcpyHostToDevice, s));
+  MASW_HIP(hipMemcpyAsync(d_c, c_test, sizeof(double) * n_c, hipMemcpyHostToDevice, s));
+  MASW_HIP(hipMemcpyAsync(d_idx, idx, sizeof(int32_t) * W, hipMemcpyHostToDevice, s));
+  a.layer_off = d_loff; a.h = d_h; a.alpha = d_abr; a.beta = d_abr + R; a.rho = d_abr + 2 * R;
+  a.lambda_off = d_woff; a.lambda = d_lam; a.c = d_c; a.idx = d_idx; a.cls = d_cls; a.c_sec = d_sec;
+  MASW_HIP(launch_classify(a, s));
+  MASW_HIP(hipMemcpyAsync(pick_class, d_cls, sizeof(int32_t) * W, hipMemcpyDeviceToHost, s));
+  if (c_sec) MASW_HIP(hipMemcpyAsync(c_sec, d_sec, sizeof(double) * W, hipMemcpyDeviceToHost, s));
+  MASW_HIP(hipStreamSynchronize(s));
+  ctx->last_stream = s;
+  ctx->last_valid = true;
+  return MASW_OK;
+}
+
 int masw_get_stats(masw_ctx* ctx, masw_stats* out) {
   if (!ctx || !out) return fail(MASW_EINVAL, "null argument");
   std::lock_guard<std::mutex> lock(ctx->mu);

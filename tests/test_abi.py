@@ -176,3 +176,24 @@ def test_timing_rejects_null_arguments(lib):
     out = M.masw_timing()
     assert lib.masw_get_timing(None, 0, ctypes.byref(out)) == M.MASW_EINVAL
     assert lib.masw_get_timing(None, 1, None) == M.MASW_EINVAL
+
+
+def test_classify_validates_on_host(lib):
+    wl = WL.two_layer_case()
+    m, lam, c = wl.models[0], wl.lambdas[0][:3], wl.c_test
+    idx = np.array([10, 20, 30], np.int32)
+    cls, sec = np.empty(3, np.int32), np.empty(3)
+
+    def call(models=(m,), lams=(lam,), grid=c, flags=0):
+        arrs = M.flatten_models(list(models), list(lams))
+        M.masw_classify_picks(None, grid, *arrs, idx, flags, None, cls, sec)
+
+    bad = WL.Model(m.h.copy(), m.beta.copy(), m.beta.copy(), m.rho.copy())  # alpha == beta
+    for kwargs, msg in ((dict(models=(bad,)), "alpha must exceed beta"),
+                        (dict(lams=(np.array([1.0, -2.0, 3.0]),)), "lambda"),
+                        (dict(grid=c[::-1].copy()), "increasing"),
+                        (dict(flags=0x80), "flags"),
+                        (dict(), "ctx")):
+        with pytest.raises(M.MaswError) as e:
+            call(**kwargs)
+        assert e.value.code == M.MASW_EINVAL and msg in str(e.value), (kwargs, str(e.value))

@@ -500,6 +500,7 @@ def test_classification_edge_cases():
     c_test = WL.uniform_grid(300.0, 1.0, 200)
     assert PR.classify(1.0, c_test, 0, m)[0] == PR.PICK_NONE
     assert PR.classify(1.0, c_test, -1, m)[0] == PR.PICK_NONE
+    assert PR.classify(1.0, c_test, len(c_test), m)[0] == PR.PICK_NONE
     assert PR.classify(1.0, c_test, 100, m)[0] == PR.PICK_LEAKY      # c_test[100] = 400 = beta
     assert PR.classify(1.0, c_test, 10, m)[0] == PR.PICK_POLE        # no root in [309, 310]
 
