@@ -43,6 +43,20 @@ def flops_per_eval(n_layers: float) -> float:
     return 101.0 * n_layers + 48.0
 
 
+def classify_flops(evals: int, layers: int, steps: int) -> float:
+    """Algorithmic FP operations of a zero/pole classification launch, from its
+    work counters (same counting rules as flops_per_eval, a shared
+    subexpression once, a reciprocal square root 1): per secular-function
+    evaluation 61 (the sample point 4, c^2, mu_ref and its reciprocal 4, the
+    half-space pair 11, its orthonormalisation 39, the traction minor 3); per
+    layer crossed 238 (M, mu, their reciprocals, rho c^2, r^2, s^2 and the
+    step count and length 15, the system matrix 13, the step propagator's
+    series and coefficients 140, the 2x2 block products XY, YX, XYX, YXY 36,
+    its assembly 34); per propagator step 95 (the 4x4 by 4x2 product 56, the
+    orthonormalisation 39)."""
+    return 61.0 * evals + 238.0 * layers + 95.0 * steps
+
+
 # HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs each scaled by the same counter's reading for a plain copy of
 # known size (FETCH x 2.000, WRITE x 1.000); see profiles/.  Keyed by the hash
@@ -57,7 +71,7 @@ MEASURED_TRAFFIC = {
 
 # (timed steps, warm-up steps) per workload when the command line gives none.
 DEFAULT_STEPS = {"fine_scale": (200, 50), "two_layer": (200, 50), "batch": (5, 1), "uniform": (20, 3),
-                 "chains": (20, 3)}
+                 "chains": (20, 3), "classify": (5, 2)}
 
 KERNEL_SOURCES = ["masw_internal.hpp", "masw_math.hpp", "masw_special.hpp", "masw_kernels.hip"]
 
@@ -345,6 +359,85 @@ def chains_bench(M, torch, a):
     }), flush=True)
 
 
+# ---------------------------------------------------------------- classify --
+def _oracle_classify(args):
+    from oracle import propagator as PR
+    lam, c, idx, model = args
+    return PR.classify(lam, c, idx, model)[0]
+
+
+def classify_bench(M, torch, a):
+    """Zero/pole classification (masw_classify_picks) of every pick of the
+    4096-model batch: picks from one FP64 batch launch (untimed), then the
+    classification launches timed back to back with device-resident inputs.
+    The oracle's propagator classifies an evenly spaced sample on the host."""
+    import multiprocessing as mp
+    import workloads as WL
+    wl = WL.batch_case()
+    dev = torch.device("cuda:0")
+    arrs = M.flatten_models(wl.models, wl.lambdas)
+    td = [torch.as_tensor(x, device=dev) for x in arrs]
+    c = torch.as_tensor(wl.c_test, device=dev)
+    W = int(arrs[-1].shape[0])
+    ctx_obj = M.Context(0, 2 << 30)
+    ctx = ctx_obj.ctx
+    ct = torch.empty(W, dtype=torch.float64, device=dev)
+    idx = torch.empty(W, dtype=torch.int32, device=dev)
+    st = torch.empty(W, dtype=torch.int32, device=dev)
+    cref = torch.empty(W, dtype=torch.float64, device=dev)
+    M.masw_dispersion_batch(ctx, c, *td, M.MASW_PREC_FP64, 0, None, ct, idx, st, cref)
+    cls = torch.empty(W, dtype=torch.int32, device=dev)
+    sec = torch.empty(W, dtype=torch.float64, device=dev)
+    for _ in range(a.warmup):
+        M.masw_classify_picks(ctx, c, *td, idx, 0, None, cls, sec)
+    torch.cuda.synchronize()
+    kms, wall, stats = [], 0.0, None
+    for _ in range(a.steps):
+        t0 = time.perf_counter()
+        M.masw_classify_picks(ctx, c, *td, idx, 0, None, cls, sec)
+        stats = M.masw_get_stats(ctx)            # waits for the launch
+        wall += time.perf_counter() - t0
+        kms.append(stats["sweep_ms"])
+    kms_mean = float(np.mean(kms))
+    flops = classify_flops(stats["classify_evals"], stats["classify_layers"], stats["classify_steps"])
+    achieved = flops / (kms_mean * 1e-3) / 1e12
+    cls_h, sec_h, cref_h = cls.cpu().numpy(), sec.cpu().numpy(), cref.cpu().numpy()
+    mode = cls_h == M.MASW_PICK_MODE
+    rel = np.abs(sec_h[mode] - cref_h[mode]) / cref_h[mode]
+    idx_h = idx.cpu().numpy()
+    ctx_obj.close()
+    out = {
+        "metric": METRIC, "value": W / (wall / a.steps), "unit": "classified picks/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": wall / a.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "classify_batch_4096models_19001c", "models": len(wl.models), "picks": W},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "classify_kernel", "kernel_ms": kms_mean, "flops_per_launch": flops},
+        "counts": {"mode": int(mode.sum()), "pole": int((cls_h == M.MASW_PICK_POLE).sum()),
+                   "other": int((~mode & (cls_h != M.MASW_PICK_POLE)).sum())},
+        "secular_evals": stats["classify_evals"], "layers_crossed": stats["classify_layers"],
+        "propagator_steps": stats["classify_steps"],
+        "root_rel_diff_vs_stiffness_max": float(rel.max()) if rel.size else None,
+    }
+    if not a.no_cpu_baseline:
+        pairs = [(float(l), mi) for mi, ls in enumerate(wl.lambdas) for l in ls]
+        pick = np.linspace(0, W - 1, 64).round().astype(int)
+        tasks = [(pairs[i][0], wl.c_test, int(idx_h[i]), wl.models[pairs[i][1]]) for i in pick]
+        workers = min(16, os.cpu_count() or 1)
+        os.environ["OMP_NUM_THREADS"] = "1"
+        t0 = time.perf_counter()
+        with mp.get_context("fork").Pool(workers) as pool:
+            want = pool.map(_oracle_classify, tasks, chunksize=1)
+        cpu_wall = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": len(tasks) / cpu_wall, "unit": "classified picks/s", "cores": workers,
+                               "kind": "oracle",
+                               "sample": f"{len(tasks)} of {W} picks evenly spaced, {cpu_wall:.1f} s wall on "
+                                         f"{workers} processes"}
+        out["oracle_class_mismatches"] = int(sum(int(w != cls_h[i]) for w, i in zip(want, pick)))
+    print(json.dumps(out), flush=True)
+
+
 def _oracle_point(args):
     import oracle as O
     lam, c, model = args
@@ -392,7 +485,7 @@ def main():
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default: per workload)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed warm-up steps (default: per workload)")
     ap.add_argument("--workload", default="fine_scale",
-                    choices=["fine_scale", "two_layer", "batch", "serving", "uniform", "chains"])
+                    choices=["fine_scale", "two_layer", "batch", "serving", "uniform", "chains", "classify"])
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="measured seconds of the serving trace")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target CPU work of the oracle sample")
@@ -433,6 +526,9 @@ def main():
         return
     if a.workload == "chains":
         chains_bench(M, torch, a)
+        return
+    if a.workload == "classify":
+        classify_bench(M, torch, a)
         return
     dev = torch.device("cuda:0")
     wl = make_workload(a.workload)

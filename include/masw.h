@@ -148,6 +148,12 @@ typedef struct {
                                misbehaves; such wavelengths get
                                MASW_STATUS_INVALID)                            */
     uint64_t helper_evals;  /* of sweep_evals, those done by joining workgroups */
+    /* After masw_classify_picks (the fields above are then 0, except
+     * sweep_ms = total_ms = the classification kernel's device time): */
+    uint64_t classify_evals;  /* secular-function evaluations (one per lane and
+                                 multisection round, 64 per round)            */
+    uint64_t classify_layers; /* layers crossed by those evaluations           */
+    uint64_t classify_steps;  /* propagator steps taken by those evaluations   */
 } masw_stats;
 
 /* Create a context on HIP device `device` that may hold up to

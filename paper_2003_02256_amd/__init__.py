@@ -79,7 +79,8 @@ class masw_stats(ctypes.Structure):
                 ("n_lambda", ctypes.c_uint64), ("waves_per_item", ctypes.c_int32),
                 ("workgroups", ctypes.c_int32), ("sweep_ms", ctypes.c_float), ("total_ms", ctypes.c_float),
                 ("shared_items", ctypes.c_int32), ("shared_stalls", ctypes.c_uint32),
-                ("helper_evals", ctypes.c_uint64)]
+                ("helper_evals", ctypes.c_uint64), ("classify_evals", ctypes.c_uint64),
+                ("classify_layers", ctypes.c_uint64), ("classify_steps", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}

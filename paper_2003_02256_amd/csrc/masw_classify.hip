@@ -9,9 +9,9 @@
 //
 // State and system.  For v = (u_x, -i u_z, tau_xz / (k mu_ref),
 // -i tau_zz / (k mu_ref)) and zeta = k z (z down), a layer obeys
-// dv/dzeta = A v with the real 4x4 matrix of `system_matrix` below, whose
-// eigenvalues are +-r, +-s (u = r^2 = 1 - c^2/alpha^2, w = s^2 = 1 - c^2/beta^2);
-// mu_ref is the half-space's rho beta^2.
+// dv/dzeta = A v with a real 4x4 matrix A (entries in `system_matrix` below)
+// whose eigenvalues are +-r, +-s (u = r^2 = 1 - c^2/alpha^2,
+// w = s^2 = 1 - c^2/beta^2); mu_ref is the half-space's rho beta^2.
 //
 // Propagator.  A^2 has the two eigenvalues u and w, so every even function of
 // A is a first-degree polynomial in A^2 and every odd one is A times such a
@@ -30,7 +30,7 @@
 // its beta) are P = (1, r, -2r, g - 2) and SV = (s, 1, g - 2, -2s),
 // g = c^2/beta^2.  The pair is carried up across every layer by exp(-A k h)
 // in equal steps of at most one unit of k dz max(|r|, |s|), and after each
-// step replaced by an orthonormal basis of its span with the same
+// step replaced by a nearly orthonormal basis of its span with the same
 // orientation (Gram-Schmidt: both columns divided by positive numbers).  At
 // the surface F = the determinant of its two traction rows, which vanishes
 // exactly at the modes; the positive factors dropped by the
@@ -79,6 +79,7 @@ struct ClassifyArgsDev {
   const int32_t* idx;
   int32_t* cls;
   double* c_sec;
+  unsigned long long* counters;  // [3]: evaluations, layers crossed, steps
   int64_t n_lam;
   int32_t n_models;
   int32_t n_c;
@@ -86,39 +87,32 @@ struct ClassifyArgsDev {
 
 __device__ __forceinline__ bool finite_pos(double v) { return v > 0.0 && v < __builtin_inf(); }
 
-// A of one layer, row-major (see the file comment for the state).
-__device__ __forceinline__ void system_matrix(double c, double alpha, double beta, double rho, double mu_ref,
-                                              double A[16]) {
-  const double mu = rho * beta * beta;
-  const double M = rho * alpha * alpha;
+// The six entries of A other than the constants A[0,1] = 1, A[3,2] = -1 (see
+// the file comment for the state; every other entry is 0), from the layer's
+// M = rho alpha^2, mu = rho beta^2, their reciprocals, rho c^2 and 1/mu_ref.
+struct SysMat {
+  double a02, a10, a13, a20, a23, a31;
+};
+
+__device__ __forceinline__ SysMat system_matrix(double M, double mu, double iM, double imu, double rc2,
+                                              double mu_ref, double i_ref) {
   const double lam = M - 2.0 * mu;
-  const double rc2 = rho * c * c;
-#pragma unroll
-  for (int i = 0; i < 16; ++i) A[i] = 0.0;
-  A[0 * 4 + 1] = 1.0;
-  A[0 * 4 + 2] = mu_ref / mu;
-  A[1 * 4 + 0] = -lam / M;
-  A[1 * 4 + 3] = mu_ref / M;
-  A[2 * 4 + 0] = (4.0 * mu * (lam + mu) / M - rc2) / mu_ref;
-  A[2 * 4 + 3] = lam / M;
-  A[3 * 4 + 1] = -rc2 / mu_ref;
-  A[3 * 4 + 2] = -1.0;
+  SysMat o;
+  o.a02 = mu_ref * imu;
+  o.a10 = -lam * iM;
+  o.a13 = mu_ref * iM;
+  o.a20 = (4.0 * mu * (lam + mu) * iM - rc2) * i_ref;
+  o.a23 = lam * iM;
+  o.a31 = -rc2 * i_ref;
+  return o;
 }
 
-__device__ __forceinline__ void matmul4(const double X[16], const double Y[16], double Z[16]) {
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      double acc = 0.0;
-#pragma unroll
-      for (int l = 0; l < 4; ++l) acc = __builtin_fma(X[i * 4 + l], Y[l * 4 + j], acc);
-      Z[i * 4 + j] = acc;
-    }
-}
-
-// exp(-A t) for one step (file comment), given u = r^2, w = s^2.
-__device__ __forceinline__ void step_propagator(const double A[16], double u, double w, double t, double P[16]) {
+// exp(-A t) for one step (file comment), given u = r^2, w = s^2, row-major.
+// A couples E = (u_x, tau_zz) only with O = (u_z, tau_xz): in that order
+// A = [[0, X], [Y, 0]] with X = [[1, a02], [a31, -1]], Y = [[a10, a13],
+// [a20, a23]], so A^2 = diag(XY, YX) and A^3 = [[0, XYX], [YXY, 0]], and
+// exp(-A t) = [[a0 I + a1 XY, -(b0 X + b1 XYX)], [-(b0 Y + b1 YXY), a0 I + a1 YX]].
+__device__ __forceinline__ void step_propagator(const SysMat& m, double u, double w, double t, double P[16]) {
   const double U = t * t * u, W = t * t * w;
   double sc1 = 0.0, ss1 = 0.0, sc0 = 0.0, ss0 = 0.0;
   double h_prev = 0.0, h_cur = 1.0, Wp = 1.0;  // h_{n-2}, h_{n-1}
@@ -140,53 +134,83 @@ __device__ __forceinline__ void step_propagator(const double A[16], double u, do
   const double a0 = 1.0 - UW * sc0;
   const double b1 = t * t * t * ss1;
   const double b0 = t * (1.0 - UW * ss0);
-  double A2[16], A3[16];
-  matmul4(A, A, A2);
-  matmul4(A, A2, A3);
-#pragma unroll
-  for (int i = 0; i < 16; ++i) P[i] = a1 * A2[i] - b0 * A[i] - b1 * A3[i];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) P[i * 4 + i] += a0;
+  // XY and YX (rows/columns in E and O order)
+  const double xy00 = __builtin_fma(m.a02, m.a20, m.a10), xy01 = __builtin_fma(m.a02, m.a23, m.a13);
+  const double xy10 = __builtin_fma(m.a31, m.a10, -m.a20), xy11 = __builtin_fma(m.a31, m.a13, -m.a23);
+  const double yx00 = __builtin_fma(m.a13, m.a31, m.a10), yx01 = __builtin_fma(m.a10, m.a02, -m.a13);
+  const double yx10 = __builtin_fma(m.a23, m.a31, m.a20), yx11 = __builtin_fma(m.a20, m.a02, -m.a23);
+  // XYX = (XY) X and YXY = (YX) Y
+  const double xyx00 = __builtin_fma(xy01, m.a31, xy00), xyx01 = __builtin_fma(xy00, m.a02, -xy01);
+  const double xyx10 = __builtin_fma(xy11, m.a31, xy10), xyx11 = __builtin_fma(xy10, m.a02, -xy11);
+  const double yxy00 = __builtin_fma(yx01, m.a20, yx00 * m.a10), yxy01 = __builtin_fma(yx01, m.a23, yx00 * m.a13);
+  const double yxy10 = __builtin_fma(yx11, m.a20, yx10 * m.a10), yxy11 = __builtin_fma(yx11, m.a23, yx10 * m.a13);
+  // state index of E = (0, 3) and O = (1, 2)
+  P[0 * 4 + 0] = __builtin_fma(a1, xy00, a0);
+  P[0 * 4 + 3] = a1 * xy01;
+  P[3 * 4 + 0] = a1 * xy10;
+  P[3 * 4 + 3] = __builtin_fma(a1, xy11, a0);
+  P[1 * 4 + 1] = __builtin_fma(a1, yx00, a0);
+  P[1 * 4 + 2] = a1 * yx01;
+  P[2 * 4 + 1] = a1 * yx10;
+  P[2 * 4 + 2] = __builtin_fma(a1, yx11, a0);
+  P[0 * 4 + 1] = -__builtin_fma(b1, xyx00, b0);
+  P[0 * 4 + 2] = -__builtin_fma(b1, xyx01, b0 * m.a02);
+  P[3 * 4 + 1] = -__builtin_fma(b1, xyx10, b0 * m.a31);
+  P[3 * 4 + 2] = -__builtin_fma(b1, xyx11, -b0);
+  P[1 * 4 + 0] = -__builtin_fma(b1, yxy00, b0 * m.a10);
+  P[1 * 4 + 3] = -__builtin_fma(b1, yxy01, b0 * m.a13);
+  P[2 * 4 + 0] = -__builtin_fma(b1, yxy10, b0 * m.a20);
+  P[2 * 4 + 3] = -__builtin_fma(b1, yxy11, b0 * m.a23);
 }
 
-// Replace the columns (x, y) by an orthonormal basis of their span with the
-// same orientation.
+// Replace the columns (x, y) by a nearly orthonormal basis of their span
+// with the same orientation: x divided by about its norm, then y less its
+// component along x and divided by about its norm.  Only the span, the
+// orientation (both divisors positive) and a well-conditioned basis matter to
+// the sign and the zeros of F, so the hardware reciprocal square root
+// (relative error below 2^-21) serves as the divisor without refinement.
 __device__ __forceinline__ void orthonormalize(double x[4], double y[4]) {
-  const double nx = __builtin_sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2] + x[3] * x[3]);
+  const double ix = __builtin_amdgcn_rsq(x[0] * x[0] + x[1] * x[1] + x[2] * x[2] + x[3] * x[3]);
 #pragma unroll
-  for (int i = 0; i < 4; ++i) x[i] = x[i] / nx;
+  for (int i = 0; i < 4; ++i) x[i] *= ix;
   const double d = x[0] * y[0] + x[1] * y[1] + x[2] * y[2] + x[3] * y[3];
 #pragma unroll
   for (int i = 0; i < 4; ++i) y[i] = __builtin_fma(-d, x[i], y[i]);
-  const double ny = __builtin_sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2] + y[3] * y[3]);
+  const double iy = __builtin_amdgcn_rsq(y[0] * y[0] + y[1] * y[1] + y[2] * y[2] + y[3] * y[3]);
 #pragma unroll
-  for (int i = 0; i < 4; ++i) y[i] = y[i] / ny;
+  for (int i = 0; i < 4; ++i) y[i] *= iy;
 }
 
 // F(c) for wavenumber k and a model of N layers over a half-space (values at
 // index N); c below the half-space's beta.  NaN if a layer needs more than
 // kMaxStepsPerLayer steps.
 __device__ double secular(double c, double k, const double* __restrict__ h, const double* __restrict__ al,
-                          const double* __restrict__ be, const double* __restrict__ rh, int N) {
+                          const double* __restrict__ be, const double* __restrict__ rh, int N,
+                          unsigned* steps_taken) {
+  const double c2 = c * c;
   const double mu_ref = rh[N] * be[N] * be[N];
-  const double g = (c / be[N]) * (c / be[N]);
-  const double r = __builtin_sqrt(1.0 - (c / al[N]) * (c / al[N]));
+  const double i_ref = 1.0 / mu_ref;
+  const double g = c2 / (be[N] * be[N]);
+  const double r = __builtin_sqrt(1.0 - c2 / (al[N] * al[N]));
   const double s = __builtin_sqrt(1.0 - g);
   double x[4] = {1.0, r, -2.0 * r, g - 2.0};
   double y[4] = {s, 1.0, g - 2.0, -2.0 * s};
   orthonormalize(x, y);
   for (int j = N - 1; j >= 0; --j) {
-    const double a = al[j], b = be[j];
-    const double u = 1.0 - (c / a) * (c / a);
-    const double w = 1.0 - (c / b) * (c / b);
+    const double a = al[j], b = be[j], rho = rh[j];
+    const double M = rho * a * a, mu = rho * b * b;
+    const double iM = 1.0 / M, imu = 1.0 / mu;
+    const double rc2 = rho * c2;
+    const double u = 1.0 - rc2 * iM;   // 1 - c^2/alpha^2
+    const double w = 1.0 - rc2 * imu;  // 1 - c^2/beta^2
     const double q = __builtin_sqrt(__builtin_fmax(__builtin_fabs(u), __builtin_fabs(w)));
     const double kh = k * h[j];
     const double need = __builtin_ceil(kh * q);
     if (!(need <= double(kMaxStepsPerLayer))) return __builtin_nan("");
     const int steps = need < 1.0 ? 1 : int(need);
-    double A[16], P[16];
-    system_matrix(c, a, b, rh[j], mu_ref, A);
-    step_propagator(A, u, w, kh / double(steps), P);
+    *steps_taken += unsigned(steps);
+    double P[16];
+    step_propagator(system_matrix(M, mu, iM, imu, rc2, mu_ref, i_ref), u, w, kh / double(steps), P);
     for (int st = 0; st < steps; ++st) {
       double nx[4], ny[4];
 #pragma unroll
@@ -228,6 +252,8 @@ __global__ __launch_bounds__(64 * kClassifyWaves) void classify_kernel(ClassifyA
 
   int cls;
   double root = __builtin_nan("");
+  unsigned steps = 0;  // propagator steps of this lane
+  int rounds = 0;      // multisection rounds (uniform across the wavefront)
   if (i < 1 || i >= a.n_c) {
     cls = MASW_PICK_NONE;
   } else {
@@ -254,7 +280,8 @@ __global__ __launch_bounds__(64 * kClassifyWaves) void classify_kernel(ClassifyA
       cls = MASW_PICK_MODE;
       for (int round = 0; round < kMaxRounds; ++round) {
         const double cl = lane == 63 ? hi : __builtin_fma(hi - lo, double(lane) * (1.0 / 63.0), lo);
-        const double F = secular(cl, k, h, al, be, rh, N);
+        const double F = secular(cl, k, h, al, be, rh, N, &steps);
+        ++rounds;
         const bool nan = !(F == F) || !(__builtin_fabs(F) < __builtin_inf());
         if (__ballot(nan) != 0ull) {
           cls = MASW_PICK_UNRESOLVED;
@@ -278,16 +305,30 @@ __global__ __launch_bounds__(64 * kClassifyWaves) void classify_kernel(ClassifyA
       if (cls == MASW_PICK_MODE) root = 0.5 * (lo + hi);
     }
   }
+  // work counters: one atomic per counter and wavefront
+  unsigned long long st = steps;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) st += __shfl_xor(st, off, 64);
   if (lane == 0) {
     a.cls[wl] = cls;
     if (a.c_sec) a.c_sec[wl] = root;
+    if (rounds) {
+      atomicAdd(&a.counters[0], 64ull * unsigned(rounds));
+      atomicAdd(&a.counters[1], 64ull * unsigned(rounds) * unsigned(N));
+      atomicAdd(&a.counters[2], st);
+    }
   }
+}
+
+__global__ void clear_counters_kernel(unsigned long long* c) {
+  if (threadIdx.x < 3) c[threadIdx.x] = 0ull;
 }
 
 }  // namespace
 
 hipError_t launch_classify(const ClassifyArgs& in, hipStream_t s) {
   if (in.n_lam <= 0) return hipSuccess;
+  if (!in.counters) return hipErrorInvalidValue;
   ClassifyArgsDev a;
   a.layer_off = in.layer_off;
   a.h = in.h;
@@ -303,6 +344,9 @@ hipError_t launch_classify(const ClassifyArgs& in, hipStream_t s) {
   a.n_lam = in.n_lam;
   a.n_models = in.n_models;
   a.n_c = in.n_c;
+  a.counters = reinterpret_cast<unsigned long long*>(in.counters);
+  // a kernel, not a memset, clears the counters, so a caller may capture the call
+  hipLaunchKernelGGL(clear_counters_kernel, dim3(1), dim3(64), 0, s, a.counters);
   const int64_t blocks = (in.n_lam + kClassifyWaves - 1) / kClassifyWaves;
   hipLaunchKernelGGL(classify_kernel, dim3(unsigned(blocks)), dim3(64 * kClassifyWaves), 0, s, a);
   return hipGetLastError();

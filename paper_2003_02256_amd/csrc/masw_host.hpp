@@ -39,6 +39,7 @@ struct ClassifyArgs {
   int32_t* cls = nullptr;
   double* c_sec = nullptr;  // may be null
   int64_t n_lam = 0;
+  uint64_t* counters = nullptr;  // [3]: evaluations, layers crossed, steps (cleared by the launch)
 };
 hipError_t launch_classify(const ClassifyArgs& a, hipStream_t s);
 
@@ -93,4 +94,9 @@ struct masw_ctx {
   int tslot_last = -1;
   masw_timing timing = {};
   masw::Server* server = nullptr; // serving loop, if started
+  // The last masw_classify_picks call: its work counters (in the arena) and
+  // HIP events around its kernel, read by masw_get_stats.
+  hipEvent_t cls_ev[2] = {};
+  uint64_t* cls_counters = nullptr;
+  bool cls_pending = false;
 };

@@ -336,6 +336,7 @@ int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t fl
   ctx->last.workgroups = in.n_lam > 0 ? blocks : 0;
   ctx->last.shared_items = ci.n_coop;
   ctx->stats_pending = true;
+  ctx->cls_pending = false;
   ctx->last_stream = s;
   ctx->last_valid = true;
 
@@ -396,6 +397,8 @@ int masw_create(int device, size_t hbm_budget_bytes, masw_ctx** out) {
     for (auto& t : ctx->tslot)
       for (auto& e : t.ev)
         if (e) (void)hipEventDestroy(e);
+    for (auto& e : ctx->cls_ev)
+      if (e) (void)hipEventDestroy(e);
     delete ctx;
     return fail(code, msg);
   };
@@ -405,6 +408,8 @@ int masw_create(int device, size_t hbm_budget_bytes, masw_ctx** out) {
   for (auto& t : ctx->tslot)
     for (auto& e : t.ev)
       if (hipEventCreate(&e) != hipSuccess) return cleanup(MASW_EDEVICE, "hipEventCreate failed");
+  for (auto& e : ctx->cls_ev)
+    if (hipEventCreate(&e) != hipSuccess) return cleanup(MASW_EDEVICE, "hipEventCreate failed");
   if (hipMalloc(&ctx->arena, budget) != hipSuccess) return cleanup(MASW_ENOMEM, "cannot allocate the HBM budget");
   ctx->arena_size = budget;
   ctx->sync_size = budget;
@@ -437,6 +442,8 @@ void masw_destroy(masw_ctx* ctx) {
   for (auto& t : ctx->tslot)
     for (auto& e : t.ev)
       if (e) (void)hipEventDestroy(e);
+  for (auto& e : ctx->cls_ev)
+    if (e) (void)hipEventDestroy(e);
   delete ctx;
 }
 
@@ -617,6 +624,7 @@ int masw_sign_map(masw_ctx* ctx, const double* c_test, int32_t n_c, const double
   a.logabs = log_dst;
   MASW_HIP(launch_sign_map(prec == MASW_PREC_SPLIT, a, s));
   ctx->stats_pending = false;
+  ctx->cls_pending = false;
   ctx->last = masw_stats{};
   ctx->last_stream = s;
   ctx->last_valid = true;
@@ -727,22 +735,29 @@ int masw_classify_picks(masw_ctx* ctx, const double* c_test, int32_t n_c, const 
   if (W == 0) return MASW_OK;
   std::lock_guard<std::mutex> lock(ctx->mu);
   MASW_HIP(hipSetDevice(ctx->device));
+  MASW_HIP(claim_arena(ctx, s));
+  Bump b{ctx->arena, ctx->sync_size, 0};
+  b.take<Counters>(1);  // keep the counters block of the last call intact
   ClassifyArgs a;
   a.n_models = batch->n_models;
   a.n_c = n_c;
   a.n_lam = W;
+  a.counters = b.take<uint64_t>(3);
+  ctx->stats_pending = false;
+  ctx->cls_pending = false;
   if (dev) {
     a.layer_off = batch->layer_off; a.h = batch->h; a.alpha = batch->alpha; a.beta = batch->beta;
     a.rho = batch->rho; a.lambda_off = batch->lambda_off; a.lambda = batch->lambda; a.c = c_test;
     a.idx = idx; a.cls = pick_class; a.c_sec = c_sec;
+    MASW_HIP(hipEventRecord(ctx->cls_ev[0], s));
     MASW_HIP(launch_classify(a, s));
+    MASW_HIP(hipEventRecord(ctx->cls_ev[1], s));
+    ctx->cls_counters = a.counters;
+    ctx->cls_pending = true;
     ctx->last_stream = s;
     ctx->last_valid = true;
     return MASW_OK;
   }
-  MASW_HIP(claim_arena(ctx, s));
-  Bump b{ctx->arena, ctx->sync_size, 0};
-  b.take<Counters>(1);  // keep the counters block of the last call intact
   int32_t* d_loff = b.take<int32_t>(n_off);
   int32_t* d_woff = b.take<int32_t>(n_off);
   double* d_h = b.take<double>(size_t(L));
@@ -764,7 +779,11 @@ int masw_classify_picks(masw_ctx* ctx, const double* c_test, int32_t n_c, const 
   MASW_HIP(hipMemcpyAsync(d_idx, idx, sizeof(int32_t) * W, hipMemcpyHostToDevice, s));
   a.layer_off = d_loff; a.h = d_h; a.alpha = d_abr; a.beta = d_abr + R; a.rho = d_abr + 2 * R;
   a.lambda_off = d_woff; a.lambda = d_lam; a.c = d_c; a.idx = d_idx; a.cls = d_cls; a.c_sec = d_sec;
+  MASW_HIP(hipEventRecord(ctx->cls_ev[0], s));
   MASW_HIP(launch_classify(a, s));
+  MASW_HIP(hipEventRecord(ctx->cls_ev[1], s));
+  ctx->cls_counters = a.counters;
+  ctx->cls_pending = true;
   MASW_HIP(hipMemcpyAsync(pick_class, d_cls, sizeof(int32_t) * W, hipMemcpyDeviceToHost, s));
   if (c_sec) MASW_HIP(hipMemcpyAsync(c_sec, d_sec, sizeof(double) * W, hipMemcpyDeviceToHost, s));
   MASW_HIP(hipStreamSynchronize(s));
@@ -776,6 +795,21 @@ int masw_classify_picks(masw_ctx* ctx, const double* c_test, int32_t n_c, const 
 int masw_get_stats(masw_ctx* ctx, masw_stats* out) {
   if (!ctx || !out) return fail(MASW_EINVAL, "null argument");
   std::lock_guard<std::mutex> lock(ctx->mu);
+  if (ctx->cls_pending) {
+    MASW_HIP(hipSetDevice(ctx->device));
+    MASW_HIP(hipEventSynchronize(ctx->cls_ev[1]));
+    uint64_t c[3];
+    MASW_HIP(hipMemcpy(c, ctx->cls_counters, sizeof(c), hipMemcpyDeviceToHost));
+    float ms = 0.f;
+    MASW_HIP(hipEventElapsedTime(&ms, ctx->cls_ev[0], ctx->cls_ev[1]));
+    ctx->last = masw_stats{};
+    ctx->last.classify_evals = c[0];
+    ctx->last.classify_layers = c[1];
+    ctx->last.classify_steps = c[2];
+    ctx->last.sweep_ms = ms;
+    ctx->last.total_ms = ms;
+    ctx->cls_pending = false;
+  }
   if (ctx->stats_pending) {
     MASW_HIP(hipSetDevice(ctx->device));
     if (ctx->last_valid) MASW_HIP(hipStreamSynchronize(ctx->last_stream));

@@ -68,6 +68,13 @@ def test_fine_scale_picks(ctx):
     m, lams, c = wl.models[0], wl.lambdas[0], wl.c_test
     C_t, idx, st, c_ref = ctx.curve(c, lams, m, prec=M.MASW_PREC_FP64)
     cls, sec = ctx.classify(c, [m], [lams], idx)
+    st_cls = ctx.stats()
+    # work counters: 64 evaluations per round, N = 20 layers each, at least
+    # one step per layer crossed
+    assert st_cls["classify_evals"] > 0 and st_cls["classify_evals"] % 64 == 0
+    assert st_cls["classify_layers"] == 20 * st_cls["classify_evals"]
+    assert st_cls["classify_steps"] >= st_cls["classify_layers"]
+    assert st_cls["sweep_ms"] > 0.0 and st_cls["useful_evals"] == 0
     counts = _check_vs_stiffness("fine-scale", cls, sec, c, st, idx, c_ref, m.beta[-1])
     print(f"fine-scale picks: mode, pole, leaky = {counts}", flush=True)
     assert counts[0] > 0
@@ -142,6 +149,8 @@ def test_edge_cases(ctx):
                             M.MASW_PICK_LEAKY, M.MASW_PICK_POLE, M.MASW_PICK_POLE]
     assert abs(sec[0] - cR) / cR < 1e-11
     assert np.isnan(sec[1:]).all()
+    st = ctx.stats()                 # a half-space has no layer to cross
+    assert st["classify_evals"] > 0 and st["classify_layers"] == 0 and st["classify_steps"] == 0
     # a layer that would need more than 65536 steps is not crossed
     cls, sec = ctx.classify(c, [thick], [lam[:1]], np.array([10], np.int32))
     assert cls.tolist() == [M.MASW_PICK_UNRESOLVED] and np.isnan(sec[0])
