@@ -63,10 +63,10 @@ def classify_flops(evals: int, layers: int, steps: int) -> float:
 # of the kernel sources the counters were taken on, the workload and the
 # launch, so a changed kernel reports null until it is measured again.
 MEASURED_TRAFFIC = {
-    ("59b0a567499c12a6", "fine_scale_N20_1000lam_115001c", "sweep_kernel<FP64,G=8>"):
-        5798.11 * 1024 * 2.000 + 2621.02 * 1024 * 1.000,
-    ("59b0a567499c12a6", "batch_4096models_19001c", "sweep_kernel<FP64,G=1>"):
-        266247.0 * 1024 * 2.000 + 147513.0 * 1024 * 1.000,
+    ("29c0b88eea1582c3", "fine_scale_N20_1000lam_115001c", "sweep_kernel<FP64,G=8>"):
+        5176.44 * 1024 * 2.000 + 2597.20 * 1024 * 1.000,
+    ("29c0b88eea1582c3", "batch_4096models_19001c", "sweep_kernel<FP64,G=1>"):
+        266439.0 * 1024 * 2.000 + 148177.0 * 1024 * 1.000,
 }
 
 # (timed steps, warm-up steps) per workload when the command line gives none.

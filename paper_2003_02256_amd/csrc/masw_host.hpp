@@ -75,6 +75,8 @@ struct masw_ctx {
   int forced_waves = 0;           // MASW_WAVES_PER_ITEM override (tuning)
   bool shared_sweeps = true;      // MASW_SHARED_SWEEPS=0 turns shared sweeps off (tuning)
   int shared_window = 8;          // MASW_SHARED_WINDOW: joiners' look-ahead in rounds (tuning)
+  int prio_hi = -1, prio_mid = -1;  // MASW_PRIO=hi,mid: issue priority by queue position (tuning;
+                                    // -1: the launch's workgroup count, i.e. each one's first item)
   std::mutex mu;
   masw_stats last = {};
   bool stats_pending = false;

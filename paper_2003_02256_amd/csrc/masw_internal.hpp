@@ -104,6 +104,10 @@ struct SweepArgs {
   uint64_t* coop_sum;    // [n_coop * coop_stride] round summaries, 0 = not yet published
   int32_t* coop_active;  // [gridDim.x] item each workgroup owns in its shared sweep, or -1
   int32_t coop_window;   // rounds a joining workgroup may run ahead of the owner's resolution
+  // Issue priority of a workgroup's wavefronts while it runs queue position
+  // it: 2 for it < prio_hi, 1 for it < prio_mid, else 0 (0 = all off).
+  int32_t prio_hi;
+  int32_t prio_mid;
 };
 
 // Zero-state of the cooperative arrays (one launch before the sweep).

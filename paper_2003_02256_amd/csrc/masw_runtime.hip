@@ -314,6 +314,10 @@ int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t fl
   sw.coop_sum = ci.coop_sum;
   sw.coop_active = ci.coop_active;
   sw.coop_window = ctx->shared_window;
+  // A workgroup's first item comes from the deep end of the queue: it takes
+  // issue precedence over items claimed later on the same compute unit.
+  sw.prio_hi = ctx->prio_hi >= 0 ? ctx->prio_hi : blocks;
+  sw.prio_mid = ctx->prio_mid >= 0 ? ctx->prio_mid : blocks;
   sw.models = p.models;
   sw.layers64 = p.layers64;
   sw.layers32 = p.layers32;
@@ -421,6 +425,14 @@ int masw_create(int device, size_t hbm_budget_bytes, masw_ctx** out) {
     if (g == 1 || g == 2 || g == 4 || g == 8 || g == 16) ctx->forced_waves = g;
   }
   if (const char* f = std::getenv("MASW_SHARED_SWEEPS")) ctx->shared_sweeps = std::atoi(f) != 0;
+  if (const char* f = std::getenv("MASW_PRIO")) {
+    // "hi,mid" queue positions (tuning; "0,0" = off)
+    int hi = 0, mid = 0;
+    if (std::sscanf(f, "%d,%d", &hi, &mid) == 2 && hi >= 0 && mid >= hi) {
+      ctx->prio_hi = hi;
+      ctx->prio_mid = mid;
+    }
+  }
   if (const char* f = std::getenv("MASW_SHARED_WINDOW")) {
     const int w = std::atoi(f);
     if (w >= 1 && w <= 1024) ctx->shared_window = w;
