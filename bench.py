@@ -60,13 +60,16 @@ def classify_flops(evals: int, layers: int, steps: int) -> float:
 # HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs each scaled by the same counter's reading for a plain copy of
 # known size (FETCH x 2.000, WRITE x 1.000); see profiles/.  Keyed by the hash
-# of the kernel sources the counters were taken on, the workload and the
+# of the kernel sources the counters were taken on (KERNEL_SOURCES for the
+# sweep, CLASSIFY_SOURCES for the classification), the workload and the
 # launch, so a changed kernel reports null until it is measured again.
 MEASURED_TRAFFIC = {
     ("29c0b88eea1582c3", "fine_scale_N20_1000lam_115001c", "sweep_kernel<FP64,G=8>"):
         5176.44 * 1024 * 2.000 + 2597.20 * 1024 * 1.000,
     ("29c0b88eea1582c3", "batch_4096models_19001c", "sweep_kernel<FP64,G=1>"):
         266439.0 * 1024 * 2.000 + 148177.0 * 1024 * 1.000,
+    ("6da9bc50b01ce006", "classify_batch_4096models_19001c", "classify_kernel"):
+        14642.625 * 1024 * 2.000 + 21872.34 * 1024 * 1.000,
 }
 
 # (timed steps, warm-up steps) per workload when the command line gives none.
@@ -74,12 +77,13 @@ DEFAULT_STEPS = {"fine_scale": (200, 50), "two_layer": (200, 50), "batch": (5, 1
                  "chains": (20, 3), "classify": (5, 2)}
 
 KERNEL_SOURCES = ["masw_internal.hpp", "masw_math.hpp", "masw_special.hpp", "masw_kernels.hip"]
+CLASSIFY_SOURCES = ["masw_classify.hip"]
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(files=KERNEL_SOURCES) -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in files:
         with open(os.path.join(ROOT, "paper_2003_02256_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -412,7 +416,9 @@ def classify_bench(M, torch, a):
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "classify_batch_4096models_19001c", "models": len(wl.models), "picks": W},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": MEASURED_TRAFFIC.get((kernel_source_hash(CLASSIFY_SOURCES),
+                                                      "classify_batch_4096models_19001c", "classify_kernel")),
                      "kernel": "classify_kernel", "kernel_ms": kms_mean, "flops_per_launch": flops},
         "counts": {"mode": int(mode.sum()), "pole": int((cls_h == M.MASW_PICK_POLE).sum()),
                    "other": int((~mode & (cls_h != M.MASW_PICK_POLE)).sum())},

@@ -36,7 +36,8 @@
 // exactly at the modes; the positive factors dropped by the
 // orthonormalisation leave its sign and zeros unchanged.
 //
-// Work split.  One wavefront per wavelength.  Lane l evaluates F at point l
+// Work split.  One wavefront per wavelength, four per workgroup.  Lane l
+// evaluates F at point l
 // of 64 equally spaced points of the bracket: a different sign at the two
 // ends is a mode, and the first lane whose sign differs from the lower end's
 // gives the next bracket, 63 times narrower (multisection), until it is no
@@ -231,10 +232,29 @@ __device__ double secular(double c, double k, const double* __restrict__ h, cons
 
 __device__ __forceinline__ int sgn(double v) { return int(v > 0.0) - int(v < 0.0); }
 
-__global__ __launch_bounds__(64 * kClassifyWaves) void classify_kernel(ClassifyArgsDev a) {
-  const int lane = int(threadIdx.x) & 63;
-  const int64_t wl = int64_t(blockIdx.x) * kClassifyWaves + int64_t(threadIdx.x >> 6);
-  if (wl >= a.n_lam) return;  // whole wavefronts
+// Workgroups are dispatched to the eight XCDs round-robin (block b on XCD
+// b mod 8), and each XCD has its own L2.  Within every run of 8 kXcdRun
+// dispatched blocks, the blocks are renumbered so that each XCD takes kXcdRun
+// consecutive block numbers: neighbouring wavelengths, which share a model's
+// records and the output cache lines, stay in one L2, while the runs keep
+// every XCD's share of the models mixed.  Blocks past the last whole run keep
+// their numbers.  The renumbering is a bijection of [0, nb), so it changes no
+// result.
+constexpr unsigned kXcds = 8;
+constexpr unsigned kXcdRun = 16;
+
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
+  constexpr unsigned span = kXcds * kXcdRun;
+  if (b >= nb / span * span) return b;
+  const unsigned base = b / span * span, w = b % span;
+  return base + (w % kXcds) * kXcdRun + w / kXcds;
+}
+
+// Class and root of wavelength wl, by one whole wavefront.  Returns the
+// multisection rounds run (uniform across the wavefront); *steps gets this
+// lane's propagator steps and *n_layers the model's layer count.
+__device__ int classify_one(const ClassifyArgsDev& a, int64_t wl, int lane, int* cls_out, double* root_out,
+                            unsigned* steps_out, int* n_layers) {
   // model of wavelength wl: lambda_off[m] <= wl < lambda_off[m + 1]
   int m_lo = 0, m_hi = a.n_models;
   while (m_hi - m_lo > 1) {
@@ -253,7 +273,7 @@ __global__ __launch_bounds__(64 * kClassifyWaves) void classify_kernel(ClassifyA
   int cls;
   double root = __builtin_nan("");
   unsigned steps = 0;  // propagator steps of this lane
-  int rounds = 0;      // multisection rounds (uniform across the wavefront)
+  int rounds = 0;
   if (i < 1 || i >= a.n_c) {
     cls = MASW_PICK_NONE;
   } else {
@@ -305,18 +325,49 @@ __global__ __launch_bounds__(64 * kClassifyWaves) void classify_kernel(ClassifyA
       if (cls == MASW_PICK_MODE) root = 0.5 * (lo + hi);
     }
   }
-  // work counters: one atomic per counter and wavefront
-  unsigned long long st = steps;
+  *cls_out = cls;
+  *root_out = root;
+  *steps_out = steps;
+  *n_layers = N;
+  return rounds;
+}
+
+__global__ __launch_bounds__(64 * kClassifyWaves) void classify_kernel(ClassifyArgsDev a) {
+  __shared__ unsigned long long s_cnt[kClassifyWaves][3];
+  const int lane = int(threadIdx.x) & 63;
+  const int wave = int(threadIdx.x) >> 6;
+  const unsigned vb = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t wl = int64_t(vb) * kClassifyWaves + wave;
+  unsigned long long n_eval = 0, n_layer = 0, n_step = 0;
+  if (wl < a.n_lam) {  // uniform across the wavefront
+    int cls, N;
+    double root;
+    unsigned steps;
+    const int rounds = classify_one(a, wl, lane, &cls, &root, &steps, &N);
+    n_step = steps;
 #pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) st += __shfl_xor(st, off, 64);
-  if (lane == 0) {
-    a.cls[wl] = cls;
-    if (a.c_sec) a.c_sec[wl] = root;
-    if (rounds) {
-      atomicAdd(&a.counters[0], 64ull * unsigned(rounds));
-      atomicAdd(&a.counters[1], 64ull * unsigned(rounds) * unsigned(N));
-      atomicAdd(&a.counters[2], st);
+    for (int off = 32; off >= 1; off >>= 1) n_step += __shfl_xor(n_step, off, 64);
+    n_eval = 64ull * unsigned(rounds);
+    n_layer = n_eval * unsigned(N);
+    if (lane == 0) {
+      a.cls[wl] = cls;
+      if (a.c_sec) a.c_sec[wl] = root;
     }
+  }
+  // work counters: summed over the workgroup in LDS, one atomic per counter
+  // and workgroup (device-scope atomics bypass the L2, so each costs a
+  // memory write)
+  if (lane == 0) {
+    s_cnt[wave][0] = n_eval;
+    s_cnt[wave][1] = n_layer;
+    s_cnt[wave][2] = n_step;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    unsigned long long sum = 0;
+#pragma unroll
+    for (int w = 0; w < kClassifyWaves; ++w) sum += s_cnt[w][threadIdx.x];
+    if (sum) atomicAdd(&a.counters[threadIdx.x], sum);
   }
 }
 
