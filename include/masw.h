@@ -64,9 +64,18 @@ enum {
     MASW_STATUS_NOT_FOUND = 1,  /* no sign change in c_test: idx = -1, C_t NaN */
     MASW_STATUS_INVALID = 2,    /* the model or grid failed device validation  */
     MASW_STATUS_NAN = 3,        /* a determinant evaluated to NaN at idx       */
-    MASW_FLAG_POLE = 0x100      /* some layer denominator D_j changes sign
+    MASW_FLAG_POLE = 0x100,     /* some layer denominator D_j changes sign
                                    between c_test[idx-1] and c_test[idx]: the
                                    change is a pole of det K, not a zero      */
+    MASW_FLAG_NOISE = 0x200     /* with MASW_CHECK_NOISE: c_test[idx-1] or
+                                   c_test[idx] lies in the FP64 noise band,
+                                   cond_2(K) 2(N+1) 2^-53 >= 1e-2, so the pick
+                                   may differ from an exact computation's.
+                                   Tested only below the half-space's S
+                                   velocity, where K is real symmetric and
+                                   cond_2 follows from eigenvalue counts
+                                   (Sylvester's law of inertia on the block
+                                   elimination)                               */
 };
 
 /* Arithmetic of the search.
@@ -80,6 +89,10 @@ typedef enum { MASW_PREC_FP64 = 0, MASW_PREC_SPLIT = 1 } masw_precision;
 /* Flags. */
 #define MASW_DEVICE_PTRS 0x1u  /* array arguments are device pointers        */
 #define MASW_NO_REFINE   0x2u  /* skip the root refinement (c_ref = NaN)     */
+#define MASW_CHECK_NOISE 0x4u  /* masw_dispersion_curve / _batch: test each
+                                  pick's bracket for the FP64 noise band and
+                                  set MASW_FLAG_NOISE (an extra kernel after
+                                  the sweep; not in its timing)               */
 
 /* Limits. */
 #define MASW_MAX_LAYERS 1024   /* finite layers per model                    */

@@ -66,6 +66,7 @@ import numpy as np
 STATUS_FOUND = 0
 STATUS_NOT_FOUND = 1
 FLAG_POLE = 0x100
+FLAG_NOISE = 0x200
 
 
 # --------------------------------------------------------------------------
@@ -250,8 +251,12 @@ def bisect_root(k: float, lo: float, hi: float, model, rel_tol: float = 1e-9) ->
     return 0.5 * (lo + hi)
 
 
-def dispersion_point(lam: float, c_test: np.ndarray, model, refine: bool = True) -> CurvePoint:
-    """One wavelength of Algorithm 1, plus the refined root and pole flag."""
+def dispersion_point(lam: float, c_test: np.ndarray, model, refine: bool = True,
+                     check_noise: bool = False) -> CurvePoint:
+    """One wavelength of Algorithm 1, plus the refined root and pole flag.
+    With check_noise, FLAG_NOISE marks a pick whose bracket has a point in the
+    FP64 noise band (in_noise_band), tested only below the half-space's S
+    velocity, where K is real."""
     k = 2.0 * np.pi / lam
     idx, evals = first_sign_change(k, c_test, model)
     if idx < 0:
@@ -259,15 +264,19 @@ def dispersion_point(lam: float, c_test: np.ndarray, model, refine: bool = True)
     status = STATUS_FOUND
     if pole_mask(k, c_test[idx - 1], model) != pole_mask(k, c_test[idx], model):
         status |= FLAG_POLE
+    if check_noise:
+        beta_hs = model.beta[model.n_layers]
+        if any(c < beta_hs and in_noise_band(lam, c, model) for c in (c_test[idx - 1], c_test[idx])):
+            status |= FLAG_NOISE
     c_ref = bisect_root(k, float(c_test[idx - 1]), float(c_test[idx]), model) if refine else float("nan")
     return CurvePoint(idx, float(c_test[idx]), status, c_ref, evals)
 
 
 def dispersion_curve(lambdas: Sequence[float], c_test: np.ndarray, model,
-                     refine: bool = True):
+                     refine: bool = True, check_noise: bool = False):
     """Algorithm 1 over all wavelengths; returns a list of CurvePoint."""
     c_test = np.asarray(c_test, dtype=np.float64)
-    return [dispersion_point(float(l), c_test, model, refine) for l in lambdas]
+    return [dispersion_point(float(l), c_test, model, refine, check_noise) for l in lambdas]
 
 
 def curve_arrays(points):

@@ -31,6 +31,7 @@ MASW_STATUS_NOT_FOUND = 1
 MASW_STATUS_INVALID = 2
 MASW_STATUS_NAN = 3
 MASW_FLAG_POLE = 0x100
+MASW_FLAG_NOISE = 0x200
 
 MASW_PICK_MODE = 0
 MASW_PICK_POLE = 1
@@ -44,6 +45,7 @@ MASW_PREC_SPLIT = 1
 
 MASW_DEVICE_PTRS = 0x1
 MASW_NO_REFINE = 0x2
+MASW_CHECK_NOISE = 0x4
 MASW_MAX_LAYERS = 1024
 
 

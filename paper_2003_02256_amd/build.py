@@ -18,7 +18,7 @@ LIB = os.path.join(PKG, "libmasw.so")
 PROBE_SRC = os.path.join(ROOT, "tests", "special_probe.hip")
 PROBE_LIB = os.path.join(ROOT, "tests", "libspecial_probe.so")
 
-SOURCES = ["masw_kernels.hip", "masw_runtime.hip", "masw_server.hip", "masw_classify.hip"]
+SOURCES = ["masw_kernels.hip", "masw_runtime.hip", "masw_server.hip", "masw_classify.hip", "masw_noise.hip"]
 HEADERS = ["masw_internal.hpp", "masw_math.hpp", "masw_special.hpp", "masw_host.hpp"]
 
 # Packed FP32 instructions stay disabled; the compiler would otherwise form

@@ -42,6 +42,10 @@ struct ClassifyArgs {
   uint64_t* counters = nullptr;  // [3]: evaluations, layers crossed, steps (cleared by the launch)
 };
 hipError_t launch_classify(const ClassifyArgs& a, hipStream_t s);
+// FP64 noise-band flag of every pick (masw_noise.hip), after the sweep.
+hipError_t launch_noise_check(const ModelDesc* models, const LayerRec64* layers64, const double* c64,
+                              const double* lam_k, const int32_t* lam_model, const int32_t* idx,
+                              int32_t* status, int64_t n_lam, hipStream_t s);
 
 // Records `msg` as the calling thread's last error and returns `code`.
 int fail(int code, const std::string& msg);

@@ -332,6 +332,11 @@ int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t fl
   MASW_HIP(hipEventRecord(T.ev[1], s));
   if (in.n_lam > 0) MASW_HIP(launch_sweep(mode, G, blocks, s, sw));
   MASW_HIP(hipEventRecord(T.ev[2], s));
+  // optional diagnostic after the timed sweep: the FP64 noise band of each
+  // pick's bracket
+  if ((flags & MASW_CHECK_NOISE) && in.n_lam > 0)
+    MASW_HIP(launch_noise_check(p.models, p.layers64, p.c64, p.lam_k, p.lam_model, sw.out_idx, sw.out_status,
+                                in.n_lam, s));
   T.pending = true;
   ctx->tslot_last = ts;
   ctx->last = masw_stats{};
@@ -360,7 +365,7 @@ int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t fl
 
 int check_common(masw_ctx* ctx, masw_precision prec, uint32_t flags) {
   if (prec != MASW_PREC_FP64 && prec != MASW_PREC_SPLIT) return fail(MASW_EINVAL, "prec: unknown precision");
-  if (flags & ~(MASW_DEVICE_PTRS | MASW_NO_REFINE)) return fail(MASW_EINVAL, "flags: unknown bits");
+  if (flags & ~(MASW_DEVICE_PTRS | MASW_NO_REFINE | MASW_CHECK_NOISE)) return fail(MASW_EINVAL, "flags: unknown bits");
   if (!ctx) return fail(MASW_EINVAL, "ctx: null context");
   return MASW_OK;
 }
