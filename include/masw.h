@@ -229,6 +229,10 @@ typedef struct {
     int32_t rounds_per_tick; /* sweep rounds per wavelength per tick (0 = 16)     */
     size_t pool_bytes;       /* device memory for resident requests, taken from
                                 the context's budget (0 = half of it)            */
+    int64_t tick_timeout_us; /* watchdog: a tick (admission + graph replay) that
+                                runs longer fails the server: pending and later
+                                calls return MASW_EDEVICE, and the server must be
+                                stopped and started again (0 = 10 s)             */
 } masw_server_opts;
 
 /* Timing of one request (CLOCK_MONOTONIC ns) and the ticks it took part in. */

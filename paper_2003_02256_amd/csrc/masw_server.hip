@@ -161,9 +161,11 @@ struct Server {
   uint32_t queue_base = 0;  // value of the tick queue counter at the next tick
   // host state
   std::mutex mu;
-  std::condition_variable cv_work, cv_done;
-  std::thread driver;
+  std::condition_variable cv_work, cv_done, cv_watch;
+  std::thread driver, watchdog;
+  uint64_t tick_start_ns = 0;  // start of the tick in flight, 0 if none
   bool stop = false;
+  bool stop_watch = false;
   bool failed = false;
   std::string fail_msg;
   std::deque<Request*> pending;
@@ -176,8 +178,32 @@ struct Server {
 
   int pick_graph(int units) const;
   void run();
+  void watch();
+  void fail_all(const std::string& msg);  // with mu held
   void release_all();
 };
+
+void Server::fail_all(const std::string& msg) {
+  failed = true;
+  fail_msg = msg;
+  for (auto& kv : requests) kv.second->done = true;
+  cv_done.notify_all();
+}
+
+// Watchdog: fails the server when a tick has been in flight longer than
+// opt.tick_timeout_us, so that waiters return instead of blocking on a tick
+// that does not come back.  The driver also checks each finished tick's
+// duration itself.
+void Server::watch() {
+  const uint64_t limit_ns = uint64_t(opt.tick_timeout_us) * 1000ull;
+  const auto period = std::chrono::microseconds(std::clamp<int64_t>(opt.tick_timeout_us / 2, 1000, 100000));
+  std::unique_lock<std::mutex> lk(mu);
+  while (!stop_watch) {
+    if (!failed && tick_start_ns != 0 && now_ns() - tick_start_ns > limit_ns)
+      fail_all("serving watchdog: a tick ran longer than tick_timeout_us");
+    cv_watch.wait_for(lk, period);
+  }
+}
 
 int Server::pick_graph(int units) const {
   for (int gi = 3; gi > 0; --gi) {
@@ -260,10 +286,11 @@ void Server::run() {
     const int gi = units > 0 ? pick_graph(units) : 0;
     stats.resident = uint32_t(resident);
     stats.max_resident = std::max(stats.max_resident, uint32_t(resident));
+    const uint64_t t0 = now_ns();
+    tick_start_ns = t0;
     lk.unlock();
 
     // 2. device work, in stream order
-    const uint64_t t0 = now_ns();
     hipError_t e = hipSuccess;
     if (n_admit > 0) e = hipMemcpyAsync(staging_dev, staging, staged, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess && n_admit > 0) e = launch_admit(admit_dev, n_admit, max_raw, remaining_dev, stream);
@@ -276,14 +303,15 @@ void Server::run() {
 
     // 3. harvest
     lk.lock();
+    tick_start_ns = 0;
     stats.busy_ms += double(t1 - t0) * 1e-6;
     if (e != hipSuccess) {
-      failed = true;
-      fail_msg = std::string("serving tick: ") + hipGetErrorString(e);
-      for (auto& kv : requests) kv.second->done = true;
-      cv_done.notify_all();
+      fail_all(std::string("serving tick: ") + hipGetErrorString(e));
       break;
     }
+    if (!failed && t1 - t0 > uint64_t(opt.tick_timeout_us) * 1000ull)
+      fail_all("serving watchdog: a tick ran longer than tick_timeout_us");
+    if (failed) break;
     ++stats.ticks;
     for (int s = 0; s < kMaxSlots; ++s) {
       Request* r = slot_req[s];
@@ -326,6 +354,12 @@ void server_destroy(Server* s) {
   }
   s->cv_work.notify_all();
   if (s->driver.joinable()) s->driver.join();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop_watch = true;
+  }
+  s->cv_watch.notify_all();
+  if (s->watchdog.joinable()) s->watchdog.join();
   (void)hipSetDevice(s->ctx->device);
   s->ctx->sync_size = s->ctx->arena_size;
   s->release_all();
@@ -346,8 +380,9 @@ int masw_server_start(masw_ctx* ctx, const masw_server_opts* opts) {
   if (o.max_lambda == 0) o.max_lambda = 512;
   if (o.max_grid == 0) o.max_grid = 32768;
   if (o.rounds_per_tick == 0) o.rounds_per_tick = 16;
+  if (o.tick_timeout_us == 0) o.tick_timeout_us = 10000000;
   if (o.max_layers < 0 || o.max_layers > MASW_MAX_LAYERS || o.max_lambda < 1 || o.max_grid < 2 ||
-      o.rounds_per_tick < 1)
+      o.rounds_per_tick < 1 || o.tick_timeout_us < 0)
     return fail(MASW_EINVAL, "server opts: out of range");
   std::lock_guard<std::mutex> lock(ctx->mu);
   if (ctx->server) return fail(MASW_EBUSY, "server already running");
@@ -445,6 +480,7 @@ int masw_server_start(masw_ctx* ctx, const masw_server_opts* opts) {
   s->stats.pool_bytes = s->pool_size;
   ctx->sync_size = (ctx->arena_size - region) & ~(kAlign - 1);
   s->driver = std::thread([s] { s->run(); });
+  s->watchdog = std::thread([s] { s->watch(); });
   ctx->server = s;
   return MASW_OK;
 }

@@ -172,3 +172,30 @@ def test_submit_validates_on_host(ctx):
         submit(ctx, wl.c_test, wl.lambdas[0], m, M.MASW_PREC_FP64)
     assert e.value.code == M.MASW_EINVAL
     M.masw_server_stop(ctx.ctx)
+
+
+def test_watchdog_fails_the_server_and_restart_recovers(ctx):
+    # The watchdog is forced from the host: with a 1 us tick limit every
+    # (normal) tick is too long, so the server fails its requests with
+    # MASW_EDEVICE instead of serving them; the kernels themselves run to
+    # completion.  A restarted server with the default limit serves again.
+    wl = WL.two_layer_case()
+    m, lam, c = wl.models[0], wl.lambdas[0], wl.c_test
+    M.masw_server_start(ctx.ctx, tick_timeout_us=1)
+    t = submit(ctx, c, lam, m, M.MASW_PREC_FP64)
+    with pytest.raises(M.MaswError) as e:
+        wait(ctx, t, lam.shape[0])
+    assert e.value.code == M.MASW_EDEVICE and "watchdog" in str(e.value)
+    with pytest.raises(M.MaswError) as e:
+        submit(ctx, c, lam, m, M.MASW_PREC_FP64)
+    assert e.value.code == M.MASW_EDEVICE
+    M.masw_server_stop(ctx.ctx)
+    M.masw_server_start(ctx.ctx)
+    t = submit(ctx, c, lam, m, M.MASW_PREC_FP64)
+    (ct, idx, st, cr), info = wait(ctx, t, lam.shape[0])
+    want = ctx.curve(c, lam, m)
+    assert np.array_equal(idx, want[1]) and np.array_equal(st, want[2])
+    M.masw_server_stop(ctx.ctx)
+    with pytest.raises(M.MaswError) as e:
+        M.masw_server_start(ctx.ctx, tick_timeout_us=-5)
+    assert e.value.code == M.MASW_EINVAL
