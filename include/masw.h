@@ -84,7 +84,10 @@ enum {
  *                  in FP64 over a window of grid points around it, and the
  *                  refinement is FP64.  idx is the first FP64 sign change in
  *                  the re-checked window.                                     */
-typedef enum { MASW_PREC_FP64 = 0, MASW_PREC_SPLIT = 1 } masw_precision;
+enum { MASW_PREC_FP64 = 0, MASW_PREC_SPLIT = 1 };
+/* A plain integer, not the enum type, so that any value a caller passes is
+ * well defined on both sides of the ABI; others are rejected (MASW_EINVAL). */
+typedef int32_t masw_precision;
 
 /* Flags. */
 #define MASW_DEVICE_PTRS 0x1u  /* array arguments are device pointers        */
