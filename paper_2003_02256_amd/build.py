@@ -37,9 +37,13 @@ def hipcc() -> str:
     return exe
 
 
-def _compile(sources, out, verbose):
+# roctx ranges around the library's calls and serving ticks
+LIB_LIBS = ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"]
+
+
+def _compile(sources, out, verbose, libs=()):
     tmp = out + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, *sources, "-o", tmp]
+    cmd = [hipcc(), *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, *sources, *libs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -51,7 +55,7 @@ def _compile(sources, out, verbose):
 
 def build(verbose: bool = False) -> str:
     """Always recompiles the library and the test probe; returns the library path."""
-    _compile([os.path.join(CSRC, s) for s in SOURCES], LIB, verbose)
+    _compile([os.path.join(CSRC, s) for s in SOURCES], LIB, verbose, LIB_LIBS)
     if os.path.exists(PROBE_SRC):
         _compile([PROBE_SRC], PROBE_LIB, verbose)
     return LIB

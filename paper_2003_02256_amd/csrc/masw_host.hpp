@@ -8,10 +8,21 @@
 #include <mutex>
 #include <string>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "masw.h"
 #include "masw_internal.hpp"
 
 namespace masw {
+// A named roctx range over a scope (shown by rocprofv3 --marker-trace; a
+// cheap no-op without a profiler).
+struct TraceRange {
+  explicit TraceRange(const char* name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
+
 int sweep_blocks_per_cu(int mode, int G);
 int tick_blocks_per_cu(int G);
 hipError_t launch_sweep(int mode, int G, int blocks, hipStream_t s, const SweepArgs& a);

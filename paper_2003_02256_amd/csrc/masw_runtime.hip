@@ -467,6 +467,7 @@ void masw_destroy(masw_ctx* ctx) {
 int masw_dispersion_curve(masw_ctx* ctx, const double* c_test, int32_t n_c, const double* lambda,
                           int32_t n_lambda, const masw_model* model, masw_precision prec, uint32_t flags,
                           void* stream, double* C_t, int32_t* idx, int32_t* status, double* c_ref) {
+  TraceRange trace("masw_dispersion_curve");
   const bool dev = (flags & MASW_DEVICE_PTRS) != 0;
   int rc;
   if (!model) return fail(MASW_EINVAL, "model: null pointer");
@@ -503,6 +504,7 @@ int masw_dispersion_curve(masw_ctx* ctx, const double* c_test, int32_t n_c, cons
 
 int masw_dispersion_batch(masw_ctx* ctx, const double* c_test, int32_t n_c, const masw_batch* batch,
                           masw_precision prec, uint32_t flags, void* stream, const masw_outputs* out) {
+  TraceRange trace("masw_dispersion_batch");
   const bool dev = (flags & MASW_DEVICE_PTRS) != 0;
   int rc;
   if (!batch) return fail(MASW_EINVAL, "batch: null pointer");
@@ -566,6 +568,7 @@ int masw_dispersion_batch(masw_ctx* ctx, const double* c_test, int32_t n_c, cons
 int masw_sign_map(masw_ctx* ctx, const double* c_test, int32_t n_c, const double* lambda, int32_t n_lambda,
                   const masw_model* model, masw_precision prec, uint32_t flags, void* stream, int8_t* sigma,
                   double* log_abs_det) {
+  TraceRange trace("masw_sign_map");
   const bool dev = (flags & MASW_DEVICE_PTRS) != 0;
   int rc;
   if (!model) return fail(MASW_EINVAL, "model: null pointer");
@@ -657,6 +660,7 @@ int masw_sign_map(masw_ctx* ctx, const double* c_test, int32_t n_c, const double
 
 int masw_misfit(masw_ctx* ctx, int32_t n_models, const int32_t* lambda_off, const double* C_t, const double* C_e,
                 uint32_t flags, void* stream, double* misfit) {
+  TraceRange trace("masw_misfit");
   const bool dev = (flags & MASW_DEVICE_PTRS) != 0;
   if (n_models < 0) return fail(MASW_EINVAL, "n_models must be >= 0");
   if (n_models > 0 && (!lambda_off || !C_t || !C_e || !misfit)) return fail(MASW_EINVAL, "misfit: null array");
@@ -706,6 +710,7 @@ int masw_misfit(masw_ctx* ctx, int32_t n_models, const int32_t* lambda_off, cons
 
 int masw_classify_picks(masw_ctx* ctx, const double* c_test, int32_t n_c, const masw_batch* batch,
                         const int32_t* idx, uint32_t flags, void* stream, int32_t* pick_class, double* c_sec) {
+  TraceRange trace("masw_classify_picks");
   const bool dev = (flags & MASW_DEVICE_PTRS) != 0;
   int rc;
   if (flags & ~MASW_DEVICE_PTRS) return fail(MASW_EINVAL, "flags: unknown bits");

@@ -215,6 +215,7 @@ int Server::pick_graph(int units) const {
 
 void Server::run() {
   (void)hipSetDevice(ctx->device);
+  roctxNameOsThread("masw serving driver");
   std::unique_lock<std::mutex> lk(mu);
   for (;;) {
     cv_work.wait(lk, [&] { return stop || !pending.empty() || resident > 0; });
@@ -292,6 +293,7 @@ void Server::run() {
 
     // 2. device work, in stream order
     hipError_t e = hipSuccess;
+    roctxRangePushA("masw_tick");
     if (n_admit > 0) e = hipMemcpyAsync(staging_dev, staging, staged, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess && n_admit > 0) e = launch_admit(admit_dev, n_admit, max_raw, remaining_dev, stream);
     if (e == hipSuccess && units > 0) {
@@ -299,6 +301,7 @@ void Server::run() {
       queue_base += uint32_t(units) + uint32_t(blocks[gi]);  // one final claim per workgroup
     }
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    roctxRangePop();
     const uint64_t t1 = now_ns();
 
     // 3. harvest

@@ -28,7 +28,8 @@ def test_host_checks_under_asan_and_ubsan(tmp_path):
     cmd = [hipcc, "--cuda-host-only", "-O1", "-g", "-std=c++17", *san,
            "-I", os.path.join(ROOT, "include"), "-I", CSRC,
            os.path.join(CSRC, "masw_runtime.hip"), os.path.join(CSRC, "masw_server.hip"),
-           "-x", "hip", os.path.join(HERE, "host_sanitize", "driver.cpp"), "-o", exe]
+           "-x", "hip", os.path.join(HERE, "host_sanitize", "driver.cpp"),
+           "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib", "-o", exe]
     b = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
     assert b.returncode == 0, b.stderr[-4000:]
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:halt_on_error=1",
