@@ -136,8 +136,8 @@ typedef struct {
  * c_t = c_test[idx] (the upper end of the bracketing grid interval, as in
  * Algorithm 1), idx = grid index (-1 if none), status = MASW_STATUS_* |
  * flags, c_ref = FP64 root inside [c_test[idx-1], c_test[idx]] to a bracket
- * width of 1e-9 c_test[idx] (NaN if not found or MASW_NO_REFINE).  c_ref may
- * be NULL. */
+ * width of refine_rel_tol c_test[idx] (masw_opts; 1e-9 by default), or NaN if
+ * not found or MASW_NO_REFINE.  c_ref may be NULL. */
 typedef struct {
     double *c_t;
     int32_t *idx;
@@ -171,6 +171,32 @@ typedef struct {
     uint64_t classify_layers; /* layers crossed by those evaluations           */
     uint64_t classify_steps;  /* propagator steps taken by those evaluations   */
 } masw_stats;
+
+/* Options of a context.  A zero field keeps its default, so a
+ * zero-initialised struct (or NULL) gives the defaults. */
+typedef struct {
+    double refine_rel_tol;    /* c_ref bracket width / c_test[idx], in
+                                 [1e-15, 1e-3] (0 = 1e-9)                      */
+    double noise_threshold;   /* MASW_CHECK_NOISE: a grid point is in the band
+                                 when cond_2(K) 2(N+1) 2^-53 >= this, in
+                                 (0, 1] (0 = 1e-2)                            */
+    int32_t waves_per_item;   /* wavefronts per wavelength in a sweep launch:
+                                 1, 2, 4, 8 or 16 (0 = chosen per launch)     */
+    int32_t shared_window;    /* rounds a workgroup with an empty queue may
+                                 evaluate ahead in a shared sweep, 1..1024
+                                 (0 = 8; -1 = no shared sweeps)               */
+    int32_t first_item_priority; /* 0 = each workgroup's first (deepest) item
+                                 runs at wave issue priority 2; -1 = off      */
+    int32_t reserved;         /* must be 0                                    */
+} masw_opts;
+
+/* Set the options of ctx (NULL = defaults).  They apply to later calls; a
+ * server takes refine_rel_tol when it starts.  MASW_EINVAL on a value out of
+ * range (nothing is changed then). */
+int masw_set_opts(masw_ctx *ctx, const masw_opts *opts);
+
+/* The options in effect, with defaults filled in. */
+int masw_get_opts(masw_ctx *ctx, masw_opts *out);
 
 /* Create a context on HIP device `device` that may hold up to
  * `hbm_budget_bytes` of device memory (0 = 256 MiB).  The budget is

@@ -88,6 +88,15 @@ class masw_stats(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class masw_opts(ctypes.Structure):
+    _fields_ = [("refine_rel_tol", ctypes.c_double), ("noise_threshold", ctypes.c_double),
+                ("waves_per_item", ctypes.c_int32), ("shared_window", ctypes.c_int32),
+                ("first_item_priority", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
 class masw_timing(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_uint64), ("sweep_ms_sum", ctypes.c_double),
                 ("total_ms_sum", ctypes.c_double), ("sweep_ms_min", ctypes.c_float),
@@ -144,6 +153,8 @@ def library() -> ctypes.CDLL:
                                              ctypes.c_int, u32, vp, vp, vp]),
             "masw_get_stats": (ctypes.c_int, [vp, ctypes.POINTER(masw_stats)]),
             "masw_get_timing": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(masw_timing)]),
+            "masw_set_opts": (ctypes.c_int, [vp, ctypes.POINTER(masw_opts)]),
+            "masw_get_opts": (ctypes.c_int, [vp, ctypes.POINTER(masw_opts)]),
             "masw_misfit": (ctypes.c_int, [vp, i32, vp, vp, vp, u32, vp, vp]),
             "masw_classify_picks": (ctypes.c_int, [vp, vp, i32, ctypes.POINTER(masw_batch), vp, u32, vp,
                                                    vp, vp]),
@@ -314,6 +325,19 @@ def masw_misfit(ctx, lambda_off, C_t, C_e, flags: int, stream, misfit) -> int:
                                         _ptr(C_t, np.float64), _ptr(C_e, np.float64), fl,
                                         _stream(stream, fl & MASW_DEVICE_PTRS), _ptr(misfit, np.float64)),
                   "masw_misfit")
+
+
+def masw_set_opts(ctx, refine_rel_tol=0.0, noise_threshold=0.0, waves_per_item=0, shared_window=0,
+                  first_item_priority=0) -> int:
+    """Options of ctx (zero = default; see masw_opts in include/masw.h)."""
+    o = masw_opts(refine_rel_tol, noise_threshold, waves_per_item, shared_window, first_item_priority, 0)
+    return _check(library().masw_set_opts(ctx, ctypes.byref(o)), "masw_set_opts")
+
+
+def masw_get_opts(ctx) -> dict:
+    o = masw_opts()
+    _check(library().masw_get_opts(ctx, ctypes.byref(o)), "masw_get_opts")
+    return o.as_dict()
 
 
 def masw_get_stats(ctx) -> dict:

@@ -56,7 +56,7 @@ hipError_t launch_classify(const ClassifyArgs& a, hipStream_t s);
 // FP64 noise-band flag of every pick (masw_noise.hip), after the sweep.
 hipError_t launch_noise_check(const ModelDesc* models, const LayerRec64* layers64, const double* c64,
                               const double* lam_k, const int32_t* lam_model, const int32_t* idx,
-                              int32_t* status, int64_t n_lam, hipStream_t s);
+                              int32_t* status, int64_t n_lam, double threshold, hipStream_t s);
 
 // Records `msg` as the calling thread's last error and returns `code`.
 int fail(int code, const std::string& msg);
@@ -87,11 +87,16 @@ struct masw_ctx {
   size_t sync_size = 0;           // front part used by the synchronous calls
   int cus = 0;
   int blocks_per_cu[2][5] = {};   // [mode][log2 G], G = 1..16
-  int forced_waves = 0;           // MASW_WAVES_PER_ITEM override (tuning)
-  bool shared_sweeps = true;      // MASW_SHARED_SWEEPS=0 turns shared sweeps off (tuning)
-  int shared_window = 8;          // MASW_SHARED_WINDOW: joiners' look-ahead in rounds (tuning)
-  int prio_hi = -1, prio_mid = -1;  // MASW_PRIO=hi,mid: issue priority by queue position (tuning;
-                                    // -1: the launch's workgroup count, i.e. each one's first item)
+  // options (masw_set_opts); the environment variables named below set their
+  // initial values, for tuning
+  double refine_rel = masw::kRefineRel;  // c_ref bracket width / c_test[idx]
+  double noise_threshold = 1e-2;   // MASW_CHECK_NOISE band
+  int forced_waves = 0;            // MASW_WAVES_PER_ITEM; 0 = chosen per launch
+  bool shared_sweeps = true;       // MASW_SHARED_SWEEPS=0 turns shared sweeps off
+  int shared_window = 8;           // MASW_SHARED_WINDOW: joiners' look-ahead in rounds
+  bool first_item_priority = true;  // each workgroup's first item at issue priority 2
+  int prio_hi = -1, prio_mid = -1;  // MASW_PRIO=hi,mid: issue priority by queue position
+                                    // (-1: the launch's workgroup count, i.e. each one's first item)
   std::mutex mu;
   masw_stats last = {};
   bool stats_pending = false;

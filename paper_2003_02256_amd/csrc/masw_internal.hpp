@@ -22,7 +22,7 @@ namespace masw {
 constexpr int kNoSign = 0x7f;        // "no predecessor" marker in the sign scan
 constexpr int kNaNSign = 2;          // sign code of a NaN determinant
 constexpr int kBuckets = 256;        // work-order buckets
-constexpr double kRefineRel = 1e-9;  // refinement bracket width / c_hi
+constexpr double kRefineRel = 1e-9;  // default refinement bracket width / c_hi
 constexpr int kPrepThreads = 256;    // threads per staging block
 constexpr int kLamBlock = 1024;      // wavelengths sorted by one staging block
 
@@ -91,6 +91,7 @@ struct SweepArgs {
   const int32_t* order;
   int32_t n_items;
   int32_t refine;  // 1 = compute c_ref
+  double refine_rel;  // refinement bracket width / c_hi
   Counters* counters;
   double* out_ct;
   int32_t* out_idx;
@@ -210,6 +211,7 @@ struct TickArgs {
   int32_t* slot_remaining;   // [kMaxSlots] items not finished
   Counters* counters;
   int32_t refine;
+  double refine_rel;         // refinement bracket width / c_hi
   // outputs in pinned host memory (device-accessible)
   double* out_ct;
   int32_t* out_idx;

@@ -358,6 +358,7 @@ struct ItemOut {
   int32_t* status;
   double* cref;  // may be null
   int refine;
+  double refine_rel;  // refinement bracket width / c_hi
 };
 
 template <int G>
@@ -736,7 +737,7 @@ __device__ bool run_item(const ItemRef& r, ItemState& st, int budget, SweepShare
       // change.  The first round also yields the layer-denominator sign
       // masks at the two grid points (pole flag).
       double lo = r.c64[found - 1], hi = r.c64[found];
-      const double tol = kRefineRel * hi;
+      const double tol = o.refine_rel * hi;
       for (int k = 0; k < 24; ++k) {
         const double w = hi - lo;
         const double c = (lane == 63) ? hi : lo + w * (double(lane) / 63.0);
@@ -899,7 +900,7 @@ __global__ __launch_bounds__(64 * G) void sweep_kernel(SweepArgs a) {
     int g;
     const ItemRef r = item_ref(a, it, &g);
     const ItemOut o{a.out_ct + g, a.out_idx + g, a.out_status + g, a.out_cref ? a.out_cref + g : nullptr,
-                    a.refine};
+                    a.refine, a.refine_rel};
     if (!(r.k64 == r.k64)) {  // invalid model, grid or wavelength
       write_missing<G>(o, MASW_STATUS_INVALID);
       continue;
@@ -1037,7 +1038,7 @@ void tick_kernel(TickArgs a) {
     r.L64 = sd.L64;
     r.L32 = sd.L32;
     const int og = sd.out_base + j;
-    const ItemOut o{a.out_ct + og, a.out_idx + og, a.out_status + og, a.out_cref + og, a.refine};
+    const ItemOut o{a.out_ct + og, a.out_idx + og, a.out_status + og, a.out_cref + og, a.refine, a.refine_rel};
     bool done;
     if (!(r.k64 == r.k64)) {
       write_missing<G>(o, MASW_STATUS_INVALID);

@@ -3,12 +3,14 @@
 // The sweep decides a pick by the sign of det K at the two grid points of its
 // bracket.  A grid point c is in the FP64 noise band when the first-order
 // relative error bound of an FP64 determinant, cond_2(K(c)) 2(N+1) 2^-53,
-// reaches 1e-2; a pick with a bracket point in the band may differ from an
-// exact computation's, and MASW_FLAG_NOISE marks it.
+// reaches a threshold (masw_opts.noise_threshold, 1e-2 by default); a pick
+// with a bracket point in the band may differ from an exact computation's,
+// and MASW_FLAG_NOISE marks it.
 //
 // Below the half-space's S velocity K(c) is real symmetric, so cond_2 is
 // max|lambda| / min|lambda| over its eigenvalues, and c is in the band iff K
-// has an eigenvalue in [-s, s], s = max|lambda| / T, T = 1e-2 2^53 / (2(N+1)).
+// has an eigenvalue in [-s, s], s = max|lambda| / T,
+// T = threshold 2^53 / (2(N+1)).
 // The number of eigenvalues of K below x is the number of negative
 // eigenvalues of the 2x2 block pivots of the block LDL^T elimination of
 // K - x I (Sylvester's law of inertia), so the eigenvalues in an interval are
@@ -124,9 +126,9 @@ __device__ bool count_below(double c, double k, const LayerRec<double>* L, int N
   return finite;
 }
 
-__device__ bool in_band(double c, double k, const LayerRec<double>* L, int N) {
+__device__ bool in_band(double c, double k, const LayerRec<double>* L, int N, double threshold) {
   const int n = 2 * (N + 1);
-  const double T = 1e-2 * 9007199254740992.0 / double(n);  // 2^53
+  const double T = threshold * 9007199254740992.0 / double(n);  // 2^53
   const double B = row_norm(c, k, L, N);
   if (!(B < __builtin_inf()) || !(B > 0.0)) return true;
   int cnt[2];
@@ -156,6 +158,7 @@ struct NoiseArgsDev {
   const int32_t* idx;
   int32_t* status;
   int64_t n_lam;
+  double threshold;
 };
 
 __global__ __launch_bounds__(kNoiseThreads) void noise_kernel(NoiseArgsDev a) {
@@ -173,7 +176,7 @@ __global__ __launch_bounds__(kNoiseThreads) void noise_kernel(NoiseArgsDev a) {
       if (d.valid && i < d.n_c) {
         const LayerRec64* L = a.layers64 + d.layer_base;
         const double c = a.c64[d.c_base + i - 1 + end];
-        if (c * c * L[d.n_layers].ib2 < 1.0) band = in_band(c, a.lam_k[g], L, d.n_layers);
+        if (c * c * L[d.n_layers].ib2 < 1.0) band = in_band(c, a.lam_k[g], L, d.n_layers, a.threshold);
       }
     }
   }
@@ -185,9 +188,9 @@ __global__ __launch_bounds__(kNoiseThreads) void noise_kernel(NoiseArgsDev a) {
 
 hipError_t launch_noise_check(const ModelDesc* models, const LayerRec64* layers64, const double* c64,
                               const double* lam_k, const int32_t* lam_model, const int32_t* idx,
-                              int32_t* status, int64_t n_lam, hipStream_t s) {
+                              int32_t* status, int64_t n_lam, double threshold, hipStream_t s) {
   if (n_lam <= 0) return hipSuccess;
-  NoiseArgsDev a{models, layers64, c64, lam_k, lam_model, idx, status, n_lam};
+  NoiseArgsDev a{models, layers64, c64, lam_k, lam_model, idx, status, n_lam, threshold};
   const int64_t blocks = (2 * n_lam + kNoiseThreads - 1) / kNoiseThreads;
   hipLaunchKernelGGL(noise_kernel, dim3(unsigned(blocks)), dim3(kNoiseThreads), 0, s, a);
   return hipGetLastError();

@@ -316,8 +316,8 @@ int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t fl
   sw.coop_window = ctx->shared_window;
   // A workgroup's first item comes from the deep end of the queue: it takes
   // issue precedence over items claimed later on the same compute unit.
-  sw.prio_hi = ctx->prio_hi >= 0 ? ctx->prio_hi : blocks;
-  sw.prio_mid = ctx->prio_mid >= 0 ? ctx->prio_mid : blocks;
+  sw.prio_hi = !ctx->first_item_priority ? 0 : ctx->prio_hi >= 0 ? ctx->prio_hi : blocks;
+  sw.prio_mid = !ctx->first_item_priority ? 0 : ctx->prio_mid >= 0 ? ctx->prio_mid : blocks;
   sw.models = p.models;
   sw.layers64 = p.layers64;
   sw.layers32 = p.layers32;
@@ -328,6 +328,7 @@ int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t fl
   sw.order = p.order;
   sw.n_items = int32_t(in.n_lam);
   sw.refine = (flags & MASW_NO_REFINE) ? 0 : 1;
+  sw.refine_rel = ctx->refine_rel;
   sw.counters = p.counters;
   MASW_HIP(hipEventRecord(T.ev[1], s));
   if (in.n_lam > 0) MASW_HIP(launch_sweep(mode, G, blocks, s, sw));
@@ -336,7 +337,7 @@ int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t fl
   // pick's bracket
   if ((flags & MASW_CHECK_NOISE) && in.n_lam > 0)
     MASW_HIP(launch_noise_check(p.models, p.layers64, p.c64, p.lam_k, p.lam_model, sw.out_idx, sw.out_status,
-                                in.n_lam, s));
+                                in.n_lam, ctx->noise_threshold, s));
   T.pending = true;
   ctx->tslot_last = ts;
   ctx->last = masw_stats{};
@@ -811,6 +812,45 @@ int masw_classify_picks(masw_ctx* ctx, const double* c_test, int32_t n_c, const 
   MASW_HIP(hipStreamSynchronize(s));
   ctx->last_stream = s;
   ctx->last_valid = true;
+  return MASW_OK;
+}
+
+int masw_set_opts(masw_ctx* ctx, const masw_opts* opts) {
+  masw_opts o{};
+  if (opts) o = *opts;
+  const double tol = o.refine_rel_tol == 0.0 ? kRefineRel : o.refine_rel_tol;
+  const double thr = o.noise_threshold == 0.0 ? 1e-2 : o.noise_threshold;
+  if (!(tol >= 1e-15 && tol <= 1e-3)) return fail(MASW_EINVAL, "opts: refine_rel_tol out of [1e-15, 1e-3]");
+  if (!(thr > 0.0 && thr <= 1.0)) return fail(MASW_EINVAL, "opts: noise_threshold out of (0, 1]");
+  const int g = o.waves_per_item;
+  if (!(g == 0 || g == 1 || g == 2 || g == 4 || g == 8 || g == 16))
+    return fail(MASW_EINVAL, "opts: waves_per_item must be 0, 1, 2, 4, 8 or 16");
+  if (!(o.shared_window == -1 || (o.shared_window >= 0 && o.shared_window <= 1024)))
+    return fail(MASW_EINVAL, "opts: shared_window must be -1 or in [0, 1024]");
+  if (!(o.first_item_priority == 0 || o.first_item_priority == -1))
+    return fail(MASW_EINVAL, "opts: first_item_priority must be 0 or -1");
+  if (o.reserved != 0) return fail(MASW_EINVAL, "opts: reserved must be 0");
+  if (!ctx) return fail(MASW_EINVAL, "ctx: null context");
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  ctx->refine_rel = tol;
+  ctx->noise_threshold = thr;
+  ctx->forced_waves = g;
+  ctx->shared_sweeps = o.shared_window != -1;
+  ctx->shared_window = o.shared_window > 0 ? o.shared_window : 8;
+  ctx->first_item_priority = o.first_item_priority == 0;
+  return MASW_OK;
+}
+
+int masw_get_opts(masw_ctx* ctx, masw_opts* out) {
+  if (!ctx || !out) return fail(MASW_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  masw_opts o{};
+  o.refine_rel_tol = ctx->refine_rel;
+  o.noise_threshold = ctx->noise_threshold;
+  o.waves_per_item = ctx->forced_waves;
+  o.shared_window = ctx->shared_sweeps ? ctx->shared_window : -1;
+  o.first_item_priority = ctx->first_item_priority ? 0 : -1;
+  *out = o;
   return MASW_OK;
 }
 

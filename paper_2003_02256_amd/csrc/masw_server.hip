@@ -453,6 +453,7 @@ int masw_server_start(masw_ctx* ctx, const masw_server_opts* opts) {
   ta.slot_remaining = s->remaining_dev;
   ta.counters = s->counters_dev;
   ta.refine = 1;
+  ta.refine_rel = ctx->refine_rel;
   void* dp = nullptr;
   if (hipHostGetDevicePointer(&dp, s->out_ct, 0) != hipSuccess) return bail("hipHostGetDevicePointer failed");
   ta.out_ct = static_cast<double*>(dp);

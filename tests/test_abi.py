@@ -197,3 +197,16 @@ def test_classify_validates_on_host(lib):
         with pytest.raises(M.MaswError) as e:
             call(**kwargs)
         assert e.value.code == M.MASW_EINVAL and msg in str(e.value), (kwargs, str(e.value))
+
+
+def test_opts_validate_on_host(lib):
+    for kwargs, msg in ((dict(refine_rel_tol=1e-16), "refine_rel_tol"), (dict(refine_rel_tol=0.5), "refine_rel_tol"),
+                        (dict(noise_threshold=2.0), "noise_threshold"), (dict(noise_threshold=-1.0), "noise_threshold"),
+                        (dict(waves_per_item=3), "waves_per_item"), (dict(shared_window=2000), "shared_window"),
+                        (dict(shared_window=-2), "shared_window"), (dict(first_item_priority=1), "first_item_priority"),
+                        (dict(), "ctx")):
+        with pytest.raises(M.MaswError) as e:
+            M.masw_set_opts(None, **kwargs)
+        assert e.value.code == M.MASW_EINVAL and msg in str(e.value), (kwargs, str(e.value))
+    out = M.masw_opts()
+    assert lib.masw_get_opts(None, ctypes.byref(out)) == M.MASW_EINVAL
