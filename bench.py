@@ -64,10 +64,10 @@ def classify_flops(evals: int, layers: int, steps: int) -> float:
 # sweep, CLASSIFY_SOURCES for the classification), the workload and the
 # launch, so a changed kernel reports null until it is measured again.
 MEASURED_TRAFFIC = {
-    ("d91a0541c3a7bed1", "fine_scale_N20_1000lam_115001c", "sweep_kernel<FP64,G=8>"):
-        5422.11 * 1024 * 2.000 + 2603.77 * 1024 * 1.000,
-    ("d91a0541c3a7bed1", "batch_4096models_19001c", "sweep_kernel<FP64,G=1>"):
-        266676.0 * 1024 * 2.000 + 147909.0 * 1024 * 1.000,
+    ("7a2fc7ee957a7c43", "fine_scale_N20_1000lam_115001c", "sweep_kernel<FP64,G=8>"):
+        5017.50 * 1024 * 2.000 + 2590.91 * 1024 * 1.000,
+    ("7a2fc7ee957a7c43", "batch_4096models_19001c", "sweep_kernel<FP64,G=1>"):
+        267019.0 * 1024 * 2.000 + 148251.0 * 1024 * 1.000,
     ("6da9bc50b01ce006", "classify_batch_4096models_19001c", "classify_kernel"):
         14642.625 * 1024 * 2.000 + 21872.34 * 1024 * 1.000,
 }

@@ -86,6 +86,21 @@ __device__ __forceinline__ int wave_first_change(int sg, int* sig_at, int* prev_
   return f;
 }
 
+// Sweep code of a grid point in the FP32 sweep: the determinant's sign code,
+// plus 4 when an odd number of layer denominators are negative.  The parity
+// flips where c crosses a pole of det K, so a pole crossing is a candidate
+// for the FP64 check even where FP32 gets the determinant's sign wrong next to
+// the pole (a zero and a pole within a grid step or two, on both sides of
+// which FP32 would otherwise see the same sign).
+__device__ __forceinline__ int sweep_code32(float c, float k, const LayerRec32* L, int N) {
+  int odd;
+  const int sg = det_sign_parity<float>(c, k, L, N, &odd);
+  return sg + 4 * odd;
+}
+
+// The determinant's sign code of a sweep code (kNoSign stays kNoSign).
+__device__ __forceinline__ int code_sign(int code) { return (code == kNoSign || code < 3) ? code : code - 4; }
+
 // ------------------------------------------------------------- staging --
 // Validation and per-layer records of model m by one wavefront, one layer
 // per lane.  With a.layer_off == nullptr the batch is a single model of
@@ -333,7 +348,7 @@ struct SweepShared {
   int last[G];
   int first[G];
   int pair[2];
-  int check[6];
+  int check[7];
   int coop[6];
 };
 
@@ -439,7 +454,7 @@ __device__ __forceinline__ int eval_round(const ItemRef& r, int rd, SweepShared<
     if constexpr (sizeof(T) == 8)
       sg = det_sign<double, false>(r.c64[i], r.k64, r.L64, r.N, nullptr);
     else
-      sg = det_sign<float, false>(r.c32[i], float(r.k64), r.L32, r.N, nullptr);
+      sg = sweep_code32(r.c32[i], float(r.k64), r.L32, r.N);
   }
   *s0 = sg;
   return round_first_change<G>(sg, kNoSign, sh.last, sh.first, sh.pair, sl, sa, pa);
@@ -581,8 +596,11 @@ __device__ int coop_sweep(const ItemRef& r, const CoopRef& co, SweepShared<G>& s
 // just before the window must equal the sign FP32 saw since the last
 // FP64-confirmed point (likewise at the end of the grid before reporting no
 // change).  If it does not, FP32 missed a change and the item continues as
-// an FP64 sweep from that point, so the split pick equals the FP64 pick
-// unless FP32 misses an even number of changes between confirmed points.
+// an FP64 sweep from that point.  A change of the parity of negative layer
+// denominators (a pole crossing, next to which FP32 signs are least
+// reliable) is a candidate too.  So the split pick equals the FP64 pick
+// unless FP32 misses an even number of changes between confirmed points with
+// no pole crossing among them.
 template <int MODE, int G>
 __device__ bool run_item(const ItemRef& r, ItemState& st, int budget, SweepShared<G>& sh, WorkCount& wc,
                          const ItemOut& o, const CoopRef& co, Counters* cnt) {
@@ -612,7 +630,7 @@ __device__ bool run_item(const ItemRef& r, ItemState& st, int budget, SweepShare
           write_missing<G>(o, MASW_STATUS_INVALID);
           return true;
         }
-        if (cand >= 0) fp32_before = p_c;
+        if (cand >= 0) fp32_before = code_sign(p_c);
       } else {
         for (int base = start; base < n_c; base += P) {
           if (rounds == budget) {
@@ -624,13 +642,13 @@ __device__ bool run_item(const ItemRef& r, ItemState& st, int budget, SweepShare
           }
           ++rounds;
           const int i = base + tid;
-          const int sg = (i < n_c) ? det_sign<float, false>(r.c32[i], k32, r.L32, r.N, nullptr) : kNoSign;
+          const int sg = (i < n_c) ? sweep_code32(r.c32[i], k32, r.L32, r.N) : kNoSign;
           int s_c, p_c;
           const int f = round_first_change<G>(sg, carry, sh.last, sh.first, sh.pair, &carry, &s_c, &p_c);
           wc.sweep += (unsigned long long)min(P, n_c - base);
           if (f >= 0) {
             cand = base + f;
-            fp32_before = p_c;
+            fp32_before = code_sign(p_c);
             break;
           }
         }
@@ -644,10 +662,11 @@ __device__ bool run_item(const ItemRef& r, ItemState& st, int budget, SweepShare
       const int ws = at_end ? n_c : max(1, cand - 48);
       if (wave == 0) {
         const int i = ws - 1 + lane;
-        int sg = kNoSign;
-        if (at_end ? lane == 0 : i < n_c) sg = det_sign<double, false>(r.c64[i], r.k64, r.L64, r.N, nullptr);
+        int sg = kNoSign, odd = 0;
+        if (at_end ? lane == 0 : i < n_c) sg = det_sign_parity<double>(r.c64[i], r.k64, r.L64, r.N, &odd);
         int last, s_c = 0, p_c = 0;
         const int f = at_end ? -1 : wave_first_change(sg, &s_c, &p_c, &last);
+        if (lane == 63) sh.check[6] = (sg == kNoSign) ? kNoSign : sg + 4 * odd;  // sweep code of the window's end
         if (at_end && lane == 1) sh.check[5] = det_sign<float, false>(r.c32[n_c - 1], k32, r.L32, r.N, nullptr);
         if (lane == 0) {
           sh.check[0] = f;
@@ -662,6 +681,7 @@ __device__ bool run_item(const ItemRef& r, ItemState& st, int budget, SweepShare
       const int last = sh.check[1];
       const int first64 = sh.check[4];
       const int fp32_last = sh.check[5];
+      const int last_code = sh.check[6];
       sig_f = sh.check[2];
       prev_f = sh.check[3];
       __syncthreads();
@@ -686,7 +706,8 @@ __device__ bool run_item(const ItemRef& r, ItemState& st, int budget, SweepShare
       // leaves nothing to search.
       start = ws + 63;
       if (start >= n_c) break;
-      carry = seg_carry = last;
+      seg_carry = last;
+      carry = last_code;
       seg_start = start;
     }
   }

@@ -234,6 +234,28 @@ __device__ __forceinline__ int det_sign(T c, T k, const LayerRec<T>* __restrict_
   return sign_code(neg, double(re));
 }
 
+// As det_sign, also returning in *odd whether an odd number of the layer
+// denominators D_j are negative.  That parity flips where c crosses a pole of
+// det K (one D_j changes sign there).
+template <typename T>
+__device__ __forceinline__ int det_sign_parity(T c, T k, const LayerRec<T>* __restrict__ L, int N, int* odd) {
+  const T c2 = c * c;
+  Block2<T> S{T(0), T(0), T(0)};
+  bool neg = false, par = false;
+  for (int j = 0; j < N; ++j) {
+    const LayerRec<T> rec = load_rec<T>(L, j);
+    const LayerK<T> K = layer_entries<T>(c2, k * rec.h, rec.ia2, rec.ib2, rec.rh, rec.mh);
+    par ^= (K.gD < T(0));
+    const T d = schur_layer<T>(S, K);
+    neg ^= (d < T(0));
+  }
+  const LayerRec<T> hs = load_rec<T>(L, N);
+  T re, im;
+  halfspace_det<T>(S, c2, hs.ia2, hs.ib2, hs.mh, &re, &im);
+  *odd = par ? 1 : 0;
+  return sign_code(neg, double(re));
+}
+
 // As det_sign, also returning ln|det K| of the unscaled matrix:
 // sum_j ln|det S_j| + ln|det S_N| + 2(N+1) ln(k mu_ref).
 template <typename T>

@@ -536,3 +536,21 @@ def test_uniform_curves(torch_dev, ctx, c_pick):
     sig, _ = ctx.sign_map(c, lam[:3], m, M.MASW_PREC_FP64, want_log=False)
     for row in sig:
         assert int(np.nonzero(row[1:] != row[:-1])[0][0]) + 1 == want
+
+
+def test_split_catches_a_mode_next_to_a_pole(torch_dev, ctx):
+    # A mode at 67.98 m/s and a pole one grid step later: FP32 takes the wrong
+    # sign between them and sees no change.  The FP32 sweep also watches the
+    # parity of negative layer denominators, so the pole crossing sends the
+    # region to the FP64 check, and the split pick is the oracle's.
+    g = _golden("split_pole_case.json")
+    m = WL.Model(np.array(g["h"]), np.array(g["alpha"]), np.array(g["beta"]), np.array(g["rho"]))
+    lam = np.array([g["lambda"]])
+    c = WL.serving_grid()
+    want_ref = float(g["c_ref"])
+    for prec in (M.MASW_PREC_FP64, M.MASW_PREC_SPLIT):
+        ct, idx, st, cr = dev_curve(torch_dev, ctx, c, lam, m, prec)
+        assert (int(idx[0]), int(st[0])) == (g["idx"], g["status"]), (prec, idx, st)
+        assert abs(cr[0] - want_ref) <= REL_TOL * want_ref
+    cls, sec = ctx.classify(c, [m], [lam], idx)
+    assert int(cls[0]) == g["class"] == M.MASW_PICK_MODE
