@@ -554,3 +554,17 @@ def test_split_catches_a_mode_next_to_a_pole(torch_dev, ctx):
         assert abs(cr[0] - want_ref) <= REL_TOL * want_ref
     cls, sec = ctx.classify(c, [m], [lam], idx)
     assert int(cls[0]) == g["class"] == M.MASW_PICK_MODE
+
+
+def test_budget_exhaustion_is_refused_before_any_work(gpu):
+    # a request whose workspace exceeds the context's budget fails with
+    # MASW_ENOMEM before anything is queued, and the context stays usable
+    wl = WL.fine_scale_case()
+    small = WL.two_layer_case()
+    with M.Context(0, 1 << 20) as c:        # the fine-scale curve needs about 1.4 MB
+        with pytest.raises(M.MaswError) as e:
+            c.curve(wl.c_test, wl.lambdas[0], wl.models[0])
+        assert e.value.code == M.MASW_ENOMEM and "budget" in str(e.value)
+        got = c.curve(small.c_test, small.lambdas[0], small.models[0])
+        want = [O.dispersion_point(l, small.c_test, small.models[0], refine=False).idx for l in small.lambdas[0][:5]]
+        assert got[1][:5].tolist() == want

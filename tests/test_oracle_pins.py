@@ -520,3 +520,22 @@ def test_sign_relation_holds_across_a_thick_layer():
         sD = (-1) ** bin(O.pole_mask(k, c, m)).count("1")
         vals.add(int(sk) * sD * PR._sgn(PR.secular(k, c, m)))
     assert vals == {1}
+
+
+# ---------------------------------------------------------------------------
+# Normal dispersion: for velocity-increasing profiles the first-mode phase
+# velocity does not decrease with wavelength (Section 3.2 observes the
+# curves of its data falling with decreasing wavelength)
+# ---------------------------------------------------------------------------
+def test_normal_dispersion_of_stored_oracle_curves():
+    import json
+    import os
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    fine = json.load(open(os.path.join(here, "fine_scale.json")))
+    assert np.all(np.diff(np.array(fine["idx"])) >= 0)        # wavelengths ascending, picks never fall
+    batch = json.load(open(os.path.join(here, "batch_sample.json")))
+    inverted = WL.batch_case().meta["inverted"]
+    falling = [e["model"] for e in batch["models"] if np.any(np.diff(np.array(e["idx"])) < 0)]
+    # only models with a low-velocity layer may disperse inversely
+    assert all(inverted[m] for m in falling)
+    assert any(not inverted[e["model"]] for e in batch["models"])
