@@ -96,6 +96,20 @@ typedef int32_t masw_precision;
                                   pick's bracket for the FP64 noise band and
                                   set MASW_FLAG_NOISE (an extra kernel after
                                   the sweep; not in its timing)               */
+#define MASW_SEARCH_INERTIA 0x8u /* masw_dispersion_curve / _batch, FP64
+                                  only: find each pick by a search on
+                                  inertia counts instead of walking the grid
+                                  (Algorithm 1's early-exit scan).  Below the
+                                  half-space's S velocity K is real symmetric
+                                  and sign(det K) = (-1)^(negative eigenvalues);
+                                  that count plus twice the number of
+                                  fixed-face layer modes below c does not
+                                  decrease along c (Wittrick-Williams), so the
+                                  grid points whose counts prove the sign
+                                  constant are skipped.  Same outputs as the
+                                  walk outside the FP64 noise band; grid points
+                                  at or above that velocity are walked.
+                                  MASW_PREC_SPLIT with it: MASW_EINVAL        */
 
 /* Limits. */
 #define MASW_MAX_LAYERS 1024   /* finite layers per model                    */
@@ -170,6 +184,11 @@ typedef struct {
                                  multisection round, 64 per round)            */
     uint64_t classify_layers; /* layers crossed by those evaluations           */
     uint64_t classify_steps;  /* propagator steps taken by those evaluations   */
+    /* With MASW_SEARCH_INERTIA (sweep_evals then counts the grid points
+     * walked, check_evals the determinant signs at the changes of the count): */
+    uint64_t inertia_evals;   /* inertia counts evaluated                      */
+    uint64_t inertia_entries; /* layer and sublayer element matrices formed    */
+    uint64_t inertia_pivots;  /* 2x2 block pivots eliminated                   */
 } masw_stats;
 
 /* Options of a context.  A zero field keeps its default, so a

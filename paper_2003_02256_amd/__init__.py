@@ -46,6 +46,7 @@ MASW_PREC_SPLIT = 1
 MASW_DEVICE_PTRS = 0x1
 MASW_NO_REFINE = 0x2
 MASW_CHECK_NOISE = 0x4
+MASW_SEARCH_INERTIA = 0x8
 MASW_MAX_LAYERS = 1024
 
 
@@ -82,7 +83,9 @@ class masw_stats(ctypes.Structure):
                 ("workgroups", ctypes.c_int32), ("sweep_ms", ctypes.c_float), ("total_ms", ctypes.c_float),
                 ("shared_items", ctypes.c_int32), ("shared_stalls", ctypes.c_uint32),
                 ("helper_evals", ctypes.c_uint64), ("classify_evals", ctypes.c_uint64),
-                ("classify_layers", ctypes.c_uint64), ("classify_steps", ctypes.c_uint64)]
+                ("classify_layers", ctypes.c_uint64), ("classify_steps", ctypes.c_uint64),
+                ("inertia_evals", ctypes.c_uint64), ("inertia_entries", ctypes.c_uint64),
+                ("inertia_pivots", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}

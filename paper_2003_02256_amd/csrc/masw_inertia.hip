@@ -1,0 +1,274 @@
+// First sign change of det K by inertia counts (opt-in: MASW_SEARCH_INERTIA).
+//
+// Algorithm 1 walks the c grid and stops at the first grid point where
+// sign(det K) differs from the previous one.  Below the half-space's S
+// velocity K is real symmetric, and sign(det K) = (-1)^s with s(c) the number
+// of negative eigenvalues of K(c), so the pick is the first grid point where
+// the parity of s differs from its parity at c_test[0].  s is not monotone in
+// c, but it is one of two monotone counts (the Wittrick-Williams theorem,
+// Wittrick and Williams 1971, for the exact dynamic stiffness of a
+// conservative system, here with wavenumber k fixed and frequency kc rising):
+//     J(c) = s(c) + P(c) = the number of modes with phase velocity below c,
+//     P(c) = sum_j P_j(c), P_j = modes of layer j with both faces fixed
+//            (the poles of det K, where D_j changes sign) below c.
+// E = J + P = s + 2P is non-decreasing, and s changes only where E does, so
+// the first change of sign(det K) along the grid is found by a search on E
+// instead of a walk:
+//   1. Multisection of (a, b] (a with E = E_a known, b = the last grid point):
+//      the 64 lanes of a wavefront count E at 64 spread grid points, and the
+//      first lane whose count differs from E_a gives the next (a, b], 64
+//      times narrower; three rounds reach one grid step on 115,001 points.
+//   2. At the first grid point b where E changed, det K's sign is evaluated
+//      as the walk would.  If it differs from the sign at c_test[0] that is
+//      the pick.  Otherwise (a mode and a pole in one grid step, or two
+//      modes) the search restarts from a = b.
+//   3. A grid point at or above the half-space's S velocity (K complex) or
+//      one where an elimination is not finite counts as a change of E.  If
+//      the search stops at such a point with the sign unchanged, the rest of
+//      the grid is walked as in Algorithm 1.
+// No grid point below the pick is skipped unless the counts at its ends
+// prove that sign(det K) is constant there, so the pick is the walk's, up to
+// rounding of the counts (the FP64 noise band).  Sign changes between two
+// counted points that cancel in E cannot happen; a determinant that is
+// exactly zero or not finite at a grid point that is not counted is not seen.
+//
+// P_j from the layer alone.  With both faces fixed, a layer's displacement
+// field vanishes at z = 0 and z = h, so its strain energy is at least
+// mu (k^2 + (pi/h)^2) times the integral of |u|^2 (the (lambda + mu)|div u|^2
+// term is non-negative, and Wirtinger's inequality bounds |u_z'|^2), and the
+// layer has no fixed-face mode with c^2 <= beta^2 (1 + (pi/(kh))^2).  So
+// P_j(c) = 0 when k h sqrt(c^2/beta^2 - 1) <= pi.  Otherwise the layer is cut
+// into m = floor(k h sqrt(c^2/beta^2 - 1)/pi) + 1 equal sublayers, none of
+// which has such a mode below c, and the theorem applied to the layer with
+// both faces fixed gives P_j = the number of negative eigenvalues of the
+// stiffness of the m - 1 interior interfaces: the same unpivoted 2x2-block
+// elimination, m - 1 pivots of one sublayer's element matrix.
+//
+// Each count costs one elimination of K plus, per layer above that bound,
+// one more element matrix and m - 1 pivots, against Algorithm 1's one
+// elimination per grid point up to the pick.  One wavefront per wavelength.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "masw.h"
+#include "masw_host.hpp"
+#include "masw_internal.hpp"
+#include "masw_math.hpp"
+#include "masw_pick.hpp"
+
+namespace masw {
+namespace {
+
+constexpr int kInertiaWaves = 4;        // wavefronts (wavelengths) per workgroup
+constexpr int kEvent = 0x7fffffff;      // count of a point that ends the search on E
+constexpr double kMaxSub = 4096.0;      // sublayers of one layer before a point counts as kEvent
+constexpr double kInvPi = 0.318309886183790671537767526745028724;
+
+// Work of one wavefront.  evals, entries and pivots are per lane (each lane
+// counts its own points); the rest are uniform across the wavefront.
+struct Tally {
+  unsigned long long evals = 0, entries = 0, pivots = 0, scan = 0, check = 0, refine = 0, useful = 0;
+};
+
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Negative eigenvalues of a symmetric 2x2 pivot with (1,1) entry a and
+// determinant d != 0.
+__device__ __forceinline__ int neg_eigs(double a, double d) { return d < 0.0 ? 1 : (a < 0.0 ? 2 : 0); }
+
+__device__ __forceinline__ bool usable(double d) { return d != 0.0 && __builtin_fabs(d) < __builtin_inf(); }
+
+// E(c) = s(c) + 2 P(c), or kEvent (c at or above the half-space's S velocity,
+// a zero or non-finite pivot, or a layer that would need more than kMaxSub
+// sublayers).  The work is added to t if `tally`.
+__device__ int count_E(double c, double k, const LayerRec64* __restrict__ L, int N, Tally& t, bool tally) {
+  const double c2 = c * c;
+  const LayerRec<double> hs = load_rec<double>(L, N);
+  if (!(c2 * hs.ib2 < 1.0)) return kEvent;
+  unsigned long long entries = unsigned(N), pivots = unsigned(N + 1);
+  Block2<double> S{0.0, 0.0, 0.0};
+  int s = 0, P = 0;
+  bool ok = true;
+  for (int j = 0; j < N; ++j) {
+    const LayerRec<double> rec = load_rec<double>(L, j);
+    const double kh = k * rec.h;
+    const LayerK<double> K = layer_entries<double>(c2, kh, rec.ia2, rec.ib2, rec.rh, rec.mh);
+    const double a = S.s11 + K.k11;
+    const double d = schur_layer<double>(S, K);
+    ok = ok && usable(d);
+    s += neg_eigs(a, d);
+    const double x = c2 * rec.ib2 - 1.0;
+    if (x > 0.0) {
+      const double q = kh * __builtin_sqrt(x) * kInvPi;
+      if (q >= 1.0) {
+        if (!(q < kMaxSub)) {
+          ok = false;
+        } else {
+          const int m = int(q) + 1;
+          const LayerK<double> Ks = layer_entries<double>(c2, kh / double(m), rec.ia2, rec.ib2, rec.rh, rec.mh);
+          Block2<double> R{Ks.k11, -Ks.k12, Ks.k22};  // the first sublayer's share of interface 1
+          for (int i = 1; i < m; ++i) {
+            const double a2 = R.s11 + Ks.k11;
+            const double d2 = schur_layer<double>(R, Ks);
+            ok = ok && usable(d2);
+            P += neg_eigs(a2, d2);
+          }
+          ++entries;
+          pivots += (unsigned long long)(m - 1);
+        }
+      }
+    }
+  }
+  double re, im, ar;
+  halfspace_det<double>(S, c2, hs.ia2, hs.ib2, hs.mh, &re, &im, &ar);
+  ok = ok && usable(re);
+  s += neg_eigs(ar, re);
+  if (tally) {
+    ++t.evals;
+    t.entries += entries;
+    t.pivots += pivots;
+  }
+  return ok ? s + 2 * P : kEvent;
+}
+
+// Algorithm 1's walk from grid index `start`, whose predecessor has sign
+// `carry`, one grid point per lane.  Returns the index of the first change
+// (-1 if none) and its signs.
+__device__ int walk(const double* c64, int n_c, double k, const LayerRec64* L, int N, int start, int carry,
+                    int* sig_f, int* prev_f, Tally& t) {
+  const int lane = threadIdx.x & 63;
+  for (int base = start; base < n_c; base += 64) {
+    const int i = base + lane;
+    const int sg = (i < n_c) ? det_sign<double, false>(c64[i], k, L, N, nullptr) : kNoSign;
+    const int up = __shfl_up(sg, 1, 64);
+    const int prev = (lane == 0) ? carry : up;
+    const bool change = (sg != kNoSign) && (prev != kNoSign) && (sg != prev);
+    const unsigned long long mask = __ballot(change);
+    t.scan += (unsigned long long)min(64, n_c - base);
+    if (mask) {
+      const int f = __ffsll((long long)mask) - 1;
+      *sig_f = __shfl(sg, f, 64);
+      *prev_f = __shfl(prev, f, 64);
+      return base + f;
+    }
+    carry = __shfl(sg, 63, 64);
+  }
+  return -1;
+}
+
+// The pick of one wavelength (-1: none), with the determinant signs at it and
+// at its predecessor.
+__device__ int search(const double* c64, int n_c, double k, const LayerRec64* L, int N, int* sig_f, int* prev_f,
+                      Tally& t) {
+  const int lane = threadIdx.x & 63;
+  // sign and count at c_test[0] (every lane computes the same)
+  const int sig0 = det_sign<double, false>(c64[0], k, L, N, nullptr);
+  ++t.check;
+  int E_a = count_E(c64[0], k, L, N, t, lane == 0);
+  if (E_a == kEvent) return walk(c64, n_c, k, L, N, 1, sig0, sig_f, prev_f, t);
+  int a = 0;
+  for (;;) {
+    // first grid point in (a, n_c - 1] whose count differs from E_a
+    int lo = a, hi = n_c - 1, E_hi = kEvent;
+    bool any = false;
+    while (hi > lo + 1 || !any) {
+      const int n = hi - lo;
+      const int p = (n <= 64) ? lo + 1 + lane : lo + int((int64_t(n) * (lane + 1)) >> 6);
+      const bool valid = (n <= 64) ? (lane < n) : true;
+      const int E = valid ? count_E(c64[p], k, L, N, t, true) : E_a;
+      const unsigned long long mask = __ballot(valid && E != E_a);
+      if (!mask) {
+        // No change of E after a: sign(det K) is constant to the end.  (With
+        // `any`, hi's count differed in an earlier round and cannot agree now;
+        // walking from lo + 1, whose predecessor has sign sig0, is the
+        // fallback that needs no such argument.)
+        if (any) return walk(c64, n_c, k, L, N, lo + 1, sig0, sig_f, prev_f, t);
+        return -1;
+      }
+      any = true;
+      const int f = __ffsll((long long)mask) - 1;
+      const int p_f = __shfl(p, f, 64);
+      const int p_before = (f == 0) ? lo : __shfl(p, f - 1, 64);
+      E_hi = __shfl(E, f, 64);
+      hi = p_f;
+      lo = p_before;
+    }
+    // hi = lo + 1 is the first grid point after a where E changed
+    const int sg = det_sign<double, false>(c64[hi], k, L, N, nullptr);
+    ++t.check;
+    if (sg != sig0) {
+      *sig_f = sg;
+      *prev_f = sig0;
+      return hi;
+    }
+    if (E_hi == kEvent) return walk(c64, n_c, k, L, N, hi + 1, sig0, sig_f, prev_f, t);
+    a = hi;
+    E_a = E_hi;
+  }
+}
+
+__global__ __launch_bounds__(64 * kInertiaWaves) void inertia_kernel(SweepArgs a) {
+  __shared__ unsigned long long s_cnt[kInertiaWaves][7];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = blockIdx.x * kInertiaWaves + wave;
+  Tally t;
+  if (g < a.n_items) {
+    const int m = __builtin_amdgcn_readfirstlane(a.lam_model[g]);
+    const ModelDesc d = a.models[m];
+    const ItemOut o{a.out_ct + g, a.out_idx + g, a.out_status + g, a.out_cref ? a.out_cref + g : nullptr, a.refine,
+                    a.refine_rel};
+    const double k = a.lam_k[g];
+    const int n_c = __builtin_amdgcn_readfirstlane(d.n_c);
+    if (!(k == k)) {  // invalid model, grid or wavelength
+      write_no_pick(o, MASW_STATUS_INVALID, lane == 0);
+    } else {
+      const int N = __builtin_amdgcn_readfirstlane(d.n_layers);
+      const double* c64 = a.c64 + __builtin_amdgcn_readfirstlane(d.c_base);
+      const LayerRec64* L = a.layers64 + __builtin_amdgcn_readfirstlane(d.layer_base);
+      int sig_f = 0, prev_f = 0;
+      const int found = search(c64, n_c, k, L, N, &sig_f, &prev_f, t);
+      if (found < 0) {
+        write_no_pick(o, MASW_STATUS_NOT_FOUND, lane == 0);
+        t.useful = (unsigned long long)n_c;
+      } else {
+        t.useful = (unsigned long long)(found + 1);
+        t.refine = refine_and_write(o, c64, k, L, N, found, sig_f, prev_f);
+      }
+    }
+  }
+  const unsigned long long evals = wave_sum(t.evals), entries = wave_sum(t.entries), pivots = wave_sum(t.pivots);
+  if (lane == 0) {
+    s_cnt[wave][0] = evals;
+    s_cnt[wave][1] = entries;
+    s_cnt[wave][2] = pivots;
+    s_cnt[wave][3] = t.scan;
+    s_cnt[wave][4] = t.check;
+    s_cnt[wave][5] = t.refine;
+    s_cnt[wave][6] = t.useful;
+  }
+  __syncthreads();
+  if (threadIdx.x < 7) {
+    unsigned long long sum = 0;
+    for (int w = 0; w < kInertiaWaves; ++w) sum += s_cnt[w][threadIdx.x];
+    Counters* c = a.counters;
+    unsigned long long* dst[7] = {&c->inertia_evals, &c->inertia_entries, &c->inertia_pivots, &c->sweep,
+                                  &c->check,         &c->refine,          &c->useful};
+    if (sum) atomicAdd(dst[threadIdx.x], sum);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_inertia(const SweepArgs& a, hipStream_t s) {
+  if (a.n_items <= 0) return hipSuccess;
+  const int64_t blocks = (int64_t(a.n_items) + kInertiaWaves - 1) / kInertiaWaves;
+  hipLaunchKernelGGL(inertia_kernel, dim3(unsigned(blocks)), dim3(64 * kInertiaWaves), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace masw

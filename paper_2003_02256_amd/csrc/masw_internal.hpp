@@ -63,6 +63,9 @@ struct alignas(64) Counters {
   unsigned long long check;   // FP64 re-check evaluations
   unsigned long long refine;  // refinement evaluations
   unsigned long long helper;  // sweep evaluations done by joining workgroups
+  unsigned long long inertia_evals;    // inertia counts (MASW_SEARCH_INERTIA)
+  unsigned long long inertia_entries;  // layer and sublayer element matrices formed by them
+  unsigned long long inertia_pivots;   // 2x2 block pivots eliminated by them
   uint32_t hist[kBuckets];    // work-order histogram, then bucket offsets
 };
 

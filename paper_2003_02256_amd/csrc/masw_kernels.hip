@@ -22,6 +22,7 @@
 
 #include "masw_internal.hpp"
 #include "masw_math.hpp"
+#include "masw_pick.hpp"
 
 namespace masw {
 
@@ -66,24 +67,6 @@ __device__ __forceinline__ int round_first_change(int sg, int prev0, int* s_last
   }
   __syncthreads();
   return first;
-}
-
-// First sign change among the 64 lanes of one wavefront, lane l holding
-// consecutive position l; lane 0 has no predecessor.  Every wavefront that
-// calls it with the same signs gets the same answer, with no LDS or barrier.
-// Returns the uniform lane of the first change or -1; *sig_at / *prev_at
-// receive the signs at the change and *last the sign of lane 63.
-__device__ __forceinline__ int wave_first_change(int sg, int* sig_at, int* prev_at, int* last) {
-  const int lane = threadIdx.x & 63;
-  const int prev = __shfl_up(sg, 1, 64);
-  const bool change = (lane > 0) && (sg != kNoSign) && (prev != kNoSign) && (sg != prev);
-  const unsigned long long mask = __ballot(change);
-  *last = __shfl(sg, 63, 64);
-  if (!mask) return -1;
-  const int f = __ffsll((long long)mask) - 1;
-  *sig_at = __shfl(sg, f, 64);
-  *prev_at = __shfl(prev, f, 64);
-  return f;
 }
 
 // Sweep code of a grid point in the FP32 sweep: the determinant's sign code,
@@ -366,24 +349,9 @@ struct ItemRef {
   const LayerRec32* L32;
 };
 
-// Output slots of one item.
-struct ItemOut {
-  double* ct;
-  int32_t* idx;
-  int32_t* status;
-  double* cref;  // may be null
-  int refine;
-  double refine_rel;  // refinement bracket width / c_hi
-};
-
 template <int G>
 __device__ __forceinline__ void write_missing(const ItemOut& o, int status) {
-  if (threadIdx.x == 0) {
-    *o.idx = -1;
-    *o.status = status;
-    *o.ct = __builtin_nan("");
-    if (o.cref) *o.cref = __builtin_nan("");
-  }
+  write_no_pick(o, status, threadIdx.x == 0);
 }
 
 // ------------------------------------------------- shared (cooperative) sweep --
@@ -748,42 +716,7 @@ __device__ bool run_item(const ItemRef& r, ItemState& st, int budget, SweepShare
   // Refinement and output by wavefront 0 alone; the others go on to the
   // next barrier.  One wavefront at a time on a SIMD finishes these few
   // rounds sooner than the whole group sharing the SIMDs would.
-  if (wave == 0) {
-    int status = MASW_STATUS_FOUND;
-    if (sig_f == kNaNSign || prev_f == kNaNSign) status = MASW_STATUS_NAN;
-    double c_ref = __builtin_nan("");
-    if (status == MASW_STATUS_FOUND) {
-      // FP64 multisection of [c[found-1], c[found]]: 64 points per round,
-      // both ends included, one per lane; the new bracket is the first sign
-      // change.  The first round also yields the layer-denominator sign
-      // masks at the two grid points (pole flag).
-      double lo = r.c64[found - 1], hi = r.c64[found];
-      const double tol = o.refine_rel * hi;
-      for (int k = 0; k < 24; ++k) {
-        const double w = hi - lo;
-        const double c = (lane == 63) ? hi : lo + w * (double(lane) / 63.0);
-        uint64_t dm = 0;
-        const int sg = det_sign<double, true>(c, r.k64, r.L64, r.N, &dm);
-        if (k == 0 && __shfl(dm, 0, 64) != __shfl(dm, 63, 64)) status |= MASW_FLAG_POLE;
-        int s_c = 0, p_c = 0, unused;
-        const int f = wave_first_change(sg, &s_c, &p_c, &unused);
-        wc.refine += 64ull;
-        if (f < 0 || s_c == kNaNSign || p_c == kNaNSign) break;
-        const double nhi = (f == 63) ? hi : lo + w * (double(f) / 63.0);
-        const double nlo = lo + w * (double(f - 1) / 63.0);
-        lo = nlo;
-        hi = nhi;
-        if (!o.refine || hi - lo <= tol) break;
-      }
-      if (o.refine) c_ref = 0.5 * (lo + hi);
-    }
-    if (tid == 0) {
-      *o.idx = found;
-      *o.status = status;
-      *o.ct = r.c64[found];
-      if (o.cref) *o.cref = c_ref;
-    }
-  }
+  if (wave == 0) wc.refine += refine_and_write(o, r.c64, r.k64, r.L64, r.N, found, sig_f, prev_f);
   return true;
 }
 

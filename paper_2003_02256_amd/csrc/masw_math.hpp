@@ -157,10 +157,10 @@ __device__ __forceinline__ T schur_layer(Block2<T>& S, const LayerK<T>& K) {
 //     h12 = mh ((1 - s^2)/(1 - r s) - 2),
 // where r and s are taken on the principal branch from their real squares
 // (x < 0 gives +i sqrt(-x)).  H is complex only above the half-space's S
-// velocity.
+// velocity.  With a_out, *a_out receives Re of the (1,1) entry of S_N.
 template <typename T>
 __device__ __forceinline__ void halfspace_det(const Block2<T>& S, T c2, T ia2, T ib2, T mh,
-                                              T* re, T* im) {
+                                              T* re, T* im, T* a_out = nullptr) {
   const T xr = T(1) - c2 * ia2;
   const T xs = T(1) - c2 * ib2;
   const T qr = sqrt_<T>(xr < T(0) ? -xr : xr);  // may be exactly 0 (c = alpha)
@@ -180,6 +180,7 @@ __device__ __forceinline__ void halfspace_det(const Block2<T>& S, T c2, T ia2, T
   const T er = S.s12 + h12r, ei = h12i;
   *re = ar * br - ai * bi - (er * er - ei * ei);
   *im = ar * bi + ai * br - T(2) * er * ei;
+  if (a_out) *a_out = ar;
 }
 
 // Layer records are read-only for a whole launch and uniform across a

@@ -278,16 +278,18 @@ int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t fl
   }
   if (!b.ok()) return fail(MASW_ENOMEM, "workspace exceeds the HBM budget");
 
+  const bool inertia = (flags & MASW_SEARCH_INERTIA) != 0;
   const int mode = prec == MASW_PREC_SPLIT ? 1 : 0;
   int blocks = 1;
-  const int G = pick_waves_per_item(ctx, mode, in.n_lam, &blocks);
+  const int G = inertia ? 1 : pick_waves_per_item(ctx, mode, in.n_lam, &blocks);
+  if (inertia) blocks = int((in.n_lam + 3) / 4);
 
   // Shared sweeps when items are few enough that the deepest ones decide the
   // launch time: every item, with one summary word per round of its grid,
   // if that fits in what is left of the budget.
   CoopInitArgs ci{};
   const int64_t stride = (int64_t(in.n_c) + 64 * G - 1) / (64 * G);
-  if (ctx->shared_sweeps && blocks > 1 && in.n_lam > 0 && in.n_lam <= 4 * int64_t(blocks)) {
+  if (!inertia && ctx->shared_sweeps && blocks > 1 && in.n_lam > 0 && in.n_lam <= 4 * int64_t(blocks)) {
     const size_t save = b.off;
     ci.n_coop = int32_t(in.n_lam);
     ci.coop = b.take<CoopItem>(size_t(ci.n_coop));
@@ -331,7 +333,7 @@ int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t fl
   sw.refine_rel = ctx->refine_rel;
   sw.counters = p.counters;
   MASW_HIP(hipEventRecord(T.ev[1], s));
-  if (in.n_lam > 0) MASW_HIP(launch_sweep(mode, G, blocks, s, sw));
+  if (in.n_lam > 0) MASW_HIP(inertia ? launch_inertia(sw, s) : launch_sweep(mode, G, blocks, s, sw));
   MASW_HIP(hipEventRecord(T.ev[2], s));
   // optional diagnostic after the timed sweep: the FP64 noise band of each
   // pick's bracket
@@ -366,7 +368,10 @@ int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t fl
 
 int check_common(masw_ctx* ctx, masw_precision prec, uint32_t flags) {
   if (prec != MASW_PREC_FP64 && prec != MASW_PREC_SPLIT) return fail(MASW_EINVAL, "prec: unknown precision");
-  if (flags & ~(MASW_DEVICE_PTRS | MASW_NO_REFINE | MASW_CHECK_NOISE)) return fail(MASW_EINVAL, "flags: unknown bits");
+  if (flags & ~(MASW_DEVICE_PTRS | MASW_NO_REFINE | MASW_CHECK_NOISE | MASW_SEARCH_INERTIA))
+    return fail(MASW_EINVAL, "flags: unknown bits");
+  if ((flags & MASW_SEARCH_INERTIA) && prec != MASW_PREC_FP64)
+    return fail(MASW_EINVAL, "flags: MASW_SEARCH_INERTIA needs MASW_PREC_FP64");
   if (!ctx) return fail(MASW_EINVAL, "ctx: null context");
   return MASW_OK;
 }
@@ -882,6 +887,9 @@ int masw_get_stats(masw_ctx* ctx, masw_stats* out) {
     ctx->last.check_evals = c.check;
     ctx->last.refine_evals = c.refine;
     ctx->last.helper_evals = c.helper;
+    ctx->last.inertia_evals = c.inertia_evals;
+    ctx->last.inertia_entries = c.inertia_entries;
+    ctx->last.inertia_pivots = c.inertia_pivots;
     ctx->last.shared_stalls = c.coop_stall;
     if (ctx->tslot_last >= 0) {
       masw_ctx::TimingSlot& T = ctx->tslot[ctx->tslot_last];

@@ -20,6 +20,7 @@ static hipError_t reached(const char* what) {
 int sweep_blocks_per_cu(int, int) { return 1; }
 int tick_blocks_per_cu(int) { return 1; }
 hipError_t launch_sweep(int, int, int, hipStream_t, const SweepArgs&) { return reached("sweep"); }
+hipError_t launch_inertia(const SweepArgs&, hipStream_t) { return reached("inertia"); }
 hipError_t launch_prep(const PrepArgs&, const CoopInitArgs&, int, int, hipStream_t) { return reached("prep"); }
 hipError_t launch_sign_map(bool, const SignMapArgs&, hipStream_t) { return reached("sign map"); }
 hipError_t launch_admit(const AdmitList*, int, int, int32_t*, hipStream_t) { return reached("admit"); }
@@ -29,7 +30,7 @@ hipError_t launch_misfit(int, const int32_t*, const double*, const double*, doub
 }
 hipError_t launch_classify(const ClassifyArgs&, hipStream_t) { return reached("classify"); }
 hipError_t launch_noise_check(const ModelDesc*, const LayerRec64*, const double*, const double*, const int32_t*,
-                              const int32_t*, int32_t*, int64_t, hipStream_t) {
+                              const int32_t*, int32_t*, int64_t, double, hipStream_t) {
   return reached("noise");
 }
 }  // namespace masw

@@ -100,6 +100,14 @@ def test_bad_precision_and_flags(lib):
     assert rc == M.MASW_EINVAL and "flags" in msg
 
 
+def test_inertia_search_needs_fp64(lib):
+    c, lam, m = _good()
+    rc, msg = _call_curve(c, lam, m, prec=M.MASW_PREC_SPLIT, flags=M.MASW_SEARCH_INERTIA)
+    assert rc == M.MASW_EINVAL and "MASW_SEARCH_INERTIA" in msg
+    rc, msg = _call_curve(c, lam, m, prec=M.MASW_PREC_FP64, flags=M.MASW_SEARCH_INERTIA)
+    assert rc == M.MASW_EINVAL and "ctx" in msg      # accepted up to the context check
+
+
 def test_create_without_device_reports_edevice(lib):
     try:
         import torch
