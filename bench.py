@@ -43,6 +43,14 @@ def flops_per_eval(n_layers: float) -> float:
     return 101.0 * n_layers + 48.0
 
 
+def inertia_flops(evals: int, entries: int, pivots: int) -> float:
+    """Algorithmic FP operations of the inertia counts of a launch, from its
+    work counters (the rules of flops_per_eval): 67 per element matrix formed
+    (a layer's or a sublayer's), 34 per 2x2 block pivot eliminated, and 48 for
+    the half-space block of each count in place of its pivot."""
+    return 67.0 * entries + 34.0 * (pivots - evals) + 48.0 * evals
+
+
 def classify_flops(evals: int, layers: int, steps: int) -> float:
     """Algorithmic FP operations of a zero/pole classification launch, from its
     work counters (same counting rules as flops_per_eval, a shared
@@ -76,7 +84,7 @@ MEASURED_TRAFFIC = {
 DEFAULT_STEPS = {"fine_scale": (200, 50), "two_layer": (200, 50), "batch": (5, 1), "uniform": (20, 3),
                  "chains": (20, 3), "classify": (5, 2)}
 
-KERNEL_SOURCES = ["masw_internal.hpp", "masw_math.hpp", "masw_special.hpp", "masw_kernels.hip"]
+KERNEL_SOURCES = ["masw_internal.hpp", "masw_math.hpp", "masw_special.hpp", "masw_pick.hpp", "masw_kernels.hip"]
 CLASSIFY_SOURCES = ["masw_classify.hip"]
 
 
@@ -119,16 +127,19 @@ class DeviceJob:
         f64, i32 = torch.float64, torch.int32
         self.out = {p: (torch.empty(self.W, dtype=f64, device=dev), torch.empty(self.W, dtype=i32, device=dev),
                         torch.empty(self.W, dtype=i32, device=dev), torch.empty(self.W, dtype=f64, device=dev))
-                    for p in (M.MASW_PREC_FP64, M.MASW_PREC_SPLIT)}
+                    for p in (M.MASW_PREC_FP64, M.MASW_PREC_SPLIT, "inertia")}
         self.n_layers = [m.n_layers for m in wl.models]
         self.lam_model = np.repeat(np.arange(len(wl.models)), [len(l) for l in wl.lambdas])
 
     def run(self, ctx, prec):
+        """prec: a precision, or "inertia" for the FP64 inertia-count search."""
         M, a = self.M, self.arrs
+        flags = M.MASW_SEARCH_INERTIA if prec == "inertia" else 0
+        p = M.MASW_PREC_FP64 if prec == "inertia" else prec
         if self.single:
-            M.masw_dispersion_curve(ctx, self.c, a[6], a[1], a[2], a[3], a[4], prec, 0, None, *self.out[prec])
+            M.masw_dispersion_curve(ctx, self.c, a[6], a[1], a[2], a[3], a[4], p, flags, None, *self.out[prec])
         else:
-            M.masw_dispersion_batch(ctx, self.c, *a, prec, 0, None, *self.out[prec])
+            M.masw_dispersion_batch(ctx, self.c, *a, p, flags, None, *self.out[prec])
 
     def results(self, prec):
         return tuple(o.cpu().numpy() for o in self.out[prec])
@@ -485,6 +496,33 @@ def cpu_baseline(wl, target_s: float, workers: int):
 
 
 # ---------------------------------------------------------------------- main --
+def inertia_leg(wl, r64, r_i, wall64, wall_i, sweep_i, st_i, n_lay, useful, n_curves):
+    """The FP64 inertia-count search on the same inputs: its outputs against
+    the FP64 walk's (bitwise), its rate, and its kernel's own roofline from its
+    work counters: the inertia counts, plus the determinant signs of the
+    refinement and of the changes at or above the half-space's S velocity
+    (F(N) each, N the mean layer count of the wavelengths)."""
+    same = all(np.array_equal(x, y, equal_nan=True) for x, y in zip(r64, r_i))
+    nbar = float(np.mean(n_lay)) if len(n_lay) else 0.0
+    flops = (inertia_flops(st_i["inertia_evals"], st_i["inertia_entries"], st_i["inertia_pivots"])
+             + (st_i["sweep_evals"] + st_i["check_evals"] + st_i["refine_evals"]) * flops_per_eval(nbar))
+    achieved = flops / (sweep_i * 1e-3) / 1e12
+    return {
+        "value": useful / wall_i, "unit": "det evals/s (useful evaluations of the walk it replaces)",
+        "ms_per_step": wall_i * 1e3, "dtype": "f64", "speedup_vs_fp64_walk": wall64 / wall_i,
+        "curves_per_s": n_curves / wall_i, "wavelengths_per_s": wl.n_lambda_total / wall_i,
+        "outputs_bitwise_equal_to_fp64_walk": bool(same),
+        "idx_mismatch_vs_fp64": int(np.sum(r64[1] != r_i[1])),
+        "inertia_evals": st_i["inertia_evals"], "inertia_entries": st_i["inertia_entries"],
+        "inertia_pivots": st_i["inertia_pivots"], "walked_evals": st_i["sweep_evals"],
+        "check_evals": st_i["check_evals"], "refine_evals": st_i["refine_evals"],
+        "kernel_ms": sweep_i,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None, "kernel": "inertia_kernel",
+                     "kernel_ms": sweep_i, "flops_per_launch": flops},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -555,6 +593,9 @@ def main():
     log("timing split path")
     wall32, sweep32, total32, st32 = time_path(job, ctx, M.MASW_PREC_SPLIT, a.steps, a.warmup)
     r32 = job.results(M.MASW_PREC_SPLIT)
+    log("timing the inertia-count search")
+    wall_i, sweep_i, total_i, st_i = time_path(job, ctx, "inertia", a.steps, a.warmup)
+    r_i = job.results("inertia")
 
     idx64, idx32 = r64[1], r32[1]
     useful = int(np.where(idx64 >= 0, idx64 + 1, wl.c_test.shape[0]).sum())
@@ -607,6 +648,7 @@ def main():
             "root_rel_err_vs_fp64_max": float(root_rel.max()) if root_rel.size else None,
             "root_rel_err_vs_fp64_mean": float(root_rel.mean()) if root_rel.size else None,
         },
+        "inertia": inertia_leg(wl, r64, r_i, wall64, wall_i, sweep_i, st_i, n_lay, useful, n_curves),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
                      "kernel": kname,

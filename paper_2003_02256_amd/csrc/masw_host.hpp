@@ -27,7 +27,7 @@ int sweep_blocks_per_cu(int mode, int G);
 int tick_blocks_per_cu(int G);
 hipError_t launch_sweep(int mode, int G, int blocks, hipStream_t s, const SweepArgs& a);
 // The inertia-count search (masw_inertia.hip), one wavefront per wavelength.
-hipError_t launch_inertia(const SweepArgs& a, hipStream_t s);
+hipError_t launch_inertia(const SweepArgs& a, int cus, hipStream_t s, int* blocks_out);
 hipError_t launch_prep(const PrepArgs& a, const CoopInitArgs& ci, int single_N, int single_W, hipStream_t s);
 hipError_t launch_sign_map(bool fp32, const SignMapArgs& a, hipStream_t s);
 hipError_t launch_admit(const AdmitList* list_dev, int n, int max_raw, int32_t* slot_remaining, hipStream_t s);

@@ -49,6 +49,7 @@
 // elimination per grid point up to the pick.  One wavefront per wavelength.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "masw.h"
@@ -161,63 +162,148 @@ __device__ int walk(const double* c64, int n_c, double k, const LayerRec64* L, i
   return -1;
 }
 
+// Sign code of a point whose count E is finite: E = s + 2P has the parity of
+// s, and sign(det K) = (-1)^s there (no zero or non-finite pivot).
+__device__ __forceinline__ int parity_sign(int E) { return (E & 1) ? -1 : 1; }
+
+// Spread points of (lo, hi] for the lanes from `first` on: every point if
+// they fit, else n_lanes points whose last is hi.  *valid is false for a lane
+// without a point.
+__device__ __forceinline__ int spread(int lo, int hi, int lane, int first, bool* valid) {
+  const int n = hi - lo, k = lane - first, n_lanes = 64 - first;
+  if (n <= n_lanes) {
+    *valid = k >= 0 && k < n;
+    return lo + 1 + k;
+  }
+  *valid = k >= 0;
+  return lo + int((int64_t(n) * (k + 1)) / n_lanes);
+}
+
+// First counted point after lo whose count differs from E_a, over (lo, hi]
+// with the 64 lanes; false if none.  On success (lo, hi] is narrowed to
+// (point before it, it] and E_hi is its count.
+__device__ __forceinline__ bool narrow_once(const double* c64, double k, const LayerRec64* L, int N, int E_a,
+                                            int* lo, int* hi, int* E_hi, Tally& t) {
+  const int lane = threadIdx.x & 63;
+  bool valid;
+  const int p = spread(*lo, *hi, lane, 0, &valid);
+  const int E = valid ? count_E(c64[p], k, L, N, t, true) : E_a;
+  const unsigned long long mask = __ballot(valid && E != E_a);
+  if (!mask) return false;
+  const int f = __ffsll((long long)mask) - 1;
+  const int p_f = __shfl(p, f, 64);
+  *lo = (f == 0) ? *lo : __shfl(p, f - 1, 64);
+  *hi = p_f;
+  *E_hi = __shfl(E, f, 64);
+  return true;
+}
+
 // The pick of one wavelength (-1: none), with the determinant signs at it and
 // at its predecessor.
+//   A. Determinant signs at c_test[0] (lane 0) and 63 spread grid points.  A
+//      sampled point whose sign differs from c_test[0]'s bounds the pick from
+//      above, so the counts that follow stay at velocities near it, where a
+//      layer needs few sublayers (their number grows with c).
+//   B. Counts at c_test[0], at the sampled point before that bound, and at 62
+//      points between the two sampled points; then narrowing on E.
+// With no sampled sign different (no change, or an even number of changes
+// between samples), the counts search the whole grid.
 __device__ int search(const double* c64, int n_c, double k, const LayerRec64* L, int N, int* sig_f, int* prev_f,
                       Tally& t) {
   const int lane = threadIdx.x & 63;
-  // sign and count at c_test[0] (every lane computes the same)
-  const int sig0 = det_sign<double, false>(c64[0], k, L, N, nullptr);
-  ++t.check;
-  int E_a = count_E(c64[0], k, L, N, t, lane == 0);
-  if (E_a == kEvent) return walk(c64, n_c, k, L, N, 1, sig0, sig_f, prev_f, t);
-  int a = 0;
-  for (;;) {
-    // first grid point in (a, n_c - 1] whose count differs from E_a
-    int lo = a, hi = n_c - 1, E_hi = kEvent;
-    bool any = false;
-    while (hi > lo + 1 || !any) {
-      const int n = hi - lo;
-      const int p = (n <= 64) ? lo + 1 + lane : lo + int((int64_t(n) * (lane + 1)) >> 6);
-      const bool valid = (n <= 64) ? (lane < n) : true;
-      const int E = valid ? count_E(c64[p], k, L, N, t, true) : E_a;
-      const unsigned long long mask = __ballot(valid && E != E_a);
-      if (!mask) {
-        // No change of E after a: sign(det K) is constant to the end.  (With
-        // `any`, hi's count differed in an earlier round and cannot agree now;
-        // walking from lo + 1, whose predecessor has sign sig0, is the
-        // fallback that needs no such argument.)
-        if (any) return walk(c64, n_c, k, L, N, lo + 1, sig0, sig_f, prev_f, t);
-        return -1;
-      }
-      any = true;
-      const int f = __ffsll((long long)mask) - 1;
-      const int p_f = __shfl(p, f, 64);
-      const int p_before = (f == 0) ? lo : __shfl(p, f - 1, 64);
-      E_hi = __shfl(E, f, 64);
-      hi = p_f;
-      lo = p_before;
+  const int n = n_c - 1;
+  // A
+  bool va;
+  const int pa = (lane == 0) ? 0 : spread(0, n, lane, 1, &va);
+  if (lane == 0) va = true;
+  const int sa = va ? det_sign<double, false>(c64[pa], k, L, N, nullptr) : kNoSign;
+  t.check += (unsigned long long)min(64, n_c);
+  const int sig0 = __shfl(sa, 0, 64);
+  if (sig0 != 1 && sig0 != -1) return walk(c64, n_c, k, L, N, 1, sig0, sig_f, prev_f, t);
+  const unsigned long long ma = __ballot(lane > 0 && va && sa != sig0);
+  int bound = n, lo, hi, E_a, E_hi;
+  if (ma) {
+    // B: the first change of sign(det K) is in (0, p_f]
+    const int f = __ffsll((long long)ma) - 1;
+    const int pf = __shfl(pa, f, 64), pb = __shfl(pa, f - 1, 64);
+    bound = pf;
+    bool vb;
+    int pbk = (lane == 0) ? 0 : (lane == 1 ? pb : spread(pb, pf, lane, 2, &vb));
+    if (lane < 2) vb = true;
+    const int E = vb ? count_E(c64[pbk], k, L, N, t, true) : 0;
+    E_a = __shfl(E, 0, 64);
+    if (E_a == kEvent) return walk(c64, n_c, k, L, N, 1, sig0, sig_f, prev_f, t);
+    const int E_b = __shfl(E, 1, 64);
+    if (E_b != E_a) {
+      lo = 0;  // a change of E before the sampled point before the bound
+      hi = pb;
+      E_hi = E_b;
+    } else {
+      const unsigned long long mb = __ballot(lane >= 2 && vb && E != E_a);
+      if (!mb) return walk(c64, n_c, k, L, N, pb + 1, sig0, sig_f, prev_f, t);
+      const int f2 = __ffsll((long long)mb) - 1;
+      hi = __shfl(pbk, f2, 64);
+      lo = __shfl(pbk, f2 - 1, 64);
+      E_hi = __shfl(E, f2, 64);
     }
-    // hi = lo + 1 is the first grid point after a where E changed
-    const int sg = det_sign<double, false>(c64[hi], k, L, N, nullptr);
-    ++t.check;
+  } else {
+    // no sampled sign differs: counts over the whole grid, c_test[0] on lane 0
+    bool v0;
+    const int p0 = (lane == 0) ? 0 : spread(0, n, lane, 1, &v0);
+    if (lane == 0) v0 = true;
+    const int E0 = v0 ? count_E(c64[p0], k, L, N, t, true) : 0;
+    E_a = __shfl(E0, 0, 64);
+    if (E_a == kEvent) return walk(c64, n_c, k, L, N, 1, sig0, sig_f, prev_f, t);
+    const unsigned long long m0 = __ballot(lane > 0 && v0 && E0 != E_a);
+    if (!m0) return -1;  // no change of E on the grid: sign(det K) is constant
+    const int f = __ffsll((long long)m0) - 1;
+    hi = __shfl(p0, f, 64);
+    lo = __shfl(p0, f - 1, 64);
+    E_hi = __shfl(E0, f, 64);
+  }
+  for (;;) {
+    // (lo, hi]: E(lo) = E_a and hi is the first counted point after lo whose
+    // count differs; narrow to one grid step.  hi's count differed before and
+    // is deterministic, so narrowing always succeeds; walking from lo + 1
+    // (predecessor sign sig0) is the fallback that needs no such argument.
+    while (hi > lo + 1)
+      if (!narrow_once(c64, k, L, N, E_a, &lo, &hi, &E_hi, t))
+        return walk(c64, n_c, k, L, N, lo + 1, sig0, sig_f, prev_f, t);
+    // hi = lo + 1 is the first grid point after lo where E changed
+    int sg;
+    if (E_hi == kEvent) {
+      sg = det_sign<double, false>(c64[hi], k, L, N, nullptr);
+      ++t.check;
+    } else {
+      sg = parity_sign(E_hi);
+    }
     if (sg != sig0) {
       *sig_f = sg;
       *prev_f = sig0;
       return hi;
     }
     if (E_hi == kEvent) return walk(c64, n_c, k, L, N, hi + 1, sig0, sig_f, prev_f, t);
-    a = hi;
+    // the sign is unchanged (a mode and a pole, or two modes, in one step):
+    // search (hi, bound] from E_a = E(hi)
     E_a = E_hi;
+    lo = hi;
+    hi = bound;
+    if (hi <= lo || !narrow_once(c64, k, L, N, E_a, &lo, &hi, &E_hi, t)) {
+      // with bound < n the sampled sign proves a change in (lo, bound]
+      if (bound < n) return walk(c64, n_c, k, L, N, lo + 1, sig0, sig_f, prev_f, t);
+      return -1;
+    }
   }
 }
 
+// Persistent grid: wavefront w of W takes wavelengths w, w + W, ...; its
+// counters stay in registers until the end.
 __global__ __launch_bounds__(64 * kInertiaWaves) void inertia_kernel(SweepArgs a) {
   __shared__ unsigned long long s_cnt[kInertiaWaves][7];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int g = blockIdx.x * kInertiaWaves + wave;
+  const int W = gridDim.x * kInertiaWaves;
   Tally t;
-  if (g < a.n_items) {
+  for (int g = blockIdx.x * kInertiaWaves + wave; g < a.n_items; g += W) {
     const int m = __builtin_amdgcn_readfirstlane(a.lam_model[g]);
     const ModelDesc d = a.models[m];
     const ItemOut o{a.out_ct + g, a.out_idx + g, a.out_status + g, a.out_cref ? a.out_cref + g : nullptr, a.refine,
@@ -226,19 +312,19 @@ __global__ __launch_bounds__(64 * kInertiaWaves) void inertia_kernel(SweepArgs a
     const int n_c = __builtin_amdgcn_readfirstlane(d.n_c);
     if (!(k == k)) {  // invalid model, grid or wavelength
       write_no_pick(o, MASW_STATUS_INVALID, lane == 0);
+      continue;
+    }
+    const int N = __builtin_amdgcn_readfirstlane(d.n_layers);
+    const double* c64 = a.c64 + __builtin_amdgcn_readfirstlane(d.c_base);
+    const LayerRec64* L = a.layers64 + __builtin_amdgcn_readfirstlane(d.layer_base);
+    int sig_f = 0, prev_f = 0;
+    const int found = search(c64, n_c, k, L, N, &sig_f, &prev_f, t);
+    if (found < 0) {
+      write_no_pick(o, MASW_STATUS_NOT_FOUND, lane == 0);
+      t.useful += (unsigned long long)n_c;
     } else {
-      const int N = __builtin_amdgcn_readfirstlane(d.n_layers);
-      const double* c64 = a.c64 + __builtin_amdgcn_readfirstlane(d.c_base);
-      const LayerRec64* L = a.layers64 + __builtin_amdgcn_readfirstlane(d.layer_base);
-      int sig_f = 0, prev_f = 0;
-      const int found = search(c64, n_c, k, L, N, &sig_f, &prev_f, t);
-      if (found < 0) {
-        write_no_pick(o, MASW_STATUS_NOT_FOUND, lane == 0);
-        t.useful = (unsigned long long)n_c;
-      } else {
-        t.useful = (unsigned long long)(found + 1);
-        t.refine = refine_and_write(o, c64, k, L, N, found, sig_f, prev_f);
-      }
+      t.useful += (unsigned long long)(found + 1);
+      t.refine += refine_and_write(o, c64, k, L, N, found, sig_f, prev_f);
     }
   }
   const unsigned long long evals = wave_sum(t.evals), entries = wave_sum(t.entries), pivots = wave_sum(t.pivots);
@@ -264,9 +350,19 @@ __global__ __launch_bounds__(64 * kInertiaWaves) void inertia_kernel(SweepArgs a
 
 }  // namespace
 
-hipError_t launch_inertia(const SweepArgs& a, hipStream_t s) {
+hipError_t launch_inertia(const SweepArgs& a, int cus, hipStream_t s, int* blocks_out) {
+  *blocks_out = 0;
   if (a.n_items <= 0) return hipSuccess;
-  const int64_t blocks = (int64_t(a.n_items) + kInertiaWaves - 1) / kInertiaWaves;
+  static const int per_cu = [] {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(inertia_kernel),
+                                                     64 * kInertiaWaves, 0) != hipSuccess || n < 1)
+      n = 1;
+    return n;
+  }();
+  const int64_t need = (int64_t(a.n_items) + kInertiaWaves - 1) / kInertiaWaves;
+  const int64_t blocks = std::min<int64_t>(need, int64_t(cus) * per_cu);
+  *blocks_out = int(blocks);
   hipLaunchKernelGGL(inertia_kernel, dim3(unsigned(blocks)), dim3(64 * kInertiaWaves), 0, s, a);
   return hipGetLastError();
 }

@@ -235,6 +235,37 @@ __device__ __forceinline__ int det_sign(T c, T k, const LayerRec<T>* __restrict_
   return sign_code(neg, double(re));
 }
 
+// As det_sign<T, true>, also returning Re det K of the scaled matrix as
+// *mant * 2^*expo (mant in [0.5, 1) in magnitude, or 0 / NaN), with no
+// overflow at any N.  Used to place refinement points.
+__device__ __forceinline__ int det_sign_value(double c, double k, const LayerRec<double>* __restrict__ L, int N,
+                                              uint64_t* dmask, double* mant, int* expo) {
+  const double c2 = c * c;
+  Block2<double> S{0.0, 0.0, 0.0};
+  bool neg = false;
+  uint64_t mask = 0;
+  double m = 1.0;
+  int e = 0;
+  for (int j = 0; j < N; ++j) {
+    const LayerRec<double> rec = load_rec<double>(L, j);
+    const LayerK<double> K = layer_entries<double>(c2, k * rec.h, rec.ia2, rec.ib2, rec.rh, rec.mh);
+    mask ^= uint64_t(K.gD < 0.0) << (j & 63);
+    const double d = schur_layer<double>(S, K);
+    neg ^= (d < 0.0);
+    int ex;
+    m = __builtin_frexp(m * d, &ex);
+    e += ex;
+  }
+  const LayerRec<double> hs = load_rec<double>(L, N);
+  double re, im;
+  halfspace_det<double>(S, c2, hs.ia2, hs.ib2, hs.mh, &re, &im);
+  *dmask = mask;
+  int ex;
+  *mant = __builtin_frexp(m * re, &ex);
+  *expo = e + ex;
+  return sign_code(neg, re);
+}
+
 // As det_sign, also returning in *odd whether an odd number of the layer
 // denominators D_j are negative.  That parity flips where c crosses a pole of
 // det K (one D_j changes sign there).

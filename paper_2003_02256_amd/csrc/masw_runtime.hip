@@ -282,7 +282,6 @@ int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t fl
   const int mode = prec == MASW_PREC_SPLIT ? 1 : 0;
   int blocks = 1;
   const int G = inertia ? 1 : pick_waves_per_item(ctx, mode, in.n_lam, &blocks);
-  if (inertia) blocks = int((in.n_lam + 3) / 4);
 
   // Shared sweeps when items are few enough that the deepest ones decide the
   // launch time: every item, with one summary word per round of its grid,
@@ -333,7 +332,7 @@ int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t fl
   sw.refine_rel = ctx->refine_rel;
   sw.counters = p.counters;
   MASW_HIP(hipEventRecord(T.ev[1], s));
-  if (in.n_lam > 0) MASW_HIP(inertia ? launch_inertia(sw, s) : launch_sweep(mode, G, blocks, s, sw));
+  if (in.n_lam > 0) MASW_HIP(inertia ? launch_inertia(sw, ctx->cus, s, &blocks) : launch_sweep(mode, G, blocks, s, sw));
   MASW_HIP(hipEventRecord(T.ev[2], s));
   // optional diagnostic after the timed sweep: the FP64 noise band of each
   // pick's bracket
