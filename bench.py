@@ -69,13 +69,18 @@ def classify_flops(evals: int, layers: int, steps: int) -> float:
 # WRITE_SIZE runs each scaled by the same counter's reading for a plain copy of
 # known size (FETCH x 2.000, WRITE x 1.000); see profiles/.  Keyed by the hash
 # of the kernel sources the counters were taken on (KERNEL_SOURCES for the
-# sweep, CLASSIFY_SOURCES for the classification), the workload and the
+# sweep, INERTIA_SOURCES for the inertia search, CLASSIFY_SOURCES for the
+# classification), the workload and the
 # launch, so a changed kernel reports null until it is measured again.
 MEASURED_TRAFFIC = {
-    ("7a2fc7ee957a7c43", "fine_scale_N20_1000lam_115001c", "sweep_kernel<FP64,G=8>"):
-        5017.50 * 1024 * 2.000 + 2590.91 * 1024 * 1.000,
-    ("7a2fc7ee957a7c43", "batch_4096models_19001c", "sweep_kernel<FP64,G=1>"):
-        267019.0 * 1024 * 2.000 + 148251.0 * 1024 * 1.000,
+    ("edc499b42c3e80e9", "fine_scale_N20_1000lam_115001c", "sweep_kernel<FP64,G=8>"):
+        4885.19 * 1024 * 2.000 + 2586.88 * 1024 * 1.000,
+    ("edc499b42c3e80e9", "batch_4096models_19001c", "sweep_kernel<FP64,G=1>"):
+        266775.0 * 1024 * 2.000 + 148119.0 * 1024 * 1.000,
+    ("c2454946afcec311", "fine_scale_N20_1000lam_115001c", "inertia_kernel"):
+        851.833 * 1024 * 2.000 + 796.875 * 1024 * 1.000,
+    ("c2454946afcec311", "batch_4096models_19001c", "inertia_kernel"):
+        81144.9 * 1024 * 2.000 + 37347.8 * 1024 * 1.000,
     ("6da9bc50b01ce006", "classify_batch_4096models_19001c", "classify_kernel"):
         14642.625 * 1024 * 2.000 + 21872.34 * 1024 * 1.000,
 }
@@ -86,6 +91,7 @@ DEFAULT_STEPS = {"fine_scale": (200, 50), "two_layer": (200, 50), "batch": (5, 1
 
 KERNEL_SOURCES = ["masw_internal.hpp", "masw_math.hpp", "masw_special.hpp", "masw_pick.hpp", "masw_kernels.hip"]
 CLASSIFY_SOURCES = ["masw_classify.hip"]
+INERTIA_SOURCES = ["masw_internal.hpp", "masw_math.hpp", "masw_special.hpp", "masw_pick.hpp", "masw_inertia.hip"]
 
 
 def kernel_source_hash(files=KERNEL_SOURCES) -> str:
@@ -518,7 +524,9 @@ def inertia_leg(wl, r64, r_i, wall64, wall_i, sweep_i, st_i, n_lay, useful, n_cu
         "check_evals": st_i["check_evals"], "refine_evals": st_i["refine_evals"],
         "kernel_ms": sweep_i,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None, "kernel": "inertia_kernel",
+                     "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": MEASURED_TRAFFIC.get((kernel_source_hash(INERTIA_SOURCES), wl.name, "inertia_kernel")),
+                     "kernel": "inertia_kernel",
                      "kernel_ms": sweep_i, "flops_per_launch": flops},
     }
 
