@@ -172,6 +172,9 @@ def test_first_changes_at_poles_and_modes(torch_dev, ctx):
             got, st = both(torch_dev, ctx, cc, np.array([lam]), m, f"lambda {lam} from {cc[0]:.2f}")
             p = O.dispersion_point(lam, cc, m)
             assert int(got[1][0]) == p.idx, (lam, cc[0], got[1][0], p.idx)
+            # the refined root, a pole's too (interpolated through 1/det K),
+            # within the refinement tolerance of the oracle's bisection
+            assert abs(got[3][0] - p.c_ref) <= 2e-9 * p.c_ref, (lam, cc[0], got[3][0], p.c_ref)
             print(f"lambda {lam} from c={cc[0]:.2f}: idx {p.idx} status {int(got[2][0])} "
                   f"counts {st['inertia_evals']}", flush=True)
 
