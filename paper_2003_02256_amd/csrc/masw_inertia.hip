@@ -13,16 +13,19 @@
 //            (the poles of det K, where D_j changes sign) below c.
 // E = J + P = s + 2P is non-decreasing, and s changes only where E does, so
 // the first change of sign(det K) along the grid is found by a search on E
-// instead of a walk:
-//   1. Multisection of (a, b] (a with E = E_a known, b = the last grid point):
-//      the 64 lanes of a wavefront count E at 64 spread grid points, and the
-//      first lane whose count differs from E_a gives the next (a, b], 64
-//      times narrower; three rounds reach one grid step on 115,001 points.
-//   2. At the first grid point b where E changed, det K's sign is evaluated
-//      as the walk would.  If it differs from the sign at c_test[0] that is
-//      the pick.  Otherwise (a mode and a pole in one grid step, or two
-//      modes) the search restarts from a = b.
-//   3. A grid point at or above the half-space's S velocity (K complex) or
+// instead of a walk (search() below):
+//   1. Sampling: det K's sign at c_test[0] and 63 spread grid points; the
+//      first sampled sign that differs bounds the pick from above, so the
+//      counts stay at velocities near it (a layer needs more sublayers, see
+//      below, the further c lies above its beta).
+//   2. Counts: multisection of (a, b] (E(a) = E_a known) by the 64 lanes of
+//      a wavefront, each counting E at one spread grid point; the first lane
+//      whose count differs from E_a gives the next (a, b], until one grid
+//      step is left.
+//   3. At that grid point the sign is the parity of E.  If it differs from
+//      the sign at c_test[0] that is the pick.  Otherwise (a mode and a pole
+//      in one grid step, or two modes) the search goes on from there.
+//   4. A grid point at or above the half-space's S velocity (K complex) or
 //      one where an elimination is not finite counts as a change of E.  If
 //      the search stops at such a point with the sign unchanged, the rest of
 //      the grid is walked as in Algorithm 1.
@@ -32,14 +35,15 @@
 // counted points that cancel in E cannot happen; a determinant that is
 // exactly zero or not finite at a grid point that is not counted is not seen.
 //
-// P_j from the layer alone.  With both faces fixed, a layer's displacement
-// field vanishes at z = 0 and z = h, so its strain energy is at least
-// mu (k^2 + (pi/h)^2) times the integral of |u|^2 (the (lambda + mu)|div u|^2
-// term is non-negative, and Wirtinger's inequality bounds |u_z'|^2), and the
-// layer has no fixed-face mode with c^2 <= beta^2 (1 + (pi/(kh))^2).  So
-// P_j(c) = 0 when k h sqrt(c^2/beta^2 - 1) <= pi.  Otherwise the layer is cut
-// into m = floor(k h sqrt(c^2/beta^2 - 1)/pi) + 1 equal sublayers, none of
-// which has such a mode below c, and the theorem applied to the layer with
+// P_j from the layer alone.  For a field u(z) e^{ikx} that vanishes on both
+// faces of a layer, the strain energy is the integral of
+// (lambda + mu)|div u|^2 + mu (k^2 |u|^2 + |u'|^2) (the cross terms
+// integrate to zero), and Wirtinger's inequality bounds the integral of
+// |u'|^2 below by (pi/h)^2 times that of |u|^2.  So every fixed-face mode has
+// rho omega^2 >= mu (k^2 + (pi/h)^2), i.e. c^2 > beta^2 (1 + (pi/(kh))^2),
+// and P_j(c) = 0 when k h sqrt(c^2/beta^2 - 1) <= pi.  Otherwise the layer is
+// cut into m = floor(k h sqrt(c^2/beta^2 - 1)/pi) + 1 equal sublayers, none
+// of which has such a mode below c, and the theorem applied to the layer with
 // both faces fixed gives P_j = the number of negative eigenvalues of the
 // stiffness of the m - 1 interior interfaces: the same unpivoted 2x2-block
 // elimination, m - 1 pivots of one sublayer's element matrix.
