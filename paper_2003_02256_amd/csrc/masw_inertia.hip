@@ -203,67 +203,121 @@ __device__ __forceinline__ bool narrow_once(const double* c64, double k, const L
 }
 
 // The pick of one wavelength (-1: none), with the determinant signs at it and
-// at its predecessor.
-//   A. Determinant signs at c_test[0] (lane 0) and 63 spread grid points.  A
-//      sampled point whose sign differs from c_test[0]'s bounds the pick from
-//      above, so the counts that follow stay at velocities near it, where a
-//      layer needs few sublayers (their number grows with c).
-//   B. Counts at c_test[0], at the sampled point before that bound, and at 62
-//      points between the two sampled points; then narrowing on E.
+// at its predecessor.  pred >= 1 predicts the pick (from the previous
+// wavelengths of the same model), or is -1.
+//   P. With a prediction: counts at c_test[0] (lane 0), at the grid point w0
+//      before a window of 62 consecutive grid points around the prediction
+//      (lane 1), and at the window's points.  E(w0) = E(c_test[0]) proves no
+//      change of E up to w0, and the first window point whose count differs
+//      is then the first change of E.  If E changes before w0 the counts
+//      narrow (0, w0]; if it changes in neither, the search goes on after
+//      the window (A, B).
+//   A. Determinant signs at the start point (lane 0) and 63 spread grid
+//      points after it.  A sampled sign that differs from the start's bounds
+//      the pick from above, so the counts that follow stay at velocities
+//      near it, where a layer needs few sublayers (their number grows with
+//      c).
+//   B. Counts at the start point, at the sampled point before that bound,
+//      and at 62 points between the two sampled points; then narrowing on E.
 // With no sampled sign different (no change, or an even number of changes
-// between samples), the counts search the whole grid.
-__device__ int search(const double* c64, int n_c, double k, const LayerRec64* L, int N, int* sig_f, int* prev_f,
-                      Tally& t) {
+// between samples), the counts search the rest of the grid.
+__device__ int search(const double* c64, int n_c, double k, const LayerRec64* L, int N, int pred, int* sig_f,
+                      int* prev_f, Tally& t) {
   const int lane = threadIdx.x & 63;
   const int n = n_c - 1;
-  // A
-  bool va;
-  const int pa = (lane == 0) ? 0 : spread(0, n, lane, 1, &va);
-  if (lane == 0) va = true;
-  const int sa = va ? det_sign<double, false>(c64[pa], k, L, N, nullptr) : kNoSign;
-  t.check += (unsigned long long)min(64, n_c);
-  const int sig0 = __shfl(sa, 0, 64);
-  if (sig0 != 1 && sig0 != -1) return walk(c64, n_c, k, L, N, 1, sig0, sig_f, prev_f, t);
-  const unsigned long long ma = __ballot(lane > 0 && va && sa != sig0);
-  int bound = n, lo, hi, E_a, E_hi;
-  if (ma) {
-    // B: the first change of sign(det K) is in (0, p_f]
-    const int f = __ffsll((long long)ma) - 1;
-    const int pf = __shfl(pa, f, 64), pb = __shfl(pa, f - 1, 64);
-    bound = pf;
-    bool vb;
-    int pbk = (lane == 0) ? 0 : (lane == 1 ? pb : spread(pb, pf, lane, 2, &vb));
-    if (lane < 2) vb = true;
-    const int E = vb ? count_E(c64[pbk], k, L, N, t, true) : 0;
+  int a = 0;         // no change of sign(det K) in [0, a]
+  int E_a = 0;       // E(a), once known
+  int sig0 = 0;      // sign(det K) on [0, a], once known
+  bool known = false;
+  bool located = false;  // (lo, hi] holds the first change of E after lo
+  int bound = n, lo = 0, hi = 0, E_hi = 0;
+  if (pred >= 1 && n >= 64) {
+    // P
+    const int w0 = max(0, min(pred - 32, n - 62));
+    const int p = (lane == 0) ? 0 : w0 + lane - 1;  // lanes 2..63: w0 + 1 .. w0 + 62 <= n
+    const int E = count_E(c64[p], k, L, N, t, lane != 1 || w0 > 0);
     E_a = __shfl(E, 0, 64);
-    if (E_a == kEvent) return walk(c64, n_c, k, L, N, 1, sig0, sig_f, prev_f, t);
-    const int E_b = __shfl(E, 1, 64);
-    if (E_b != E_a) {
-      lo = 0;  // a change of E before the sampled point before the bound
-      hi = pb;
-      E_hi = E_b;
-    } else {
-      const unsigned long long mb = __ballot(lane >= 2 && vb && E != E_a);
-      if (!mb) return walk(c64, n_c, k, L, N, pb + 1, sig0, sig_f, prev_f, t);
-      const int f2 = __ffsll((long long)mb) - 1;
-      hi = __shfl(pbk, f2, 64);
-      lo = __shfl(pbk, f2 - 1, 64);
-      E_hi = __shfl(E, f2, 64);
+    if (E_a == kEvent) {
+      sig0 = det_sign<double, false>(c64[0], k, L, N, nullptr);
+      ++t.check;
+      return walk(c64, n_c, k, L, N, 1, sig0, sig_f, prev_f, t);
     }
-  } else {
-    // no sampled sign differs: counts over the whole grid, c_test[0] on lane 0
-    bool v0;
-    const int p0 = (lane == 0) ? 0 : spread(0, n, lane, 1, &v0);
-    if (lane == 0) v0 = true;
-    const int E0 = v0 ? count_E(c64[p0], k, L, N, t, true) : 0;
-    E_a = __shfl(E0, 0, 64);
-    if (E_a == kEvent) return walk(c64, n_c, k, L, N, 1, sig0, sig_f, prev_f, t);
-    const unsigned long long m0 = __ballot(lane > 0 && v0 && E0 != E_a);
-    if (!m0) return -1;  // no change of E on the grid: sign(det K) is constant
-    const int f = __ffsll((long long)m0) - 1;
-    hi = __shfl(p0, f, 64);
-    lo = __shfl(p0, f - 1, 64);
-    E_hi = __shfl(E0, f, 64);
+    sig0 = parity_sign(E_a);
+    known = true;
+    const int E_w = __shfl(E, 1, 64);
+    if (E_w != E_a) {  // a change of E in (0, w0]
+      hi = w0;
+      E_hi = E_w;
+      located = true;
+    } else {
+      const unsigned long long m = __ballot(lane >= 2 && E != E_a);
+      if (m) {
+        const int f = __ffsll((long long)m) - 1;
+        hi = __shfl(p, f, 64);
+        lo = __shfl(p, f - 1, 64);
+        E_hi = __shfl(E, f, 64);
+        located = true;
+      } else {
+        a = w0 + 62;  // no change up to the window's end
+      }
+    }
+  }
+  if (!located) {
+    // A
+    bool va;
+    const int pa = (lane == 0) ? a : spread(a, n, lane, 1, &va);
+    if (lane == 0) va = true;
+    const int sa =
+        (lane == 0 && known) ? sig0 : (va ? det_sign<double, false>(c64[pa], k, L, N, nullptr) : kNoSign);
+    t.check += (unsigned long long)((known ? 0 : 1) + min(63, n - a));
+    if (!known) {
+      sig0 = __shfl(sa, 0, 64);
+      if (sig0 != 1 && sig0 != -1) return walk(c64, n_c, k, L, N, 1, sig0, sig_f, prev_f, t);
+    }
+    const unsigned long long ma = __ballot(lane > 0 && va && sa != sig0);
+    if (ma) {
+      // B: the first change of sign(det K) after a is in (a, p_f]
+      const int f = __ffsll((long long)ma) - 1;
+      const int pf = __shfl(pa, f, 64), pb = __shfl(pa, f - 1, 64);
+      bound = pf;
+      bool vb;
+      const int pbk = (lane == 0) ? a : (lane == 1 ? pb : spread(pb, pf, lane, 2, &vb));
+      if (lane < 2) vb = true;
+      const int E = (lane == 0 && known) ? E_a : (vb ? count_E(c64[pbk], k, L, N, t, lane != 1 || pb != a) : 0);
+      if (!known) {
+        E_a = __shfl(E, 0, 64);
+        if (E_a == kEvent) return walk(c64, n_c, k, L, N, a + 1, sig0, sig_f, prev_f, t);
+      }
+      const int E_b = __shfl(E, 1, 64);
+      if (E_b != E_a) {
+        lo = a;  // a change of E before the sampled point before the bound
+        hi = pb;
+        E_hi = E_b;
+      } else {
+        const unsigned long long mb = __ballot(lane >= 2 && vb && E != E_a);
+        if (!mb) return walk(c64, n_c, k, L, N, pb + 1, sig0, sig_f, prev_f, t);
+        const int f2 = __ffsll((long long)mb) - 1;
+        hi = __shfl(pbk, f2, 64);
+        lo = __shfl(pbk, f2 - 1, 64);
+        E_hi = __shfl(E, f2, 64);
+      }
+    } else {
+      // no sampled sign differs: counts over the rest of the grid
+      bool v0;
+      const int p0 = (lane == 0) ? a : spread(a, n, lane, 1, &v0);
+      if (lane == 0) v0 = true;
+      const int E0 = (lane == 0 && known) ? E_a : (v0 ? count_E(c64[p0], k, L, N, t, true) : 0);
+      if (!known) {
+        E_a = __shfl(E0, 0, 64);
+        if (E_a == kEvent) return walk(c64, n_c, k, L, N, a + 1, sig0, sig_f, prev_f, t);
+      }
+      const unsigned long long m0 = __ballot(lane > 0 && v0 && E0 != E_a);
+      if (!m0) return -1;  // no change of E after a: sign(det K) is constant
+      const int f = __ffsll((long long)m0) - 1;
+      hi = __shfl(p0, f, 64);
+      lo = __shfl(p0, f - 1, 64);
+      E_hi = __shfl(E0, f, 64);
+    }
   }
   for (;;) {
     // (lo, hi]: E(lo) = E_a and hi is the first counted point after lo whose
@@ -300,38 +354,69 @@ __device__ int search(const double* c64, int n_c, double k, const LayerRec64* L,
   }
 }
 
-// Persistent grid: wavefront w of W takes wavelengths w, w + W, ...; its
-// counters stay in registers until the end.  Three wavefronts per SIMD
-// (at most 168 VGPRs, two of them spilled) ran the 4096-model batch 6%
-// faster than the two that 173 VGPRs allow.
+// One wavelength: search, refinement and outputs.  Returns the pick (-1: none).
+__device__ int run_wavelength(const SweepArgs& a, int g, int pred, Tally& t) {
+  const int lane = threadIdx.x & 63;
+  const int m = __builtin_amdgcn_readfirstlane(a.lam_model[g]);
+  const ModelDesc d = a.models[m];
+  const ItemOut o{a.out_ct + g, a.out_idx + g, a.out_status + g, a.out_cref ? a.out_cref + g : nullptr, a.refine,
+                  a.refine_rel};
+  const double k = a.lam_k[g];
+  const int n_c = __builtin_amdgcn_readfirstlane(d.n_c);
+  if (!(k == k)) {  // invalid model, grid or wavelength
+    write_no_pick(o, MASW_STATUS_INVALID, lane == 0);
+    return -1;
+  }
+  const int N = __builtin_amdgcn_readfirstlane(d.n_layers);
+  const double* c64 = a.c64 + __builtin_amdgcn_readfirstlane(d.c_base);
+  const LayerRec64* L = a.layers64 + __builtin_amdgcn_readfirstlane(d.layer_base);
+  int sig_f = 0, prev_f = 0;
+  const int found = search(c64, n_c, k, L, N, pred, &sig_f, &prev_f, t);
+  if (found < 0) {
+    write_no_pick(o, MASW_STATUS_NOT_FOUND, lane == 0);
+    t.useful += (unsigned long long)n_c;
+  } else {
+    t.useful += (unsigned long long)(found + 1);
+    t.refine += refine_and_write(o, c64, k, L, N, found, sig_f, prev_f);
+  }
+  return found;
+}
+
+// Persistent grid; counters stay in registers until the end.  With
+// chunk = 1 (wavelengths no more than a few per wavefront) wavefront w of W
+// takes wavelengths w, w + W, ...  Otherwise each wavefront claims runs of
+// `chunk` consecutive wavelengths from an atomic queue, and within a run the
+// picks of the previous wavelengths of the same model predict the next pick
+// (round P of search()).  Three wavefronts per SIMD (at most 168 VGPRs, two
+// of them spilled) ran the 4096-model batch 6% faster than the two that 173
+// VGPRs allow.
 __global__ __launch_bounds__(64 * kInertiaWaves) __attribute__((amdgpu_waves_per_eu(3))) void inertia_kernel(
-    SweepArgs a) {
+    SweepArgs a, int chunk) {
   __shared__ unsigned long long s_cnt[kInertiaWaves][7];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int W = gridDim.x * kInertiaWaves;
   Tally t;
-  for (int g = blockIdx.x * kInertiaWaves + wave; g < a.n_items; g += W) {
-    const int m = __builtin_amdgcn_readfirstlane(a.lam_model[g]);
-    const ModelDesc d = a.models[m];
-    const ItemOut o{a.out_ct + g, a.out_idx + g, a.out_status + g, a.out_cref ? a.out_cref + g : nullptr, a.refine,
-                    a.refine_rel};
-    const double k = a.lam_k[g];
-    const int n_c = __builtin_amdgcn_readfirstlane(d.n_c);
-    if (!(k == k)) {  // invalid model, grid or wavelength
-      write_no_pick(o, MASW_STATUS_INVALID, lane == 0);
-      continue;
-    }
-    const int N = __builtin_amdgcn_readfirstlane(d.n_layers);
-    const double* c64 = a.c64 + __builtin_amdgcn_readfirstlane(d.c_base);
-    const LayerRec64* L = a.layers64 + __builtin_amdgcn_readfirstlane(d.layer_base);
-    int sig_f = 0, prev_f = 0;
-    const int found = search(c64, n_c, k, L, N, &sig_f, &prev_f, t);
-    if (found < 0) {
-      write_no_pick(o, MASW_STATUS_NOT_FOUND, lane == 0);
-      t.useful += (unsigned long long)n_c;
-    } else {
-      t.useful += (unsigned long long)(found + 1);
-      t.refine += refine_and_write(o, c64, k, L, N, found, sig_f, prev_f);
+  if (chunk <= 1) {
+    const int W = gridDim.x * kInertiaWaves;
+    for (int g = blockIdx.x * kInertiaWaves + wave; g < a.n_items; g += W) run_wavelength(a, g, -1, t);
+  } else {
+    for (;;) {
+      unsigned q = 0;
+      if (lane == 0) q = atomicAdd(&a.counters->queue_head, 1u);
+      const int64_t first = int64_t(__shfl(q, 0, 64)) * chunk;
+      if (first >= a.n_items) break;
+      const int last = int(std::min<int64_t>(first + chunk, a.n_items));
+      int model = -1, p1 = -1, p2 = -1;  // the last two picks of `model` in this run
+      for (int g = int(first); g < last; ++g) {
+        const int m = __builtin_amdgcn_readfirstlane(a.lam_model[g]);
+        if (m != model) {
+          model = m;
+          p1 = p2 = -1;
+        }
+        const int pred = p1 < 1 ? -1 : (p2 < 1 ? p1 : max(1, 2 * p1 - p2));
+        const int found = run_wavelength(a, g, pred, t);
+        p2 = found < 0 ? -1 : p1;
+        p1 = found;
+      }
     }
   }
   const unsigned long long evals = wave_sum(t.evals), entries = wave_sum(t.entries), pivots = wave_sum(t.pivots);
@@ -370,7 +455,11 @@ hipError_t launch_inertia(const SweepArgs& a, int cus, hipStream_t s, int* block
   const int64_t need = (int64_t(a.n_items) + kInertiaWaves - 1) / kInertiaWaves;
   const int64_t blocks = std::min<int64_t>(need, int64_t(cus) * per_cu);
   *blocks_out = int(blocks);
-  hipLaunchKernelGGL(inertia_kernel, dim3(unsigned(blocks)), dim3(64 * kInertiaWaves), 0, s, a);
+  // runs of consecutive wavelengths only when each wavefront gets many
+  // (a run is searched in sequence), at most 16 so that runs balance
+  const int64_t waves = blocks * kInertiaWaves;
+  const int chunk = int(std::max<int64_t>(1, std::min<int64_t>(16, int64_t(a.n_items) / (4 * waves))));
+  hipLaunchKernelGGL(inertia_kernel, dim3(unsigned(blocks)), dim3(64 * kInertiaWaves), 0, s, a, chunk);
   return hipGetLastError();
 }
 
