@@ -77,10 +77,10 @@ MEASURED_TRAFFIC = {
         4885.19 * 1024 * 2.000 + 2586.88 * 1024 * 1.000,
     ("edc499b42c3e80e9", "batch_4096models_19001c", "sweep_kernel<FP64,G=1>"):
         266775.0 * 1024 * 2.000 + 148119.0 * 1024 * 1.000,
-    ("96fc2dce36e74457", "fine_scale_N20_1000lam_115001c", "inertia_kernel"):
-        851.833 * 1024 * 2.000 + 796.875 * 1024 * 1.000,
-    ("96fc2dce36e74457", "batch_4096models_19001c", "inertia_kernel"):
-        81144.9 * 1024 * 2.000 + 37347.8 * 1024 * 1.000,
+    ("1b3c9807d56ef5cf", "fine_scale_N20_1000lam_115001c", "inertia_kernel"):
+        881.604 * 1024 * 2.000 + 1546.88 * 1024 * 1.000,
+    ("1b3c9807d56ef5cf", "batch_4096models_19001c", "inertia_kernel"):
+        41346.8 * 1024 * 2.000 + 34384.4 * 1024 * 1.000,
     ("6da9bc50b01ce006", "classify_batch_4096models_19001c", "classify_kernel"):
         14642.625 * 1024 * 2.000 + 21872.34 * 1024 * 1.000,
 }
