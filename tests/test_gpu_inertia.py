@@ -210,3 +210,29 @@ def test_full_batch_equals_the_walk(torch_dev, ctx):
     np.testing.assert_array_equal(got[2], walk[2])
     np.testing.assert_array_equal(got[0], walk[0])
     np.testing.assert_array_equal(got[3], walk[3])
+
+
+def test_runs_with_predictions_across_models_and_invalid_items(torch_dev, ctx):
+    # 200 models (about 55,000 wavelengths, so wavefronts claim runs of
+    # consecutive wavelengths and predict picks within them).  Invalid
+    # models and wavelengths inside runs, and wavelengths in reverse order
+    # (picks that fall along the run), must not disturb the predictions'
+    # effect: outputs equal the walk's bit for bit.
+    wl = WL.batch_case(n_models=200, seed=11)
+    models, lambdas = list(wl.models), [l.copy() for l in wl.lambdas]
+    for i in (3, 50, 51, 120):
+        m = models[i].copy()
+        m.alpha[1] = 0.5 * m.beta[1]        # alpha < beta: invalid on the device
+        models[i] = m
+    for i in (7, 90):
+        lambdas[i][10] = -1.0               # one invalid wavelength in the middle of a run
+    for i in range(0, 200, 9):
+        lambdas[i] = lambdas[i][::-1].copy()
+    walk = dev_batch(torch_dev, ctx, wl.c_test, models, lambdas, FP64)
+    got = dev_batch(torch_dev, ctx, wl.c_test, models, lambdas, FP64, INERTIA)
+    st = ctx.stats()
+    print(f"runs: {len(got[1])} wavelengths, stats {st}", flush=True)
+    for x, y, what in zip(walk, got, ("C_t", "idx", "status", "c_ref")):
+        np.testing.assert_array_equal(y, x, err_msg=what)
+    assert np.sum(got[2] == M.MASW_STATUS_INVALID) >= 4 * 50 + 2
+    assert st["check_evals"] < 64 * len(got[1]) // 2   # runs of 4 here: most wavelengths were predicted
