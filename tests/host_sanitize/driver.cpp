@@ -86,6 +86,8 @@ int main() {
                                ct.data(), idx.data(), st.data(), cref.data()), E, "unknown flag");
   expect(masw_dispersion_curve(nullptr, c.data(), 801, lam.data(), 30, &m, MASW_PREC_FP64, MASW_CHECK_NOISE,
                                nullptr, ct.data(), idx.data(), st.data(), cref.data()), E, "null context");
+  expect(masw_dispersion_curve(nullptr, c.data(), 801, lam.data(), 30, &m, MASW_PREC_SPLIT, MASW_SEARCH_INERTIA,
+                               nullptr, ct.data(), idx.data(), st.data(), cref.data()), E, "inertia with split");
 
   // batch: offsets
   const int32_t loff[3] = {0, 2, 4}, woff_bad[3] = {0, 30, 20};
