@@ -91,7 +91,8 @@ DEFAULT_STEPS = {"fine_scale": (200, 50), "two_layer": (200, 50), "batch": (5, 1
 
 KERNEL_SOURCES = ["masw_internal.hpp", "masw_math.hpp", "masw_special.hpp", "masw_pick.hpp", "masw_kernels.hip"]
 CLASSIFY_SOURCES = ["masw_classify.hip"]
-INERTIA_SOURCES = ["masw_internal.hpp", "masw_math.hpp", "masw_special.hpp", "masw_pick.hpp", "masw_inertia.hip"]
+INERTIA_SOURCES = ["masw_internal.hpp", "masw_math.hpp", "masw_special.hpp", "masw_pick.hpp", "masw_inertia.hpp",
+                   "masw_inertia.hip"]
 
 
 def kernel_source_hash(files=KERNEL_SOURCES) -> str:
@@ -192,16 +193,22 @@ def serving_trace(rate: float, warm_s: float, dur_s: float, seed: int = 55):
     return times, reqs
 
 
-def run_serving(M, ctx, prec, times, reqs, c, warm_s: float):
+def run_serving(M, ctx, prec, times, reqs, c, warm_s: float, search_inertia: int = 0):
     """Replay the trace against the serving loop: a submitter thread at the
     arrival times, a collector waiting on tickets in order.  Latency = the
-    library's completion timestamp - the scheduled arrival (CLOCK_MONOTONIC)."""
+    library's completion timestamp - the scheduled arrival (CLOCK_MONOTONIC).
+    search_inertia: FP64 requests take the inertia-count search."""
     import threading
     n = len(times)
     tickets = [None] * n
     sched = [0] * n
     ready = threading.Semaphore(0)
-    M.masw_server_start(ctx)
+    M.masw_server_start(ctx, search_inertia=search_inertia)
+    # the submitter must keep to the arrival times: no collector pauses
+    # during the replay (latency counts from the scheduled arrival)
+    import gc
+    gc.collect()
+    gc.disable()
     t0 = time.monotonic_ns() + 50_000_000
 
     def submitter():
@@ -225,6 +232,7 @@ def run_serving(M, ctx, prec, times, reqs, c, warm_s: float):
         info = M.masw_wait(ctx, tickets[i], -1, *out)
         results[i] = (info, out[1])
     th.join()
+    gc.enable()
     stats = M.masw_server_get_stats(ctx)
     M.masw_server_stop(ctx)
     meas = [i for i in range(n) if times[i] >= warm_s]
@@ -251,7 +259,10 @@ def serving_bench(M, torch, a):
     log(f"split: {split}")
     fp64, idx_d = run_serving(M, ctx_obj.ctx, M.MASW_PREC_FP64, times, reqs, c, warm)
     log(f"fp64: {fp64}")
+    inertia, idx_i = run_serving(M, ctx_obj.ctx, M.MASW_PREC_FP64, times, reqs, c, warm, search_inertia=1)
+    log(f"fp64 with the inertia search: {inertia}")
     mism = sum(int(np.sum(x != y)) for x, y in zip(idx_s, idx_d))
+    mism_i = sum(int(np.sum(x != y)) for x, y in zip(idx_i, idx_d))
     ctx_obj.close()
     n_lam = int(np.mean([len(r[4]) for r in reqs]))
     res = {
@@ -263,6 +274,7 @@ def serving_bench(M, torch, a):
                    "n_c": int(c.shape[0]), "wavelengths_mean": n_lam},
         "p50_ms": split["p50_ms"], "p99_ms": split["p99_ms"], "curves_per_s": split["curves_per_s"],
         "split": split, "fp64": fp64, "idx_mismatch_split_vs_fp64": mism,
+        "fp64_inertia": inertia, "idx_mismatch_inertia_vs_fp64": mism_i,
     }
     print(json.dumps(res), flush=True)
 

@@ -281,6 +281,13 @@ typedef struct {
                                 runs longer fails the server: pending and later
                                 calls return MASW_EDEVICE, and the server must be
                                 stopped and started again (0 = 10 s)             */
+    int32_t search_inertia;  /* 1: FP64 requests find their picks with the
+                                inertia-count search (as MASW_SEARCH_INERTIA),
+                                each within one tick: the tick's wavefronts
+                                sample det K's sign, one wavefront finishes;
+                                0: they walk.  Split requests always walk.
+                                Other values: MASW_EINVAL                       */
+    int32_t reserved;        /* must be 0                                         */
 } masw_server_opts;
 
 /* Timing of one request (CLOCK_MONOTONIC ns) and the ticks it took part in. */

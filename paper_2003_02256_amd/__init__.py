@@ -112,7 +112,8 @@ class masw_timing(ctypes.Structure):
 class masw_server_opts(ctypes.Structure):
     _fields_ = [("max_layers", ctypes.c_int32), ("max_lambda", ctypes.c_int32), ("max_grid", ctypes.c_int32),
                 ("rounds_per_tick", ctypes.c_int32), ("pool_bytes", ctypes.c_size_t),
-                ("tick_timeout_us", ctypes.c_int64)]
+                ("tick_timeout_us", ctypes.c_int64), ("search_inertia", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class masw_request_info(ctypes.Structure):
@@ -356,8 +357,9 @@ def masw_get_timing(ctx, reset: bool = False) -> dict:
 
 
 def masw_server_start(ctx, max_layers=0, max_lambda=0, max_grid=0, rounds_per_tick=0, pool_bytes=0,
-                      tick_timeout_us=0) -> int:
-    o = masw_server_opts(max_layers, max_lambda, max_grid, rounds_per_tick, pool_bytes, tick_timeout_us)
+                      tick_timeout_us=0, search_inertia=0) -> int:
+    o = masw_server_opts(max_layers, max_lambda, max_grid, rounds_per_tick, pool_bytes, tick_timeout_us,
+                         search_inertia, 0)
     return _check(library().masw_server_start(ctx, ctypes.byref(o)), "masw_server_start")
 
 

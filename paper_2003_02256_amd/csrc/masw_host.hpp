@@ -24,7 +24,7 @@ struct TraceRange {
 };
 
 int sweep_blocks_per_cu(int mode, int G);
-int tick_blocks_per_cu(int G);
+int tick_blocks_per_cu(int G, bool inertia);
 hipError_t launch_sweep(int mode, int G, int blocks, hipStream_t s, const SweepArgs& a);
 // The inertia-count search (masw_inertia.hip), one wavefront per wavelength.
 hipError_t launch_inertia(const SweepArgs& a, int cus, hipStream_t s, int* blocks_out);

@@ -214,6 +214,7 @@ struct TickArgs {
   int32_t* slot_remaining;   // [kMaxSlots] items not finished
   Counters* counters;
   int32_t refine;
+  int32_t inertia;           // 1: FP64 items use the inertia-count search
   double refine_rel;         // refinement bracket width / c_hi
   // outputs in pinned host memory (device-accessible)
   double* out_ct;

@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <type_traits>
 
+#include "masw_inertia.hpp"
 #include "masw_internal.hpp"
 #include "masw_math.hpp"
 #include "masw_pick.hpp"
@@ -954,10 +955,67 @@ __global__ __launch_bounds__(kAdmitChunk) void admit_kernel(const AdmitList* __r
 // at most desc->budget sweep rounds (then its re-check and refinement if its
 // change was found).  The last item of a request to finish raises the
 // request's completion flag in pinned host memory.
-// With G = 8 the kernel is held to 128 VGPRs (4 wavefronts per SIMD), so two
-// workgroups fit on a CU, as for the batch sweep.
+// One FP64 item of a serving tick by the inertia-count search: the sampling
+// round of the search on all G wavefronts (64 G grid points: c_test[0] and
+// 64 G - 1 spread points), then the counts, the sign at the change and the
+// refinement on wavefront 0.  The sampled bound leaves a bracket of about
+// n_c / (64 G) grid points, which one round of counts resolves.  The other
+// wavefronts wait at the tick's barrier.  Outputs equal the walk's.
 template <int G>
-__global__ __launch_bounds__(64 * G) __attribute__((amdgpu_waves_per_eu(G >= 8 ? 4 : 1)))
+__device__ void inertia_tick_item(const ItemRef& r, SweepShared<G>& sh, WorkCount& wc, const ItemOut& o) {
+  constexpr int P = 64 * G;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int n = r.n_c - 1;
+  bool va = true;
+  const int pa = (tid == 0) ? 0 : inertia::spread(0, n, tid, 1, &va, P);
+  if (tid == 0) va = true;
+  const int sa = va ? det_sign<double, false>(r.c64[pa], r.k64, r.L64, r.N, nullptr) : kNoSign;
+  if (tid == 0) sh.check[0] = sa;
+  __syncthreads();
+  const int sig0 = sh.check[0];
+  const unsigned long long m = __ballot(tid > 0 && va && sa != sig0);
+  if (lane == 0) sh.first[wave] = m ? wave * 64 + (__ffsll((long long)m) - 1) : P;
+  __syncthreads();
+  if (wave != 0) return;
+  int f = P;
+#pragma unroll
+  for (int w = 0; w < G; ++w) f = min(f, sh.first[w]);
+  inertia::Tally t;
+  t.check = (unsigned long long)min(P, r.n_c);
+  int sig_f = 0, prev_f = 0, found;
+  if (sig0 != 1 && sig0 != -1) {
+    found = inertia::walk(r.c64, r.n_c, r.k64, r.L64, r.N, 1, sig0, &sig_f, &prev_f, t);
+  } else if (f == P) {
+    // no sampled sign differs: the one-wavefront search from the start
+    found = inertia::search(r.c64, r.n_c, r.k64, r.L64, r.N, -1, &sig_f, &prev_f, t);
+  } else {
+    bool v;
+    const int pf = inertia::spread(0, n, f, 1, &v, P);
+    const int pb = (f == 1) ? 0 : inertia::spread(0, n, f - 1, 1, &v, P);
+    inertia::Bracket br;
+    found = inertia::from_sampled_bound(r.c64, r.n_c, r.k64, r.L64, r.N, 0, false, 0, sig0, pb, pf, &br, &sig_f,
+                                        &prev_f, t);
+    if (found == inertia::kLocated)
+      found = inertia::finish(r.c64, r.n_c, r.k64, r.L64, r.N, sig0, br, &sig_f, &prev_f, t);
+  }
+  wc.sweep += t.scan;
+  wc.check += t.check;
+  if (found < 0) {
+    write_no_pick(o, MASW_STATUS_NOT_FOUND, lane == 0);
+    wc.useful += (unsigned long long)r.n_c;
+  } else {
+    wc.useful += (unsigned long long)(found + 1);
+    wc.refine += refine_and_write(o, r.c64, r.k64, r.L64, r.N, found, sig_f, prev_f);
+  }
+}
+
+// With G = 8 the kernel is held to 128 VGPRs (4 wavefronts per SIMD), so two
+// workgroups fit on a CU, as for the batch sweep.  INERTIA (a server started
+// with search_inertia) runs FP64 items with the inertia-count search instead
+// of walking them; it needs more registers, so it is an instantiation of its
+// own and the walking ticks keep their allocation.
+template <int G, bool INERTIA>
+__global__ __launch_bounds__(64 * G) __attribute__((amdgpu_waves_per_eu((G >= 8 && !INERTIA) ? 4 : 1)))
 void tick_kernel(TickArgs a) {
   __shared__ SweepShared<G> sh;
   WorkCount wc;
@@ -1000,6 +1058,10 @@ void tick_kernel(TickArgs a) {
       done = true;
     } else if (sd.prec == MASW_PREC_SPLIT) {
       done = run_item<kModeSplit, G>(r, st, budget, sh, wc, o, kNoCoop, a.counters);
+    } else if (INERTIA) {
+      inertia_tick_item<G>(r, sh, wc, o);  // the whole search in this tick
+      st.done = 1;
+      done = true;
     } else {
       done = run_item<kModeFP64, G>(r, st, budget, sh, wc, o, kNoCoop, a.counters);
     }
@@ -1137,18 +1199,22 @@ hipError_t launch_prep(const PrepArgs& a, const CoopInitArgs& ci, int single_N, 
   return hipGetLastError();
 }
 
-static const void* tick_symbol(int G) {
+static const void* tick_symbol(int G, bool inertia) {
   switch (G) {
-    case 1: return reinterpret_cast<const void*>(&tick_kernel<1>);
-    case 2: return reinterpret_cast<const void*>(&tick_kernel<2>);
-    case 4: return reinterpret_cast<const void*>(&tick_kernel<4>);
-    case 8: return reinterpret_cast<const void*>(&tick_kernel<8>);
+    case 1: return inertia ? reinterpret_cast<const void*>(&tick_kernel<1, true>)
+                           : reinterpret_cast<const void*>(&tick_kernel<1, false>);
+    case 2: return inertia ? reinterpret_cast<const void*>(&tick_kernel<2, true>)
+                           : reinterpret_cast<const void*>(&tick_kernel<2, false>);
+    case 4: return inertia ? reinterpret_cast<const void*>(&tick_kernel<4, true>)
+                           : reinterpret_cast<const void*>(&tick_kernel<4, false>);
+    case 8: return inertia ? reinterpret_cast<const void*>(&tick_kernel<8, true>)
+                           : reinterpret_cast<const void*>(&tick_kernel<8, false>);
   }
   return nullptr;
 }
 
-int tick_blocks_per_cu(int G) {
-  const void* f = tick_symbol(G);
+int tick_blocks_per_cu(int G, bool inertia) {
+  const void* f = tick_symbol(G, inertia);
   int n = 0;
   if (!f || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 64 * G, 0) != hipSuccess) return 0;
   return n;
@@ -1162,7 +1228,7 @@ hipError_t launch_admit(const AdmitList* list_dev, int n, int max_raw, int32_t* 
 }
 
 hipError_t launch_tick(int G, int blocks, hipStream_t s, const TickArgs& a) {
-  const void* f = tick_symbol(G);
+  const void* f = tick_symbol(G, a.inertia != 0);
   if (!f) return hipErrorInvalidValue;
   void* args[] = {const_cast<TickArgs*>(&a)};
   return hipLaunchKernel(f, dim3(blocks), dim3(64 * G), args, 0, s);

@@ -385,7 +385,8 @@ int masw_server_start(masw_ctx* ctx, const masw_server_opts* opts) {
   if (o.rounds_per_tick == 0) o.rounds_per_tick = 16;
   if (o.tick_timeout_us == 0) o.tick_timeout_us = 10000000;
   if (o.max_layers < 0 || o.max_layers > MASW_MAX_LAYERS || o.max_lambda < 1 || o.max_grid < 2 ||
-      o.rounds_per_tick < 1 || o.tick_timeout_us < 0)
+      o.rounds_per_tick < 1 || o.tick_timeout_us < 0 || (o.search_inertia != 0 && o.search_inertia != 1) ||
+      o.reserved != 0)
     return fail(MASW_EINVAL, "server opts: out of range");
   std::lock_guard<std::mutex> lock(ctx->mu);
   if (ctx->server) return fail(MASW_EBUSY, "server already running");
@@ -453,6 +454,7 @@ int masw_server_start(masw_ctx* ctx, const masw_server_opts* opts) {
   ta.slot_remaining = s->remaining_dev;
   ta.counters = s->counters_dev;
   ta.refine = 1;
+  ta.inertia = o.search_inertia;
   ta.refine_rel = ctx->refine_rel;
   void* dp = nullptr;
   if (hipHostGetDevicePointer(&dp, s->out_ct, 0) != hipSuccess) return bail("hipHostGetDevicePointer failed");
@@ -467,7 +469,7 @@ int masw_server_start(masw_ctx* ctx, const masw_server_opts* opts) {
   ta.host_done = static_cast<int32_t*>(dp);
   for (int gi = 0; gi < 4; ++gi) {
     const int G = 1 << gi;
-    s->bpc[gi] = tick_blocks_per_cu(G);
+    s->bpc[gi] = tick_blocks_per_cu(G, o.search_inertia != 0);
     const int blocks = ctx->cus * std::max(1, s->bpc[gi]);
     s->blocks[gi] = blocks;
     if (hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
@@ -480,6 +482,14 @@ int masw_server_start(masw_ctx* ctx, const masw_server_opts* opts) {
     if (e != hipSuccess || e2 != hipSuccess) return bail("capturing the tick graph failed");
     if (hipGraphInstantiate(&s->exec[gi], g, nullptr, nullptr, 0) != hipSuccess)
       return bail("hipGraphInstantiate failed");
+  }
+  // One empty replay of each graph (no units: every workgroup makes its one
+  // final claim and exits), so that no served tick pays a first launch.
+  for (int gi = 0; gi < 4; ++gi) {
+    s->desc_host->base = s->queue_base;
+    if (hipGraphLaunch(s->exec[gi], s->stream) != hipSuccess || hipStreamSynchronize(s->stream) != hipSuccess)
+      return bail("warming the tick graphs failed");
+    s->queue_base += uint32_t(s->blocks[gi]);
   }
   s->stats.pool_bytes = s->pool_size;
   ctx->sync_size = (ctx->arena_size - region) & ~(kAlign - 1);

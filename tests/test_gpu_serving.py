@@ -94,6 +94,35 @@ def test_alone_equals_in_mix(ctx):
     print(f"served {2 * len(reqs)} requests, stats {stats}", flush=True)
 
 
+def test_inertia_server_matches_the_walk(ctx):
+    # search_inertia: FP64 requests take the inertia-count search, each within
+    # one tick; results equal the synchronous walk's bit for bit, mixed with
+    # split requests (which walk) in the same ticks
+    with pytest.raises(M.MaswError) as e:
+        M.masw_server_start(ctx.ctx, search_inertia=2)
+    assert e.value.code == M.MASW_EINVAL
+    c = WL.serving_grid()
+    reqs = chain_requests(32, seed=7)
+    prec_of = lambda i: M.MASW_PREC_SPLIT if i % 4 == 3 else M.MASW_PREC_FP64
+    M.masw_server_start(ctx.ctx, search_inertia=1)
+    tickets = [(submit(ctx, c, lam, m, prec_of(i)), len(lam)) for i, (m, lam) in enumerate(reqs)]
+    got = [wait(ctx, t, W) for t, W in tickets]
+    stats = M.masw_server_get_stats(ctx.ctx)
+    M.masw_server_stop(ctx.ctx)
+    for i, ((m, lam), (out, info)) in enumerate(zip(reqs, got)):
+        want = ctx.curve(c, lam, m, prec_of(i))
+        for x, y in zip(out, want):
+            np.testing.assert_array_equal(x, y)
+        if prec_of(i) == M.MASW_PREC_FP64:
+            assert info["ticks"] == 1, info      # the whole search in one tick
+    wl = WL.two_layer_case()
+    M.masw_server_start(ctx.ctx, search_inertia=1)
+    out, info = wait(ctx, submit(ctx, wl.c_test, wl.lambdas[0], wl.models[0], M.MASW_PREC_FP64), 30)
+    M.masw_server_stop(ctx.ctx)
+    assert list(out[1]) == [p.idx for p in O.dispersion_curve(wl.lambdas[0], wl.c_test, wl.models[0])]
+    print(f"inertia server: {len(reqs)} requests, stats {stats}", flush=True)
+
+
 def test_poll_wait_and_ticket_lifecycle(ctx):
     wl = WL.fine_scale_case()
     m, lam, c = wl.models[0], wl.lambdas[0][::4].copy(), wl.c_test
