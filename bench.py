@@ -73,14 +73,14 @@ def classify_flops(evals: int, layers: int, steps: int) -> float:
 # classification), the workload and the
 # launch, so a changed kernel reports null until it is measured again.
 MEASURED_TRAFFIC = {
-    ("edc499b42c3e80e9", "fine_scale_N20_1000lam_115001c", "sweep_kernel<FP64,G=8>"):
-        4885.19 * 1024 * 2.000 + 2586.88 * 1024 * 1.000,
-    ("edc499b42c3e80e9", "batch_4096models_19001c", "sweep_kernel<FP64,G=1>"):
-        266775.0 * 1024 * 2.000 + 148119.0 * 1024 * 1.000,
-    ("1b3c9807d56ef5cf", "fine_scale_N20_1000lam_115001c", "inertia_kernel"):
-        881.604 * 1024 * 2.000 + 1546.88 * 1024 * 1.000,
-    ("1b3c9807d56ef5cf", "batch_4096models_19001c", "inertia_kernel"):
-        41346.8 * 1024 * 2.000 + 34384.4 * 1024 * 1.000,
+    ("9a6d510802a64b31", "fine_scale_N20_1000lam_115001c", "sweep_kernel<FP64,G=8>"):
+        4824.69 * 1024 * 2.000 + 2597.37 * 1024 * 1.000,
+    ("9a6d510802a64b31", "batch_4096models_19001c", "sweep_kernel<FP64,G=1>"):
+        266847.0 * 1024 * 2.000 + 148185.0 * 1024 * 1.000,
+    ("293922657f2d89cc", "fine_scale_N20_1000lam_115001c", "inertia_kernel"):
+        881.0 * 1024 * 2.000 + 1546.88 * 1024 * 1.000,
+    ("293922657f2d89cc", "batch_4096models_19001c", "inertia_kernel"):
+        41416.2 * 1024 * 2.000 + 34320.4 * 1024 * 1.000,
     ("6da9bc50b01ce006", "classify_batch_4096models_19001c", "classify_kernel"):
         14642.625 * 1024 * 2.000 + 21872.34 * 1024 * 1.000,
 }
