@@ -87,7 +87,7 @@ MEASURED_TRAFFIC = {
 
 # (timed steps, warm-up steps) per workload when the command line gives none.
 DEFAULT_STEPS = {"fine_scale": (200, 50), "two_layer": (200, 50), "batch": (5, 1), "uniform": (20, 3),
-                 "chains": (20, 3), "classify": (5, 2)}
+                 "chains": (100, 3), "classify": (5, 2)}
 
 KERNEL_SOURCES = ["masw_internal.hpp", "masw_math.hpp", "masw_special.hpp", "masw_pick.hpp", "masw_kernels.hip"]
 CLASSIFY_SOURCES = ["masw_classify.hip"]
@@ -370,12 +370,31 @@ def chains_bench(M, torch, a):
     useful[0] = 0
     ev.models_evaluated = 0
     M.masw_get_timing(ctx, reset=True)
+    import gc
+    gc.collect()
+    gc.disable()  # no collector pause inside a timed run
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     res = I.run_chains(ev, start, a.steps, step=0.02, temperature=T, seed=9)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    gc.enable()
     tm = M.masw_get_timing(ctx, reset=True)
+    # the same chains with the FP64 inertia-count search: its picks are the
+    # FP64 walk's, which the split path's equal on these workloads
+    ev_i = I.DeviceEvaluator(ctx, c, site.lambdas, C_e, inertia=True)
+    I.run_chains(ev_i, start[:8], max(1, a.warmup), step=0.02, temperature=T, seed=1)
+    ev_i.models_evaluated = 0
+    M.masw_get_timing(ctx, reset=True)
+    gc.collect()
+    gc.disable()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res_i = I.run_chains(ev_i, start, a.steps, step=0.02, temperature=T, seed=9)
+    torch.cuda.synchronize()
+    wall_i = time.perf_counter() - t0
+    gc.enable()
+    tm_i = M.masw_get_timing(ctx, reset=True)
     ctx_obj.close()
     steps = a.steps + 1  # the start models are evaluated too
     print(json.dumps({
@@ -389,6 +408,11 @@ def chains_bench(M, torch, a):
         "acceptance": res.acceptance_rate,
         "mean_misfit_start": float(np.nanmean(res.start_misfit)),
         "mean_misfit_best": float(np.nanmean(res.best_misfit)),
+        "inertia": {"ms_per_step": wall_i / steps * 1e3, "models_per_s": ev_i.models_evaluated / wall_i,
+                    "sweep_ms_per_step": tm_i["sweep_ms_sum"] / max(1, tm_i["launches"]),
+                    "speedup_vs_split": wall / wall_i, "acceptance": res_i.acceptance_rate,
+                    "same_best_misfits": bool(np.array_equal(res_i.best_misfit, res.best_misfit,
+                                                             equal_nan=True))},
     }), flush=True)
 
 

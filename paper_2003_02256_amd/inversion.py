@@ -23,7 +23,8 @@ from typing import Callable, List, Sequence
 
 import numpy as np
 
-from . import MASW_NO_REFINE, MASW_PREC_SPLIT, masw_dispersion_batch, masw_misfit
+from . import (MASW_NO_REFINE, MASW_PREC_FP64, MASW_PREC_SPLIT, MASW_SEARCH_INERTIA, masw_dispersion_batch,
+               masw_misfit)
 
 
 @dataclass
@@ -158,15 +159,20 @@ class DeviceEvaluator:
     experimental curve C_e.  One call flattens the models, runs the batched
     sweep with device-resident outputs (C_t only: the misfit uses the grid
     velocity of each pick, so the root refinement is skipped), reduces the
-    misfits on the device and copies back only the misfits."""
+    misfits on the device and copies back only the misfits.  With
+    inertia=True the picks come from the FP64 inertia-count search
+    (MASW_SEARCH_INERTIA; prec is then FP64), whose C_t equal the FP64 walk's
+    bit for bit."""
 
-    def __init__(self, ctx, c_test, lambdas, C_e, prec: int = MASW_PREC_SPLIT, device: str = "cuda:0"):
+    def __init__(self, ctx, c_test, lambdas, C_e, prec: int = MASW_PREC_SPLIT, device: str = "cuda:0",
+                 inertia: bool = False):
         import torch
 
         self.torch = torch
         self.ctx = ctx
         self.dev = torch.device(device)
-        self.prec = prec
+        self.prec = MASW_PREC_FP64 if inertia else prec
+        self.flags = MASW_NO_REFINE | (MASW_SEARCH_INERTIA if inertia else 0)
         self.lam = np.ascontiguousarray(lambdas, np.float64)
         self.C_e = np.ascontiguousarray(C_e, np.float64)
         if self.C_e.shape != self.lam.shape:
@@ -196,7 +202,7 @@ class DeviceEvaluator:
         idx = torch.empty(W, dtype=i32, device=dev)
         st = torch.empty(W, dtype=i32, device=dev)
         masw_dispersion_batch(self.ctx, self.c, layer_off, t(pop.h), t(pop.alpha), t(pop.beta), t(pop.rho),
-                              lam_off, lam, self.prec, MASW_NO_REFINE, None, ct, idx, st, None)
+                              lam_off, lam, self.prec, self.flags, None, ct, idx, st, None)
         mis = torch.empty(n, dtype=f64, device=dev)
         masw_misfit(self.ctx, lam_off, ct, ce, 0, None, mis)
         self.models_evaluated += n

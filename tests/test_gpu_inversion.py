@@ -22,10 +22,11 @@ def setup(gpu):
     ctx.close()
 
 
-@pytest.mark.parametrize("prec", [M.MASW_PREC_FP64, M.MASW_PREC_SPLIT])
-def test_device_misfit_matches_oracle(setup, prec):
+@pytest.mark.parametrize("prec,inertia", [(M.MASW_PREC_FP64, False), (M.MASW_PREC_SPLIT, False),
+                                          (M.MASW_PREC_FP64, True)])
+def test_device_misfit_matches_oracle(setup, prec, inertia):
     ctx, truth, lam, c, C_e = setup
-    ev = I.DeviceEvaluator(ctx.ctx, c, lam, C_e, prec=prec)
+    ev = I.DeviceEvaluator(ctx.ctx, c, lam, C_e, prec=prec, inertia=inertia)
     assert ev([truth])[0] == 0.0  # the true model reproduces its own curve
     rng = np.random.Generator(np.random.PCG64(21))
     models = [I.perturb(rng, truth, 0.08) for _ in range(6)]
@@ -54,3 +55,17 @@ def test_chains_reduce_misfit(setup):
     assert 0.0 < res.acceptance_rate < 1.0
     # the recorded best misfits are those of the best models, evaluated again
     np.testing.assert_array_equal(ev(res.best_models), res.best_misfit)
+
+
+def test_inertia_evaluator_equals_the_walk_on_a_population(setup):
+    # 64 proposals on the serving grid: the inertia search's C_t are the
+    # walk's, so the misfits are equal bit for bit
+    ctx, truth, lam, c, C_e = setup
+    base = WL.chain_bases(8, seed=5)[3]
+    rng = np.random.Generator(np.random.PCG64(4))
+    models = [I.perturb(rng, base.model, 0.05) for _ in range(64)]
+    grid = WL.serving_grid()
+    C_obs = np.full(len(base.lambdas), 300.0)
+    walk = I.DeviceEvaluator(ctx.ctx, grid, base.lambdas, C_obs, prec=M.MASW_PREC_FP64)(models)
+    fast = I.DeviceEvaluator(ctx.ctx, grid, base.lambdas, C_obs, inertia=True)(models)
+    np.testing.assert_array_equal(fast, walk)
