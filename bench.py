@@ -588,7 +588,7 @@ def main():
     a.warmup = warmup if a.warmup is None else a.warmup
     if a.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported (the dispersion path has no "
-              f"cross-GPU exchange and this build runs on a single MI355X)", file=sys.stderr)
+              f"cross-GPU exchange; the library runs on a single MI355X)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -23,7 +23,7 @@ def _gpu_available() -> bool:
 
 @pytest.fixture(scope="session")
 def gpu():
-    """Skip a GPU test when no device is present (never on the GPU machine)."""
+    """Skip a GPU test when no device is present."""
     if not _gpu_available():
         pytest.skip("no GPU device")
     return True
