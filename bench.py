@@ -73,15 +73,15 @@ def classify_flops(evals: int, layers: int, steps: int) -> float:
 # classification), the workload and the
 # launch, so a changed kernel reports null until it is measured again.
 MEASURED_TRAFFIC = {
-    ("9a6d510802a64b31", "fine_scale_N20_1000lam_115001c", "sweep_kernel<FP64,G=8>"):
+    ("9eafcc39db7e92e4", "fine_scale_N20_1000lam_115001c", "sweep_kernel<FP64,G=8>"):
         4824.69 * 1024 * 2.000 + 2597.37 * 1024 * 1.000,
-    ("9a6d510802a64b31", "batch_4096models_19001c", "sweep_kernel<FP64,G=1>"):
+    ("9eafcc39db7e92e4", "batch_4096models_19001c", "sweep_kernel<FP64,G=1>"):
         266847.0 * 1024 * 2.000 + 148185.0 * 1024 * 1.000,
-    ("293922657f2d89cc", "fine_scale_N20_1000lam_115001c", "inertia_kernel"):
+    ("de7b31af11e39fb6", "fine_scale_N20_1000lam_115001c", "inertia_kernel"):
         881.0 * 1024 * 2.000 + 1546.88 * 1024 * 1.000,
-    ("293922657f2d89cc", "batch_4096models_19001c", "inertia_kernel"):
+    ("de7b31af11e39fb6", "batch_4096models_19001c", "inertia_kernel"):
         41416.2 * 1024 * 2.000 + 34320.4 * 1024 * 1.000,
-    ("6da9bc50b01ce006", "classify_batch_4096models_19001c", "classify_kernel"):
+    ("ef681d38c885d05d", "classify_batch_4096models_19001c", "classify_kernel"):
         14642.625 * 1024 * 2.000 + 21872.34 * 1024 * 1.000,
 }
 
@@ -96,11 +96,17 @@ INERTIA_SOURCES = ["masw_internal.hpp", "masw_math.hpp", "masw_special.hpp", "ma
 
 
 def kernel_source_hash(files=KERNEL_SOURCES) -> str:
+    """sha256[:16] of the sources' code: comments, trailing blanks and empty
+    lines removed, so that an edit of a comment keeps a measurement valid."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in files:
-        with open(os.path.join(ROOT, "paper_2003_02256_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2003_02256_amd", "csrc", f), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        lines = (re.sub(r"//.*$", "", line).rstrip() for line in text.splitlines())
+        h.update("\n".join(line for line in lines if line).encode())
     return h.hexdigest()[:16]
 
 

@@ -51,9 +51,9 @@ __device__ int run_wavelength(const SweepArgs& a, int g, int pred, Tally& t) {
 // takes wavelengths w, w + W, ...  Otherwise each wavefront claims runs of
 // `chunk` consecutive wavelengths from an atomic queue, and within a run the
 // picks of the previous wavelengths of the same model predict the next pick
-// (round P of search()).  Three wavefronts per SIMD (at most 168 VGPRs, two
-// of them spilled) ran the 4096-model batch 6% faster than the two that 173
-// VGPRs allow.
+// (round P of search()).  Three wavefronts per SIMD (at most 168 VGPRs,
+// with a few spilled) ran the 4096-model batch 6% faster than the two that
+// the unconstrained 173 VGPRs allow.
 __global__ __launch_bounds__(64 * kInertiaWaves) __attribute__((amdgpu_waves_per_eu(3))) void inertia_kernel(
     SweepArgs a, int chunk) {
   __shared__ unsigned long long s_cnt[kInertiaWaves][7];
