@@ -236,3 +236,44 @@ def test_runs_with_predictions_across_models_and_invalid_items(torch_dev, ctx):
         np.testing.assert_array_equal(y, x, err_msg=what)
     assert np.sum(got[2] == M.MASW_STATUS_INVALID) >= 4 * 50 + 2
     assert st["check_evals"] < 64 * len(got[1]) // 2   # runs of 4 here: most wavelengths were predicted
+
+
+def _random_model(rng, N):
+    """A layered model outside the workloads' recipes: thicknesses over two
+    decades, velocities that may fall with depth (several low-velocity
+    layers, a half-space slower than some layers), Poisson ratios 0.05-0.45."""
+    h = np.exp(rng.uniform(np.log(0.2), np.log(20.0), size=N))
+    beta = rng.uniform(80.0, 600.0, size=N + 1)
+    nu = rng.uniform(0.05, 0.45, size=N + 1)
+    alpha = WL.alpha_from_poisson(beta, nu)
+    rho = rng.uniform(1500.0, 2600.0, size=N + 1)
+    return WL.Model(h, alpha, beta, rho)
+
+
+@pytest.mark.parametrize("seed,dc,n_c,lo", [(101, 0.5, 3001, 40.0), (102, 0.05, 12001, 60.0),
+                                            (103, 0.01, 40001, 90.0)])
+def test_random_models_equal_the_walk(torch_dev, ctx, seed, dc, n_c, lo):
+    # random models (N 1-40) and wavelengths 0.3-150 m on three grids; with
+    # many wavelengths per model the wavefronts also take predicted runs.
+    # Outputs equal the walk's bit for bit; an index that differs would be
+    # excused only inside the FP64 noise band (none has been seen).
+    rng = np.random.Generator(np.random.PCG64(seed))
+    models = [_random_model(rng, int(rng.integers(1, 41))) for _ in range(96)]
+    lambdas = [np.sort(np.exp(rng.uniform(np.log(0.3), np.log(150.0), size=int(rng.integers(20, 400)))))
+               for _ in models]
+    c = WL.uniform_grid(lo, dc, n_c)
+    walk = dev_batch(torch_dev, ctx, c, models, lambdas, FP64)
+    got = dev_batch(torch_dev, ctx, c, models, lambdas, FP64, INERTIA)
+    st = ctx.stats()
+    off = np.concatenate([[0], np.cumsum([len(l) for l in lambdas])])
+    diff = np.nonzero(got[1] != walk[1])[0]
+    for w in diff:
+        mi = int(np.searchsorted(off, w, side="right") - 1)
+        lam = float(lambdas[mi][w - off[mi]])
+        pts = {p for i in (int(got[1][w]), int(walk[1][w])) if i > 0 for p in (i - 1, i)}
+        assert any(O.in_noise_band(lam, float(c[p]), models[mi]) for p in pts), (w, got[1][w], walk[1][w])
+    same = got[1] == walk[1]
+    for x, y, what in zip(walk, got, ("C_t", "idx", "status", "c_ref")):
+        np.testing.assert_array_equal(y[same], x[same], err_msg=what)
+    print(f"random seed {seed}: {len(got[1])} wavelengths, {len(diff)} index differences (noise band), "
+          f"found {int(np.sum(got[1] >= 0))}, walked {st['sweep_evals']}, counts {st['inertia_evals']}", flush=True)
