@@ -568,3 +568,41 @@ def test_budget_exhaustion_is_refused_before_any_work(gpu):
         got = c.curve(small.c_test, small.lambdas[0], small.models[0])
         want = [O.dispersion_point(l, small.c_test, small.models[0], refine=False).idx for l in small.lambdas[0][:5]]
         assert got[1][:5].tolist() == want
+
+
+def test_random_models_match_oracle(torch_dev, ctx):
+    # 12 random models outside the workloads' recipes (N 1-12, thicknesses
+    # 0.2-20 m, velocities falling as well as rising with depth, Poisson
+    # ratios 0.05-0.45), 5 wavelengths each on a 0.5 m/s grid: the FP64 walk,
+    # the split path and the inertia search against the oracle
+    rng = np.random.Generator(np.random.PCG64(707))
+    c = WL.uniform_grid(40.0, 0.5, 3001)
+    for trial in range(12):
+        N = int(rng.integers(1, 13))
+        h = np.exp(rng.uniform(np.log(0.2), np.log(20.0), size=N))
+        beta = rng.uniform(80.0, 600.0, size=N + 1)
+        alpha = WL.alpha_from_poisson(beta, rng.uniform(0.05, 0.45, size=N + 1))
+        m = WL.Model(h, alpha, beta, rng.uniform(1500.0, 2600.0, size=N + 1))
+        lam = np.sort(np.exp(rng.uniform(np.log(0.3), np.log(150.0), size=5)))
+        want_idx, want_st, want_ref = oracle_curve(lam, c, m)
+        for prec, flags, name in ((M.MASW_PREC_FP64, 0, "walk"), (M.MASW_PREC_SPLIT, 0, "split"),
+                                  (M.MASW_PREC_FP64, M.MASW_SEARCH_INERTIA, "inertia")):
+            ct, idx, st, cr = dev_curve(torch_dev, ctx, c, lam, m, prec, flags)
+            for w in range(len(lam)):
+                i = int(want_idx[w])
+                assert (int(idx[w]), int(st[w])) == (i, want_st[w]), (trial, name, w, idx[w], i)
+                if i < 1:
+                    continue
+                assert ct[w] == c[i]
+                k = 2 * math.pi / lam[w]
+                fine = O.det_sign(k, np.linspace(c[i - 1], c[i], 2001), m)
+                if np.count_nonzero(fine[1:] != fine[:-1]) <= 1:
+                    # one sign change in the grid step: the refined roots agree
+                    assert abs(cr[w] - want_ref[w]) <= REL_TOL * want_ref[w], (trial, name, w, cr[w], want_ref[w])
+                else:
+                    # several changes in the step (poles and zeros closer than
+                    # the grid): any of them is a valid refinement, so check
+                    # that the device's root is one
+                    d = 2e-9 * cr[w]
+                    assert c[i - 1] <= cr[w] <= c[i]
+                    assert O.det_sign(k, cr[w] - d, m)[0] != O.det_sign(k, cr[w] + d, m)[0], (trial, name, w)
