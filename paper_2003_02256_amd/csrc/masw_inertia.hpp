@@ -14,6 +14,10 @@
 // E = J + P = s + 2P is non-decreasing, and s changes only where E does, so
 // the first change of sign(det K) along the grid is found by a search on E
 // instead of a walk (search() below):
+//   0. Prediction (when the picks of neighbouring wavelengths predict this
+//      one): counts at c_test[0], before a 62-point window around the
+//      prediction and in it; equal counts before the window prove no change
+//      there, and the window's first differing count is the change of E.
 //   1. Sampling: det K's sign at c_test[0] and 63 spread grid points; the
 //      first sampled sign that differs bounds the pick from above, so the
 //      counts stay at velocities near it (a layer needs more sublayers, see
