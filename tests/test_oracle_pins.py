@@ -385,6 +385,137 @@ def test_noise_band_only_at_the_root():
     assert not O.in_noise_band(3.0, cR - 0.01, m)
 
 
+# P9: the FP64 noise band against 50-digit determinants.  K is rebuilt in
+# mpmath from the P-SV equations of motion (transfer matrices for the layers,
+# decaying eigen-solutions for the half-space; not the oracle's entry
+# formulas), and its exact determinant is compared with the oracle's FP64
+# determinant (dense LU) at grid points approaching a root from both sides.
+def _mp_sysmat(k, c, alpha, beta, rho):
+    k_, c_, a_, b_, r_ = (mp.mpf(v) for v in (k, c, alpha, beta, rho))
+    mu = r_ * b_ ** 2
+    lam = r_ * a_ ** 2 - 2 * mu
+    M = lam + 2 * mu
+    w2 = (k_ * c_) ** 2
+    A = mp.zeros(4, 4)
+    A[0, 1] = k_
+    A[0, 2] = 1 / mu
+    A[1, 0] = -k_ * lam / M
+    A[1, 3] = 1 / M
+    A[2, 0] = -r_ * w2 + k_ * k_ * 4 * mu * (lam + mu) / M
+    A[2, 3] = k_ * lam / M
+    A[3, 1] = -r_ * w2
+    A[3, 2] = -k_
+    return A
+
+
+def mp_stiffness_det(k, c, model):
+    """det K(k, c) in the working mpmath precision: each layer's stiffness
+    from its transfer matrix exp(A h) (loads vs face displacements), the
+    half-space's from its decaying eigen-solutions, assembled as in the
+    stiffness method.  Similar to the oracle's K by sign flips of the vertical
+    degrees of freedom, so the determinant is the same (c below the
+    half-space's S velocity)."""
+    N = model.n_layers
+    n = 2 * (N + 1)
+    K = mp.zeros(n, n)
+    for j in range(N):
+        P = mp.expm(_mp_sysmat(k, c, model.alpha[j], model.beta[j], model.rho[j]) * mp.mpf(model.h[j]))
+        Puu, Put, Ptu, Ptt = P[0:2, 0:2], P[0:2, 2:4], P[2:4, 0:2], P[2:4, 2:4]
+        iPut = mp.inverse(Put)
+        blocks = ((iPut * Puu, -iPut), (Ptu - Ptt * iPut * Puu, Ptt * iPut))
+        for bi in range(2):
+            for bj in range(2):
+                for a in range(2):
+                    for b in range(2):
+                        K[2 * j + 2 * bi + a, 2 * j + 2 * bj + b] += blocks[bi][bj][a, b]
+    ev, V = mp.eig(_mp_sysmat(k, c, model.alpha[N], model.beta[N], model.rho[N]))
+    order = sorted(range(4), key=lambda i: mp.re(ev[i]))[:2]
+    Vd = mp.matrix(4, 2)
+    for q, i in enumerate(order):
+        for r in range(4):
+            Vd[r, q] = mp.re(V[r, i])
+    H = -(Vd[2:4, 0:2] * mp.inverse(Vd[0:2, 0:2]))
+    for a in range(2):
+        for b in range(2):
+            K[2 * N + a, 2 * N + b] += H[a, b]
+    return mp.det(K)
+
+
+def _noise_cases():
+    b = 400.0
+    yield halfspace_model(math.sqrt(3.0) * b, b, 2000.0), 3.0
+    yield halfspace_model(b * math.sqrt(1.2 / 0.2), b, 1800.0), 10.0
+    m1 = WL.Model(np.array([3.0]), np.array([300.0, 700.0]), np.array([150.0, 380.0]), np.array([1800.0, 2000.0]))
+    yield m1, 2.0
+    yield m1, 9.0
+    two = WL.two_layer_case().models[0]
+    for lam in (1.0, 9.87, 40.0):
+        yield two, lam
+    m3 = WL.Model(np.array([1.5, 2.5, 4.0]), np.array([330.0, 480.0, 620.0, 900.0]),
+                  np.array([170.0, 240.0, 330.0, 480.0]), np.array([1750.0, 1850.0, 1950.0, 2050.0]))
+    for lam in (1.5, 6.0, 25.0):
+        yield m3, lam
+
+
+NOISE_FACTOR = 4.0   # the measured FP64 error stays below this multiple of cond_2 2(N+1) 2^-53
+
+
+def test_noise_band_calibrated_against_50_digit_determinants():
+    """Reading 11's band against exact determinants on N = 0..3 models, at
+    grid points 10^-16.5 .. 10^-11.5 relative from a root on both sides:
+      * every FP64 sign that differs from the exact sign lies in the band;
+      * the FP64 determinant's relative error never exceeds NOISE_FACTOR
+        times the first-order bound cond_2(K) 2(N+1) 2^-53 the band is built on;
+      * calibration of the threshold: per root, R = (band half-width) /
+        (half-width of the region where the measured error reaches 1e-2);
+        the band is meant to cover that 1% region, so min R over the roots
+        must lie in [0.25, 2], i.e. in the tightest case the band ends
+        within a factor of a few of where the FP64 determinant stops being
+        1%-accurate (a threshold 10 times larger or smaller moves min R by a
+        factor of 10 and fails), and max R stays below 50.
+    """
+    mp.mp.dps = 50
+    u = 2.0 ** -53
+    ratios = []
+    for model, lam in _noise_cases():
+        k = 2.0 * math.pi / lam
+        grid = np.arange(50.0, float(model.beta[-1]) - 0.01, 0.05)
+        p = O.dispersion_point(lam, grid, model)
+        # the exact root inside the oracle's refined bracket (width <= 1e-9 c)
+        root = mp.findroot(lambda x: mp_stiffness_det(k, x, model),
+                           (mp.mpf(p.c_ref) * (1 - mp.mpf(2e-9)), mp.mpf(p.c_ref) * (1 + mp.mpf(2e-9))),
+                           solver="illinois", verify=False)
+        lo_s = mp.sign(mp_stiffness_det(k, root * (1 - mp.mpf(10) ** -30), model))
+        hi_s = mp.sign(mp_stiffness_det(k, root * (1 + mp.mpf(10) ** -30), model))
+        assert lo_s != hi_s, (model.n_layers, lam)     # a simple root, located to 1e-30
+        assert abs(root - p.c_ref) <= 1e-9 * p.c_ref
+        w_band = w_meas = 0.0
+        for e in np.arange(-16.5, -11.4, 0.25):
+            for side in (-1, 1):
+                c = float(root * (1 + side * mp.mpf(10) ** e))
+                exact = mp_stiffness_det(k, mp.mpf(c), model)
+                sig, phase, logabs = O.det_sign_logabs(k, np.array([c]), model)
+                d64 = mp.mpf(float(phase[0].real)) * mp.exp(mp.mpf(float(logabs[0])))
+                err = float(abs(d64 - exact) / abs(exact))
+                K = O.stiffness_matrix(k, np.array([c]), model.h, model.alpha, model.beta, model.rho)[0]
+                bound = float(np.linalg.cond(K) * K.shape[0] * u)
+                band = O.in_noise_band(lam, c, model)
+                assert err <= NOISE_FACTOR * bound, (model.n_layers, lam, e, err, bound)
+                if int(sig[0]) != int(mp.sign(exact)):
+                    assert band, (model.n_layers, lam, e, "FP64 sign wrong outside the band")
+                if band:
+                    w_band = max(w_band, 10.0 ** e)
+                if err >= 1e-2:
+                    w_meas = max(w_meas, 10.0 ** e)
+        # beyond the sampled offsets neither the band nor the 1% region reaches
+        for e in (-11.0, -9.0, -6.0):
+            assert not O.in_noise_band(lam, float(root * (1 + mp.mpf(10) ** e)), model)
+        assert w_band > 0.0 and w_meas > 0.0, (model.n_layers, lam)
+        ratios.append(w_band / w_meas)
+    assert 0.25 <= min(ratios) <= 2.0, ratios
+    assert max(ratios) <= 50.0, ratios
+
+
 # ---------------------------------------------------------------------------
 # P10: the propagator secular function and the zero/pole classification
 # (oracle/propagator.py), against the equations of motion, the Rayleigh
