@@ -5,16 +5,28 @@ A step is one whole dispersion-curve job through the C ABI: staging and
 precompute, work ordering, the early-exit sweep with its FP64 refinement, and
 the results in HBM.  Inputs are resident in HBM before timing starts.
 
-Default workload: the 20-layer fine-scale model, 1000 wavelengths log-spaced
-1-100 m, c 50-1200 m/s at 0.01 m/s (115,001 values), plain FP64.  The split
-path (FP32 sweep + FP64 re-check + FP64 refinement) is timed on the same
-inputs and reported beside it with its root error against the FP64 path.
+Default workload: the batch of 4096 seeded models of uneven sizes (N 3-30,
+50-500 wavelengths log-spaced 1-80 m each, about 1.1 M wavelengths; c 50-1000
+m/s at 0.05 m/s, 19,001 values; about 15% with a low-velocity layer), one
+persistent launch per job.  Headline: the plain FP64 path.  The split path
+(FP32 sweep + FP64 re-check and inertia-count certificate + FP64 refinement)
+and the FP64 inertia-count search are timed on the same inputs and reported
+beside it.  Legs of the default run:
+  * fine_scale: the 20-layer model, 1000 wavelengths log-spaced 1-100 m,
+    c 50-1200 m/s at 0.01 m/s (115,001 values), the same three paths;
+  * serving: a short replay of the 2000 req/s trace, p50/p99 latency of the
+    split and plain-FP64 servers;
+  * two_layer_vs_oracle (with the CPU leg): the two-layer case's picks and
+    refined roots against the oracle, split and FP64;
+  * cpu_baseline: the oracle on a bounded sample of the batch.
 
-Headline: useful determinant evaluations per second, sum over wavelengths of
-(pick index + 1), the work Algorithm 1 needs whatever the implementation.
+Headline unit: useful determinant evaluations per second, the sum over
+wavelengths of (pick index + 1), the work Algorithm 1 needs whatever the
+implementation.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
-                       [--workload fine_scale|two_layer|batch] [--no-cpu-baseline]
+                       [--workload batch|fine_scale|two_layer|serving|uniform|chains|classify]
+                       [--no-cpu-baseline] [--no-legs]
 """
 from __future__ import annotations
 
@@ -181,21 +193,13 @@ def time_path(job, ctx, prec, steps, warmup):
 
 # ------------------------------------------------------------------ serving --
 def serving_trace(rate: float, warm_s: float, dur_s: float, seed: int = 55):
-    """Arrival times and request models: each arrival picks one of 64 chains
-    uniformly and advances it one random-walk step."""
+    """Arrival times and request arrays of the serving workload
+    (workloads.serving_trace): each arrival picks one of 64 chains uniformly
+    and advances it one random-walk step."""
     import workloads as WL
-    bases = WL.chain_bases(64, 5)
-    times = WL.poisson_arrivals(rate, warm_s + dur_s, seed)
-    rng = np.random.Generator(np.random.PCG64(seed + 1))
-    pick = rng.integers(0, len(bases), size=len(times))
-    state = [b.model for b in bases]
-    reqs = []
-    for i in range(len(times)):
-        ch = int(pick[i])
-        state[ch] = WL.chain_step(rng, state[ch])
-        m = state[ch]
-        reqs.append((np.ascontiguousarray(m.h), np.ascontiguousarray(m.alpha), np.ascontiguousarray(m.beta),
-                     np.ascontiguousarray(m.rho), bases[ch].lambdas, m.n_layers))
+    times, models = WL.serving_trace(rate, warm_s + dur_s, seed)
+    reqs = [(np.ascontiguousarray(m.h), np.ascontiguousarray(m.alpha), np.ascontiguousarray(m.beta),
+             np.ascontiguousarray(m.rho), lam, m.n_layers) for m, lam in models]
     return times, reqs
 
 
@@ -544,26 +548,31 @@ def cpu_baseline(wl, target_s: float, workers: int):
 
 
 # ---------------------------------------------------------------------- main --
-def inertia_leg(wl, r64, r_i, wall64, wall_i, sweep_i, st_i, n_lay, useful, n_curves):
+def inertia_leg(wl, r64, r_i, wall64, wall_i, sweep_i, st_i, n_lay, n_curves):
     """The FP64 inertia-count search on the same inputs: its outputs against
-    the FP64 walk's (bitwise), its rate, and its kernel's own roofline from its
-    work counters: the inertia counts, plus the determinant signs of the
-    refinement and of the changes at or above the half-space's S velocity
-    (F(N) each, N the mean layer count of the wavelengths)."""
+    the FP64 walk's (bitwise), its rates in wavelengths and curves per second
+    and the work it performed (inertia counts, and the determinant signs it
+    evaluated), and its kernel's own roofline from its work counters: the
+    inertia counts, plus the determinant signs of the sampling, refinement and
+    of any walk at or above the half-space's S velocity (F(N) each, N the mean
+    layer count of the wavelengths)."""
     same = all(np.array_equal(x, y, equal_nan=True) for x, y in zip(r64, r_i))
     nbar = float(np.mean(n_lay)) if len(n_lay) else 0.0
+    det_evals = st_i["sweep_evals"] + st_i["check_evals"] + st_i["refine_evals"]
     flops = (inertia_flops(st_i["inertia_evals"], st_i["inertia_entries"], st_i["inertia_pivots"])
-             + (st_i["sweep_evals"] + st_i["check_evals"] + st_i["refine_evals"]) * flops_per_eval(nbar))
+             + det_evals * flops_per_eval(nbar))
     achieved = flops / (sweep_i * 1e-3) / 1e12
     return {
-        "value": useful / wall_i, "unit": "det evals/s (useful evaluations of the walk it replaces)",
+        "value": wl.n_lambda_total / wall_i, "unit": "wavelengths/s",
         "ms_per_step": wall_i * 1e3, "dtype": "f64", "speedup_vs_fp64_walk": wall64 / wall_i,
-        "curves_per_s": n_curves / wall_i, "wavelengths_per_s": wl.n_lambda_total / wall_i,
+        "curves_per_s": n_curves / wall_i,
         "outputs_bitwise_equal_to_fp64_walk": bool(same),
         "idx_mismatch_vs_fp64": int(np.sum(r64[1] != r_i[1])),
-        "inertia_evals": st_i["inertia_evals"], "inertia_entries": st_i["inertia_entries"],
-        "inertia_pivots": st_i["inertia_pivots"], "walked_evals": st_i["sweep_evals"],
-        "check_evals": st_i["check_evals"], "refine_evals": st_i["refine_evals"],
+        "performed": {"inertia_counts": st_i["inertia_evals"], "element_matrices": st_i["inertia_entries"],
+                      "pivots": st_i["inertia_pivots"], "det_signs": det_evals,
+                      "walked": st_i["sweep_evals"], "check": st_i["check_evals"],
+                      "refine": st_i["refine_evals"]},
+        "performed_counts_and_signs_per_s": (st_i["inertia_evals"] + det_evals) / wall_i,
         "kernel_ms": sweep_i,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS,
@@ -573,15 +582,167 @@ def inertia_leg(wl, r64, r_i, wall64, wall_i, sweep_i, st_i, n_lay, useful, n_cu
     }
 
 
+def measure_curves(M, torch, wl, steps: int, warmup: int, inertia: bool = True) -> dict:
+    """One workload through masw_dispersion_curve / _batch with inputs resident
+    in HBM: the plain FP64 walk (the headline rate), the split path and the
+    FP64 inertia-count search on the same inputs, each timed over `steps`
+    back-to-back jobs after `warmup`, and the FP64 sweep kernel's roofline
+    from the library's HIP events."""
+    dev = torch.device("cuda:0")
+    log(f"workload {wl.name}: {len(wl.models)} model(s), {wl.n_lambda_total} wavelengths, {wl.c_test.shape[0]} c")
+    job = DeviceJob(wl, torch, dev)
+    ctx_obj = M.Context(0, 4 << 30)
+    ctx = ctx_obj.ctx
+    # first call (includes module load and first-touch of the arena) vs steady state
+    t0 = time.perf_counter()
+    job.run(ctx, M.MASW_PREC_FP64)
+    torch.cuda.synchronize()
+    first_call_ms = (time.perf_counter() - t0) * 1e3
+
+    log(f"{wl.name}: timing the FP64 path")
+    wall64, sweep64, total64, st64 = time_path(job, ctx, M.MASW_PREC_FP64, steps, warmup)
+    r64 = job.results(M.MASW_PREC_FP64)
+    log(f"{wl.name}: timing the split path")
+    wall32, sweep32, total32, st32 = time_path(job, ctx, M.MASW_PREC_SPLIT, steps, warmup)
+    r32 = job.results(M.MASW_PREC_SPLIT)
+    if inertia:
+        log(f"{wl.name}: timing the inertia-count search")
+        wall_i, sweep_i, total_i, st_i = time_path(job, ctx, "inertia", steps, warmup)
+        r_i = job.results("inertia")
+    ctx_obj.close()
+
+    idx64, idx32 = r64[1], r32[1]
+    useful = int(np.where(idx64 >= 0, idx64 + 1, wl.c_test.shape[0]).sum())
+    assert useful == st64["useful_evals"], (useful, st64["useful_evals"])
+    both = (idx64 == idx32) & (idx64 >= 0)
+    root_rel = np.abs(r32[3][both] - r64[3][both]) / r64[3][both]
+
+    # algorithmic flops of one FP64 launch: the evaluations the method needs
+    # (every grid point up to each pick, plus the refinement) x F(N); rounds
+    # evaluated past a pick, speculatively or to fill a round, are not counted
+    n_lay = np.asarray(job.n_layers)[job.lam_model]
+    nbar = float(np.average(n_lay, weights=np.where(idx64 >= 0, idx64 + 1, wl.c_test.shape[0])))
+    performed64 = st64["sweep_evals"] + st64["check_evals"] + st64["refine_evals"]
+    algorithmic64 = st64["useful_evals"] + st64["check_evals"] + st64["refine_evals"]
+    flops64 = algorithmic64 * flops_per_eval(nbar)
+    achieved = flops64 / (sweep64 * 1e-3) / 1e12
+    algorithmic32 = st32["useful_evals"] + st32["check_evals"] + st32["refine_evals"]
+    achieved32 = algorithmic32 * flops_per_eval(nbar) / (sweep32 * 1e-3) / 1e12
+    n_curves = len(wl.models)
+    kname = f"sweep_kernel<FP64,G={st64['waves_per_item']}>"
+    traffic = MEASURED_TRAFFIC.get((kernel_source_hash(), wl.name, kname))
+    res = {
+        "value": useful / wall64, "unit": "det evals/s", "ms_per_step": wall64 * 1e3, "dtype": "f64",
+        "config": {"workload": wl.name, "models": n_curves, "wavelengths": wl.n_lambda_total,
+                   "n_c": int(wl.c_test.shape[0]), "layers_mean": nbar, "path": "plain FP64"},
+        "curves_per_s": n_curves / wall64,
+        "wavelengths_per_s": wl.n_lambda_total / wall64,
+        "useful_evals": useful,
+        "performed_evals": performed64,
+        "algorithmic_evals": algorithmic64,
+        "first_call_ms": first_call_ms,
+        "device_ms_per_step": total64,
+        "split": {
+            "value": useful / wall32, "unit": "det evals/s", "ms_per_step": wall32 * 1e3,
+            "dtype": "f32 sweep + f64 re-check/refine", "speedup_vs_fp64": wall64 / wall32,
+            "curves_per_s": n_curves / wall32, "wavelengths_per_s": wl.n_lambda_total / wall32,
+            "sweep_evals": st32["sweep_evals"], "check_evals": st32["check_evals"],
+            "refine_evals": st32["refine_evals"], "sweep_kernel_ms": sweep32,
+            "kernel": f"sweep_kernel<split,G={st32['waves_per_item']}>",
+            "achieved_tflops_fp64_counted": achieved32,
+            "idx_mismatch_vs_fp64": int(np.sum((idx64 != idx32))),
+            "root_rel_err_vs_fp64_max": float(root_rel.max()) if root_rel.size else None,
+            "root_rel_err_vs_fp64_mean": float(root_rel.mean()) if root_rel.size else None,
+        },
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
+                     "kernel": kname,
+                     "kernel_ms": sweep64, "flops_per_launch": flops64},
+    }
+    if inertia:
+        res["inertia"] = inertia_leg(wl, r64, r_i, wall64, wall_i, sweep_i, st_i, n_lay, n_curves)
+    return res
+
+
+def serving_leg(M, torch, seconds: float) -> dict:
+    """A short replay of the serving trace (2000 req/s Poisson arrivals from
+    64 random-walk chains, 1 s warm-up): p50/p99 latency and curves/s of the
+    split path and of the plain-FP64 server on the identical trace."""
+    import workloads as WL
+    c = WL.serving_grid()
+    warm = 1.0
+    times, reqs = serving_trace(2000.0, warm, seconds)
+    log(f"serving leg: {len(times)} requests over {warm + seconds:.0f} s, split then FP64")
+    ctx_obj = M.Context(0, 4 << 30)
+    split, idx_s = run_serving(M, ctx_obj.ctx, M.MASW_PREC_SPLIT, times, reqs, c, warm)
+    fp64, idx_d = run_serving(M, ctx_obj.ctx, M.MASW_PREC_FP64, times, reqs, c, warm)
+    ctx_obj.close()
+    keep = ("requests", "p50_ms", "p99_ms", "mean_ms", "max_ms", "curves_per_s", "det_evals_per_s", "busy_frac")
+    return {"workload": "serving_64chains_2000rps", "seconds": seconds, "n_c": int(c.shape[0]),
+            "split": {k: split[k] for k in keep}, "fp64": {k: fp64[k] for k in keep},
+            "idx_mismatch_split_vs_fp64": sum(int(np.sum(x != y)) for x, y in zip(idx_s, idx_d))}
+
+
+def _oracle_curve_points(args):
+    import oracle as O
+    lam, c, model = args
+    p = O.dispersion_point(lam, c, model, refine=True)
+    return p.idx, p.c_ref, p.evals
+
+
+def two_layer_vs_oracle(M, torch, workers: int) -> dict:
+    """The split path on the two-layer case (30 wavelengths, 801 velocities)
+    against the oracle, per wavelength: grid-index mismatches and the root
+    error |c_ref - c_ref_oracle| / c_ref_oracle (max and mean over the
+    curve), with the plain FP64 path beside it.  The oracle runs on the host
+    here, as part of the CPU leg."""
+    import multiprocessing as mp
+    import workloads as WL
+    wl = WL.two_layer_case()
+    m, lam, c = wl.models[0], wl.lambdas[0], wl.c_test
+    ctx_obj = M.Context(0, 64 << 20)
+    got = {p: ctx_obj.curve(c, lam, m, p) for p in (M.MASW_PREC_SPLIT, M.MASW_PREC_FP64)}
+    ctx_obj.close()
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(workers) as pool:
+        want = pool.map(_oracle_curve_points, [(float(l), c, m) for l in lam], chunksize=1)
+    wall = time.perf_counter() - t0
+    w_idx = np.array([w[0] for w in want])
+    w_ref = np.array([w[1] for w in want])
+    out = {"workload": wl.name, "wavelengths": int(len(lam)), "oracle_s": wall}
+    for p, name in ((M.MASW_PREC_SPLIT, "split"), (M.MASW_PREC_FP64, "fp64")):
+        ct, idx, st, cr = got[p]
+        ok = (idx == w_idx) & (w_idx >= 0)
+        rel = np.abs(cr[ok] - w_ref[ok]) / w_ref[ok]
+        out[name] = {"idx_mismatch_vs_oracle": int(np.sum(idx != w_idx)),
+                     "root_rel_err_max": float(rel.max()) if rel.size else None,
+                     "root_rel_err_mean": float(rel.mean()) if rel.size else None}
+    return out
+
+
+def host_workers() -> int:
+    """Host processes for the oracle: the CPUs this process may run on,
+    at most 16 (one GPU's share of the GPU machine's host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default: per workload)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed warm-up steps (default: per workload)")
-    ap.add_argument("--workload", default="fine_scale",
+    ap.add_argument("--workload", default="batch",
                     choices=["fine_scale", "two_layer", "batch", "serving", "uniform", "chains", "classify"])
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="measured seconds of the serving trace")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="batch workload: only the headline, without the fine-scale, serving and two-layer legs")
+    ap.add_argument("--serve-leg-seconds", type=float, default=2.0,
+                    help="measured seconds of the serving leg of the default run")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target CPU work of the oracle sample")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (the reference "
@@ -624,91 +785,29 @@ def main():
     if a.workload == "classify":
         classify_bench(M, torch, a)
         return
-    dev = torch.device("cuda:0")
+    import workloads as WL
     wl = make_workload(a.workload)
-    log(f"workload {wl.name}: {len(wl.models)} model(s), {wl.n_lambda_total} wavelengths, {wl.c_test.shape[0]} c")
-    job = DeviceJob(wl, torch, dev)
-    ctx_obj = M.Context(0, 4 << 30)
-    ctx = ctx_obj.ctx
-
-    # first call (includes module load and first-touch of the arena) vs steady state
-    t0 = time.perf_counter()
-    job.run(ctx, M.MASW_PREC_FP64)
-    torch.cuda.synchronize()
-    first_call_ms = (time.perf_counter() - t0) * 1e3
-
-    log("timing FP64 path")
-    wall64, sweep64, total64, st64 = time_path(job, ctx, M.MASW_PREC_FP64, a.steps, a.warmup)
-    r64 = job.results(M.MASW_PREC_FP64)
-    log("timing split path")
-    wall32, sweep32, total32, st32 = time_path(job, ctx, M.MASW_PREC_SPLIT, a.steps, a.warmup)
-    r32 = job.results(M.MASW_PREC_SPLIT)
-    log("timing the inertia-count search")
-    wall_i, sweep_i, total_i, st_i = time_path(job, ctx, "inertia", a.steps, a.warmup)
-    r_i = job.results("inertia")
-
-    idx64, idx32 = r64[1], r32[1]
-    useful = int(np.where(idx64 >= 0, idx64 + 1, wl.c_test.shape[0]).sum())
-    assert useful == st64["useful_evals"], (useful, st64["useful_evals"])
-    both = (idx64 == idx32) & (idx64 >= 0)
-    root_rel = np.abs(r32[3][both] - r64[3][both]) / r64[3][both]
-
-    # algorithmic flops of one FP64 launch: the evaluations the method needs
-    # (every grid point up to each pick, plus the refinement) x F(N); rounds
-    # evaluated past a pick, speculatively or to fill a round, are not counted
-    n_lay = np.asarray(job.n_layers)[job.lam_model]
-    nbar = float(np.average(n_lay, weights=np.where(idx64 >= 0, idx64 + 1, wl.c_test.shape[0])))
-    performed64 = st64["sweep_evals"] + st64["check_evals"] + st64["refine_evals"]
-    algorithmic64 = st64["useful_evals"] + st64["check_evals"] + st64["refine_evals"]
-    flops64 = algorithmic64 * flops_per_eval(nbar)
-    achieved = flops64 / (sweep64 * 1e-3) / 1e12
-    n_curves = len(wl.models)
-    kname = f"sweep_kernel<FP64,G={st64['waves_per_item']}>"
-    traffic = MEASURED_TRAFFIC.get((kernel_source_hash(), wl.name, kname))
-
-    res = {
-        "metric": METRIC,
-        "value": useful / wall64,
-        "unit": "det evals/s",
-        "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
-        "ms_per_step": wall64 * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": wl.name, "models": n_curves, "wavelengths": wl.n_lambda_total,
-                   "n_c": int(wl.c_test.shape[0]), "layers_mean": nbar, "path": "plain FP64"},
-        "curves_per_s": n_curves / wall64,
-        "wavelengths_per_s": wl.n_lambda_total / wall64,
-        "useful_evals": useful,
-        "performed_evals": performed64,
-        "algorithmic_evals": algorithmic64,
-        "first_call_ms": first_call_ms,
-        "device_ms_per_step": total64,
-        "split": {
-            "value": useful / wall32, "unit": "det evals/s", "ms_per_step": wall32 * 1e3,
-            "dtype": "f32 sweep + f64 re-check/refine", "speedup_vs_fp64": wall64 / wall32,
-            "curves_per_s": n_curves / wall32,
-            "sweep_evals": st32["sweep_evals"], "check_evals": st32["check_evals"],
-            "refine_evals": st32["refine_evals"], "sweep_kernel_ms": sweep32,
-            "idx_mismatch_vs_fp64": int(np.sum((idx64 != idx32))),
-            "root_rel_err_vs_fp64_max": float(root_rel.max()) if root_rel.size else None,
-            "root_rel_err_vs_fp64_mean": float(root_rel.mean()) if root_rel.size else None,
-        },
-        "inertia": inertia_leg(wl, r64, r_i, wall64, wall_i, sweep_i, st_i, n_lay, useful, n_curves),
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
-                     "kernel": kname,
-                     "kernel_ms": sweep64, "flops_per_launch": flops64},
-    }
+    res = {"metric": METRIC}
+    head = measure_curves(M, torch, wl, a.steps, a.warmup)
+    res.update({"value": head.pop("value"), "unit": head.pop("unit"), "n_gpus": 1, "steps": a.steps,
+                "warmup": a.warmup, "ms_per_step": head.pop("ms_per_step"), "higher_is_better": True,
+                "scaling": "weak", "vs_baseline": None, "dtype": head.pop("dtype"), "data": "synthetic",
+                "config": head.pop("config")})
+    res.update(head)
+    if a.workload == "batch" and not a.no_legs:
+        # the other configurations, each a leg of its own beside the headline
+        fs_steps, fs_warm = DEFAULT_STEPS["fine_scale"]
+        fs = measure_curves(M, torch, WL.fine_scale_case(), fs_steps, fs_warm)
+        fs["steps"], fs["warmup"] = fs_steps, fs_warm
+        res["fine_scale"] = fs
+        res["serving"] = serving_leg(M, torch, a.serve_leg_seconds)
     if not a.no_cpu_baseline:
-        log("timing the CPU oracle on a sample")
-        workers = min(os.cpu_count() or 1, 16)
+        workers = host_workers()
+        log(f"timing the CPU oracle on a sample ({workers} processes)")
         res["cpu_baseline"] = cpu_baseline(wl, a.cpu_seconds, workers)
-    ctx_obj.close()
+        if a.workload == "batch" and not a.no_legs:
+            log("the two-layer case against the oracle")
+            res["two_layer_vs_oracle"] = two_layer_vs_oracle(M, torch, workers)
     print(json.dumps(res), flush=True)
 
 

@@ -80,10 +80,16 @@ enum {
 
 /* Arithmetic of the search.
  * MASW_PREC_FP64:  every determinant sign in FP64.
- * MASW_PREC_SPLIT: the c-grid sweep in FP32; the FP32 bracket is re-checked
- *                  in FP64 over a window of grid points around it, and the
- *                  refinement is FP64.  idx is the first FP64 sign change in
- *                  the re-checked window.                                     */
+ * MASW_PREC_SPLIT: the c-grid sweep in FP32 below the half-space's S
+ *                  velocity; each FP32 candidate is re-checked in FP64 over a
+ *                  window of grid points around it, the stretch FP32 passed
+ *                  over is certified by FP64 inertia counts (equal
+ *                  Wittrick-Williams counts at its ends prove no zero and no
+ *                  pole of det K in it, otherwise it is walked in FP64), the
+ *                  grid at or above the half-space's S velocity is walked in
+ *                  FP64, and the refinement is FP64.  So idx is Algorithm 1's
+ *                  FP64 pick, as with MASW_PREC_FP64, outside the FP64 noise
+ *                  band.                                                      */
 enum { MASW_PREC_FP64 = 0, MASW_PREC_SPLIT = 1 };
 /* A plain integer, not the enum type, so that any value a caller passes is
  * well defined on both sides of the ABI; others are rejected (MASW_EINVAL). */
@@ -246,6 +252,21 @@ int masw_dispersion_batch(masw_ctx *ctx, const double *c_test, int32_t n_c,
                           uint32_t flags, void *stream,
                           const masw_outputs *out);
 
+/* One step of inversion chains (Algorithm 2 over a batch): the batch's
+ * curves, as masw_dispersion_batch, and the misfit of every model,
+ * misfit[m] = mean over its wavelengths i of |C_t,i - C_e,i| / C_e,i, as
+ * masw_misfit computes it (bit for bit), in the same persistent launch: the
+ * workgroup that finishes a model's last wavelength reduces the model's
+ * misfit.  C_e: [total wavelengths], laid out as batch->lambda, finite and
+ * > 0 (checked on the host for host pointers); misfit: [n_models] (NaN for a
+ * model without wavelengths, or with a wavelength without a pick).  With
+ * MASW_SEARCH_INERTIA the misfit is a second launch after the search.  Same
+ * rules as masw_dispersion_batch otherwise. */
+int masw_dispersion_batch_misfit(masw_ctx *ctx, const double *c_test, int32_t n_c,
+                                 const masw_batch *batch, masw_precision prec,
+                                 uint32_t flags, void *stream, const masw_outputs *out,
+                                 const double *C_e, double *misfit);
+
 /* Full sign map of one model: for every wavelength w and grid point i, with
  * no early exit, sigma[w * n_c + i] = sign(Re det K) in {-1, 0, +1} (2 if the
  * determinant is NaN) and, if log_abs_det is not NULL,
@@ -321,13 +342,16 @@ int masw_server_start(masw_ctx *ctx, const masw_server_opts *opts);
 int masw_server_stop(masw_ctx *ctx);
 
 /* Queue one request.  Arguments as masw_dispersion_curve with host pointers;
- * they are checked and copied before the call returns.  MASW_EINVAL on a bad
- * argument or one above the server's limits, MASW_ENOMEM if the request could
- * never fit the pool, MASW_EBUSY if the loop is not running.  *ticket
- * identifies the request. */
+ * they are checked and copied before the call returns.  flags: 0, or any of
+ * MASW_CHECK_NOISE (each pick's bracket is tested for the FP64 noise band
+ * when the pick is made, and MASW_FLAG_NOISE set in its status, as for the
+ * synchronous calls) and MASW_NO_REFINE (c_ref = NaN); other bits are
+ * MASW_EINVAL.  MASW_EINVAL on a bad argument or one above the server's
+ * limits, MASW_ENOMEM if the request could never fit the pool, MASW_EBUSY if
+ * the loop is not running.  *ticket identifies the request. */
 int masw_submit(masw_ctx *ctx, const double *c_test, int32_t n_c, const double *lambda,
                 int32_t n_lambda, const masw_model *model, masw_precision prec,
-                uint64_t *ticket);
+                uint32_t flags, uint64_t *ticket);
 
 /* If the request is finished, copy its results (arrays of its n_lambda;
  * c_ref and info may be NULL) and forget the ticket: MASW_OK.  MASW_EBUSY if

@@ -151,6 +151,8 @@ def library() -> ctypes.CDLL:
             "masw_destroy": (None, [vp]),
             "masw_dispersion_curve": (ctypes.c_int, [vp, vp, i32, vp, i32, ctypes.POINTER(masw_model),
                                                      ctypes.c_int, u32, vp, vp, vp, vp, vp]),
+            "masw_dispersion_batch_misfit": (ctypes.c_int, [vp, vp, i32, ctypes.POINTER(masw_batch), ctypes.c_int,
+                                                            u32, vp, ctypes.POINTER(masw_outputs), vp, vp]),
             "masw_dispersion_batch": (ctypes.c_int, [vp, vp, i32, ctypes.POINTER(masw_batch),
                                                      ctypes.c_int, u32, vp, ctypes.POINTER(masw_outputs)]),
             "masw_sign_map": (ctypes.c_int, [vp, vp, i32, vp, i32, ctypes.POINTER(masw_model),
@@ -164,7 +166,7 @@ def library() -> ctypes.CDLL:
                                                    vp, vp]),
             "masw_server_start": (ctypes.c_int, [vp, ctypes.POINTER(masw_server_opts)]),
             "masw_server_stop": (ctypes.c_int, [vp]),
-            "masw_submit": (ctypes.c_int, [vp, vp, i32, vp, i32, ctypes.POINTER(masw_model), ctypes.c_int,
+            "masw_submit": (ctypes.c_int, [vp, vp, i32, vp, i32, ctypes.POINTER(masw_model), ctypes.c_int, u32,
                                            ctypes.POINTER(ctypes.c_uint64)]),
             "masw_poll": (ctypes.c_int, [vp, ctypes.c_uint64, vp, vp, vp, vp, ctypes.POINTER(masw_request_info)]),
             "masw_wait": (ctypes.c_int, [vp, ctypes.c_uint64, ctypes.c_int64, vp, vp, vp, vp,
@@ -271,9 +273,7 @@ def masw_dispersion_curve(ctx, c_test, lam, h, alpha, beta, rho, prec: int, flag
         "masw_dispersion_curve")
 
 
-def masw_dispersion_batch(ctx, c_test, layer_off, h, alpha, beta, rho, lambda_off, lam,
-                          prec: int, flags: int, stream, C_t, idx, status, c_ref=None) -> int:
-    fl = flags | _device_flag(c_test, layer_off, h, alpha, beta, rho, lambda_off, lam, C_t, idx, status, c_ref)
+def _batch_structs(layer_off, h, alpha, beta, rho, lambda_off, lam, C_t, idx, status, c_ref):
     b = masw_batch()
     b.n_models = int(layer_off.shape[0]) - 1
     b.layer_off = ctypes.cast(_ptr(layer_off, np.int32), _ip)
@@ -288,9 +288,28 @@ def masw_dispersion_batch(ctx, c_test, layer_off, h, alpha, beta, rho, lambda_of
     o.idx = ctypes.cast(_ptr(idx, np.int32), _ip)
     o.status = ctypes.cast(_ptr(status, np.int32), _ip)
     o.c_ref = ctypes.cast(_ptr(c_ref, np.float64), _dp)
+    return b, o
+
+
+def masw_dispersion_batch(ctx, c_test, layer_off, h, alpha, beta, rho, lambda_off, lam,
+                          prec: int, flags: int, stream, C_t, idx, status, c_ref=None) -> int:
+    fl = flags | _device_flag(c_test, layer_off, h, alpha, beta, rho, lambda_off, lam, C_t, idx, status, c_ref)
+    b, o = _batch_structs(layer_off, h, alpha, beta, rho, lambda_off, lam, C_t, idx, status, c_ref)
     return _check(library().masw_dispersion_batch(
         ctx, _ptr(c_test, np.float64), int(c_test.shape[0]), ctypes.byref(b), prec, fl,
         _stream(stream, fl & MASW_DEVICE_PTRS), ctypes.byref(o)), "masw_dispersion_batch")
+
+
+def masw_dispersion_batch_misfit(ctx, c_test, layer_off, h, alpha, beta, rho, lambda_off, lam,
+                                 prec: int, flags: int, stream, C_t, idx, status, c_ref, C_e, misfit) -> int:
+    """Marshals to the C function of the same name (see include/masw.h)."""
+    fl = flags | _device_flag(c_test, layer_off, h, alpha, beta, rho, lambda_off, lam, C_t, idx, status, c_ref,
+                              C_e, misfit)
+    b, o = _batch_structs(layer_off, h, alpha, beta, rho, lambda_off, lam, C_t, idx, status, c_ref)
+    return _check(library().masw_dispersion_batch_misfit(
+        ctx, _ptr(c_test, np.float64), int(c_test.shape[0]), ctypes.byref(b), prec, fl,
+        _stream(stream, fl & MASW_DEVICE_PTRS), ctypes.byref(o), _ptr(C_e, np.float64), _ptr(misfit, np.float64)),
+        "masw_dispersion_batch_misfit")
 
 
 def masw_sign_map(ctx, c_test, lam, h, alpha, beta, rho, prec: int, flags: int, stream,
@@ -367,12 +386,12 @@ def masw_server_stop(ctx) -> int:
     return _check(library().masw_server_stop(ctx), "masw_server_stop")
 
 
-def masw_submit(ctx, c_test, lam, h, alpha, beta, rho, prec: int) -> int:
+def masw_submit(ctx, c_test, lam, h, alpha, beta, rho, prec: int, flags: int = 0) -> int:
     """Host numpy arrays only (copied before returning); returns the ticket."""
     m = _model_struct(h, alpha, beta, rho)
     t = ctypes.c_uint64()
     _check(library().masw_submit(ctx, _ptr(c_test, np.float64), int(c_test.shape[0]), _ptr(lam, np.float64),
-                                 int(lam.shape[0]), ctypes.byref(m), prec, ctypes.byref(t)), "masw_submit")
+                                 int(lam.shape[0]), ctypes.byref(m), prec, flags, ctypes.byref(t)), "masw_submit")
     return t.value
 
 

@@ -55,6 +55,10 @@ struct ClassifyArgs {
   uint64_t* counters = nullptr;  // [3]: evaluations, layers crossed, steps (cleared by the launch)
 };
 hipError_t launch_classify(const ClassifyArgs& a, hipStream_t s);
+// FP64 noise-band flag of the picks of finished served requests
+// (masw_noise.hip), after their tick.
+hipError_t launch_serve_noise(const ServeNoiseList& list, const int32_t* out_idx, int32_t* out_status,
+                              double threshold, hipStream_t s);
 // FP64 noise-band flag of every pick (masw_noise.hip), after the sweep.
 hipError_t launch_noise_check(const ModelDesc* models, const LayerRec64* layers64, const double* c64,
                               const double* lam_k, const int32_t* lam_model, const int32_t* idx,

@@ -90,6 +90,34 @@ __device__ __forceinline__ int neg_eigs(double a, double d) { return d < 0.0 ? 1
 
 __device__ __forceinline__ bool usable(double d) { return d != 0.0 && __builtin_fabs(d) < __builtin_inf(); }
 
+// P_j(c) of one layer (its modes with both faces fixed below c), added to
+// *P: zero by the energy bound when k h sqrt(c^2/beta^2 - 1) <= pi, else the
+// negative eigenvalues of the m - 1 interior interfaces of m equal
+// sublayers.  Clears *ok where a pivot is zero or not finite, or where the
+// layer would need more than kMaxSub sublayers.  Returns the sublayer pivots
+// eliminated (0 when the bound settles it).
+__device__ __forceinline__ unsigned layer_poles(double c2, double kh, const LayerRec<double>& rec, int* P,
+                                                bool* ok) {
+  const double x = c2 * rec.ib2 - 1.0;
+  if (!(x > 0.0)) return 0u;
+  const double q = kh * __builtin_sqrt(x) * kInvPi;
+  if (!(q >= 1.0)) return 0u;
+  if (!(q < kMaxSub)) {
+    *ok = false;
+    return 0u;
+  }
+  const int m = int(q) + 1;
+  const LayerK<double> Ks = layer_entries<double>(c2, kh / double(m), rec.ia2, rec.ib2, rec.rh, rec.mh);
+  Block2<double> R{Ks.k11, -Ks.k12, Ks.k22};  // the first sublayer's share of interface 1
+  for (int i = 1; i < m; ++i) {
+    const double a2 = R.s11 + Ks.k11;
+    const double d2 = schur_layer<double>(R, Ks);
+    *ok = *ok && usable(d2);
+    *P += neg_eigs(a2, d2);
+  }
+  return unsigned(m);
+}
+
 // E(c) = s(c) + 2 P(c), or kEvent (c at or above the half-space's S velocity,
 // a zero or non-finite pivot, or a layer that would need more than kMaxSub
 // sublayers).  The work is added to t if `tally`.
@@ -109,26 +137,10 @@ __device__ inline int count_E(double c, double k, const LayerRec64* __restrict__
     const double d = schur_layer<double>(S, K);
     ok = ok && usable(d);
     s += neg_eigs(a, d);
-    const double x = c2 * rec.ib2 - 1.0;
-    if (x > 0.0) {
-      const double q = kh * __builtin_sqrt(x) * kInvPi;
-      if (q >= 1.0) {
-        if (!(q < kMaxSub)) {
-          ok = false;
-        } else {
-          const int m = int(q) + 1;
-          const LayerK<double> Ks = layer_entries<double>(c2, kh / double(m), rec.ia2, rec.ib2, rec.rh, rec.mh);
-          Block2<double> R{Ks.k11, -Ks.k12, Ks.k22};  // the first sublayer's share of interface 1
-          for (int i = 1; i < m; ++i) {
-            const double a2 = R.s11 + Ks.k11;
-            const double d2 = schur_layer<double>(R, Ks);
-            ok = ok && usable(d2);
-            P += neg_eigs(a2, d2);
-          }
-          ++entries;
-          pivots += (unsigned long long)(m - 1);
-        }
-      }
+    const unsigned m = layer_poles(c2, kh, rec, &P, &ok);
+    if (m) {
+      ++entries;
+      pivots += (unsigned long long)(m - 1);
     }
   }
   double re, im, ar;
@@ -141,6 +153,70 @@ __device__ inline int count_E(double c, double k, const LayerRec64* __restrict__
     t.pivots += pivots;
   }
   return ok ? s + 2 * P : kEvent;
+}
+
+// The split path's FP64 check of one grid point: det_sign_parity<double>'s
+// sign code and pole parity from the same elimination, and in *E the
+// inertia of its pivots, s(c), or kEvent where a pivot is zero or not finite
+// or c is at or above the half-space's S velocity.  E(c) = s(c) when
+// *poles_bounded (every layer's P_j is zero by the energy bound); otherwise
+// count_E gives E(c).  Tallying s costs a few operations per layer; the
+// sublayers of P_j are left to count_E, which needs them rarely.
+__device__ __forceinline__ int det_sign_inertia(double c, double k, const LayerRec64* __restrict__ L, int N,
+                                                int* odd, int* E, bool* poles_bounded) {
+  const double c2 = c * c;
+  Block2<double> S{0.0, 0.0, 0.0};
+  bool neg = false, par = false, ok = true, bounded = true;
+  int s = 0;
+  for (int j = 0; j < N; ++j) {
+    const LayerRec<double> rec = load_rec<double>(L, j);
+    const double kh = k * rec.h;
+    const LayerK<double> K = layer_entries<double>(c2, kh, rec.ia2, rec.ib2, rec.rh, rec.mh);
+    par ^= (K.gD < 0.0);
+    const double a = S.s11 + K.k11;
+    const double d = schur_layer<double>(S, K);
+    neg ^= (d < 0.0);
+    ok = ok && usable(d);
+    s += neg_eigs(a, d);
+    // P_j = 0 when k h sqrt(c^2/beta^2 - 1) < pi (layer_poles' bound), tested
+    // with a margin below pi^2 so that layer_poles' own rounding agrees
+    const double x = c2 * rec.ib2 - 1.0;
+    bounded = bounded && !(x > 0.0 && kh * kh * x >= 9.86);
+  }
+  const LayerRec<double> hs = load_rec<double>(L, N);
+  double re, im, ar;
+  halfspace_det<double>(S, c2, hs.ia2, hs.ib2, hs.mh, &re, &im, &ar);
+  ok = ok && usable(re) && (c2 * hs.ib2 < 1.0);
+  s += neg_eigs(ar, re);
+  *odd = par ? 1 : 0;
+  *E = ok ? s : kEvent;
+  *poles_bounded = bounded;
+  return sign_code(neg, re);
+}
+
+// P(c) = sum_j P_j(c) of all layers, by layer_poles, in a loop of its own
+// (the split path's rare full counts: the pivots' inertia comes from
+// det_sign_inertia, and keeping the sublayers out of that elimination keeps
+// its registers down).  Clears *ok as layer_poles does.
+__device__ __forceinline__ int poles_below(double c, double k, const LayerRec64* __restrict__ L, int N, bool* ok) {
+  const double c2 = c * c;
+  int P = 0;
+  for (int j = 0; j < N; ++j) {
+    const LayerRec<double> rec = load_rec<double>(L, j);
+    layer_poles(c2, k * rec.h, rec, &P, ok);
+  }
+  return P;
+}
+
+// E(c) as count_E gives it, from det_sign_inertia and poles_below.
+__device__ __forceinline__ int count_E_split(double c, double k, const LayerRec64* __restrict__ L, int N) {
+  int odd, E;
+  bool bounded;
+  det_sign_inertia(c, k, L, N, &odd, &E, &bounded);
+  if (E == kEvent || bounded) return E;
+  bool ok = true;
+  const int P = poles_below(c, k, L, N, &ok);
+  return ok ? E + 2 * P : kEvent;
 }
 
 // Algorithm 1's walk from grid index `start`, whose predecessor has sign

@@ -49,7 +49,8 @@ struct alignas(32) ModelDesc {
   int32_t lam_base;    // first wavelength (flattened index)
   int32_t n_lam;       // wavelengths
   int32_t valid;       // 1 if the model and its grid passed validation
-  int32_t pad;
+  int32_t n_real;      // grid points c with c^2 / beta_hs^2 < 1 (K real, inertia counts exist): the
+                       // leading part of the grid, where the split path sweeps in FP32
 };
 
 // Counters written by the kernels (one block in the arena, zeroed per call).
@@ -112,6 +113,12 @@ struct SweepArgs {
   // it: 2 for it < prio_hi, 1 for it < prio_mid, else 0 (0 = all off).
   int32_t prio_hi;
   int32_t prio_mid;
+  // Algorithm 2 fused into the launch (misfit null: off): the workgroup that
+  // finishes a model's last wavelength reduces the model's misfit.
+  const double* c_e;          // [n_lam] experimental velocities
+  double* misfit;             // [n_models]
+  int32_t* model_left;        // [n_models] wavelengths not finished (set by the staging)
+  const int32_t* lambda_off;  // [n_models + 1]
 };
 
 // Zero-state of the cooperative arrays (one launch before the sweep).
@@ -149,6 +156,8 @@ struct PrepArgs {
   int32_t n_lam;
   Counters* counters;
   uint32_t* grid_flags;  // [ceil(n_c / kPrepThreads)] 1 where a block of the grid failed its checks
+  int32_t* model_left;   // fused misfit: [n_models] set to each model's wavelength count (else null)
+  double* misfit;        // fused misfit: [n_models], NaN written here for a model with no wavelength
 };
 
 // Where one item's search stands.  The batch kernels keep it in registers;
@@ -180,7 +189,9 @@ struct alignas(64) SlotDesc {
   ItemState* state;         // [W]
   int32_t N, W, n_c, prec;  // prec: MASW_PREC_*
   int32_t out_base;         // first output index (slot * w_max)
-  int32_t pad[3];
+  int32_t n_real;           // as ModelDesc::n_real, computed by the host at submit
+  uint32_t flags;           // the request's MASW_CHECK_NOISE / MASW_NO_REFINE
+  int32_t pad;
 };
 
 // Per-tick descriptor, written by the host into pinned memory and copied to
@@ -207,6 +218,14 @@ struct AdmitList {
   int32_t slot[kMaxAdmit];
   SlotDesc desc[kMaxAdmit];
   const double* src[kMaxAdmit];
+};
+
+// Finished requests with MASW_CHECK_NOISE whose picks the serve-noise
+// kernel tests after a tick (kernel argument, by value).
+constexpr int kNoiseList = 16;
+struct ServeNoiseList {
+  int32_t n;
+  SlotDesc slot[kNoiseList];
 };
 
 struct TickArgs {

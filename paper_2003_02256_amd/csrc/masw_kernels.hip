@@ -110,6 +110,21 @@ __device__ void build_model(const PrepArgs& a, int m, int single_N, int single_W
     ok = __ballot(!lok) == 0ull;
   }
   if (lane == 0) {
+    // Grid points below the half-space's S velocity: the first c with
+    // c^2 / beta_hs^2 >= 1, in the arithmetic of the inertia count's test
+    // (the grid rises; a grid that does not fails its own checks).
+    int n_real = 0;
+    if (ok) {
+      const double be = a.beta[rec0 + N];
+      const double ib2 = 1.0 / (be * be);
+      int lo = 0, hi = a.n_c;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        const double c = a.c_in[mid];
+        if (c * c * ib2 < 1.0) lo = mid + 1; else hi = mid;
+      }
+      n_real = lo;
+    }
     ModelDesc d;
     d.n_layers = ok ? N : 0;
     d.layer_base = rec0;
@@ -118,8 +133,12 @@ __device__ void build_model(const PrepArgs& a, int m, int single_N, int single_W
     d.lam_base = a.lambda_off ? a.lambda_off[m] : 0;
     d.n_lam = a.lambda_off ? (a.lambda_off[m + 1] - a.lambda_off[m]) : single_W;
     d.valid = ok ? 1 : 0;
-    d.pad = 0;
+    d.n_real = n_real;
     a.models[m] = d;
+    if (a.model_left) {
+      a.model_left[m] = d.n_lam;
+      if (d.n_lam == 0) a.misfit[m] = __builtin_nan("");
+    }
   }
   if (!ok) return;
   const double mu_ref = a.rho[rec0 + N] * a.beta[rec0 + N] * a.beta[rec0 + N];
@@ -332,7 +351,7 @@ struct SweepShared {
   int last[G];
   int first[G];
   int pair[2];
-  int check[7];
+  int check[8];
   int coop[6];
 };
 
@@ -343,12 +362,20 @@ struct WorkCount {
 // Everything uniform about one item.
 struct ItemRef {
   int N, n_c;
+  int n_real;  // leading grid points below the half-space's S velocity (the FP32 sweep's extent)
   double k64;
   const double* c64;
   const float* c32;
   const LayerRec64* L64;
   const LayerRec32* L32;
 };
+
+// Extent of a sweep in precision T: the whole grid in FP64; in FP32 the
+// points below the half-space's S velocity, where inertia counts certify it.
+template <typename T>
+__device__ __forceinline__ int sweep_len(const ItemRef& r) {
+  return sizeof(T) == 8 ? r.n_c : r.n_real;
+}
 
 template <int G>
 __device__ __forceinline__ void write_missing(const ItemOut& o, int status) {
@@ -419,7 +446,7 @@ __device__ __forceinline__ int eval_round(const ItemRef& r, int rd, SweepShared<
   constexpr int P = 64 * G;
   const int i = rd * P + int(threadIdx.x);
   int sg = kNoSign;
-  if (i < r.n_c) {
+  if (i < sweep_len<T>(r)) {
     if constexpr (sizeof(T) == 8)
       sg = det_sign<double, false>(r.c64[i], r.k64, r.L64, r.N, nullptr);
     else
@@ -441,7 +468,8 @@ __device__ int coop_sweep(const ItemRef& r, const CoopRef& co, SweepShared<G>& s
                           Counters* cnt, int* sig, int* prev) {
   constexpr int P = 64 * G;
   const int tid = threadIdx.x;
-  const int n_rounds = (r.n_c + P - 1) / P;
+  const int n_sw = sweep_len<T>(r);
+  const int n_rounds = (n_sw + P - 1) / P;
   int claim = 0, resolved = 0, carry = kNoSign, found = -1, fs = 0, fp = 0;
   int stop = 0x7fffffff;
   bool done = false;
@@ -467,7 +495,7 @@ __device__ int coop_sweep(const ItemRef& r, const CoopRef& co, SweepShared<G>& s
       }
       int s0, sl, sa = 0, pa = 0;
       const int f = eval_round<T, G>(r, rd, sh, &s0, &sl, &sa, &pa);
-      wc.sweep += (unsigned long long)min(P, r.n_c - rd * P);
+      wc.sweep += (unsigned long long)min(P, n_sw - rd * P);
       if (tid == 0) {
         if (f >= 0) {
           atomicMin(&co.ci->stop, rd);
@@ -560,16 +588,23 @@ __device__ int coop_sweep(const ItemRef& r, const CoopRef& co, SweepShared<G>& s
 // in `st` and return false; resuming from `st` gives the same result as an
 // uninterrupted run, whatever G the resumed call uses.
 //
-// The split path trusts FP32 signs only where FP64 confirms them: every FP32
-// candidate is re-checked in FP64 on a 64-point window, and the FP64 sign
-// just before the window must equal the sign FP32 saw since the last
-// FP64-confirmed point (likewise at the end of the grid before reporting no
-// change).  If it does not, FP32 missed a change and the item continues as
-// an FP64 sweep from that point.  A change of the parity of negative layer
-// denominators (a pole crossing, next to which FP32 signs are least
-// reliable) is a candidate too.  So the split pick equals the FP64 pick
-// unless FP32 misses an even number of changes between confirmed points with
-// no pole crossing among them.
+// The split path trusts FP32 signs only where FP64 certifies them.  It
+// sweeps in FP32 only below the half-space's S velocity, where K is real
+// symmetric and the inertia count E(c) = s + 2P of the inertia search exists
+// (s: negative eigenvalues of K; P: poles below c).  E is non-decreasing in
+// c and changes at every zero and every pole of det K, so equal counts at
+// two points prove that sign(det K) is constant between them.  Every FP32
+// candidate (a change of the sign, or of the parity of negative layer
+// denominators) is re-checked in FP64 on a 64-point window, and the stretch
+// FP32 passed over before the window, from the segment's origin (the grid
+// start, or the last FP64-checked point), is certified by E at the window's
+// first point: E = 0 there proves it at once (E is non-negative and
+// non-decreasing); otherwise E at the origin must be equal.  The same
+// certificate covers the stretch before the end of the FP32 sweep when FP32
+// sees no change.  A failed certificate sends the item back to an FP64 walk
+// from the segment's origin; the grid above the half-space's S velocity is
+// walked in FP64.  So the split pick is Algorithm 1's pick in FP64 (up to
+// the noise band of the FP64 signs and counts).
 template <int MODE, int G>
 __device__ bool run_item(const ItemRef& r, ItemState& st, int budget, SweepShared<G>& sh, WorkCount& wc,
                          const ItemOut& o, const CoopRef& co, Counters* cnt) {
@@ -582,14 +617,19 @@ __device__ bool run_item(const ItemRef& r, ItemState& st, int budget, SweepShare
   int start = st.start, carry = st.carry, rounds = 0;
   bool fp64 = (MODE == kModeFP64) || st.fp64;
 
+  if (!fp64 && r.n_real <= 0) {  // the whole grid at or above the half-space's S velocity
+    fp64 = true;
+    st.fp64 = 1;
+  }
   if (!fp64) {
     const float k32 = float(r.k64);
+    const int n32 = r.n_real;
     int seg_start = st.seg_start, seg_carry = st.seg_carry;
     bool shared = co.ci != nullptr;  // the first FP32 pass is a shared sweep
     for (;;) {
       // FP32 sweep for a candidate, from `start` (inside the segment that
       // began at seg_start, whose predecessor's FP64 sign is seg_carry).
-      int cand = -1, fp32_before = kNoSign;
+      int cand = -1;
       if (shared) {
         shared = false;
         int s_c = 0, p_c = 0;
@@ -599,9 +639,8 @@ __device__ bool run_item(const ItemRef& r, ItemState& st, int budget, SweepShare
           write_missing<G>(o, MASW_STATUS_INVALID);
           return true;
         }
-        if (cand >= 0) fp32_before = code_sign(p_c);
       } else {
-        for (int base = start; base < n_c; base += P) {
+        for (int base = start; base < n32; base += P) {
           if (rounds == budget) {
             st.start = base;
             st.carry = carry;
@@ -611,73 +650,115 @@ __device__ bool run_item(const ItemRef& r, ItemState& st, int budget, SweepShare
           }
           ++rounds;
           const int i = base + tid;
-          const int sg = (i < n_c) ? sweep_code32(r.c32[i], k32, r.L32, r.N) : kNoSign;
+          const int sg = (i < n32) ? sweep_code32(r.c32[i], k32, r.L32, r.N) : kNoSign;
           int s_c, p_c;
           const int f = round_first_change<G>(sg, carry, sh.last, sh.first, sh.pair, &carry, &s_c, &p_c);
-          wc.sweep += (unsigned long long)min(P, n_c - base);
+          wc.sweep += (unsigned long long)min(P, n32 - base);
           if (f >= 0) {
             cand = base + f;
-            fp32_before = code_sign(p_c);
             break;
           }
         }
       }
       // FP64 check by wavefront 0 while the others wait: the 64 positions
       // ws-1 .. ws+62 around a candidate (48 before it, 15 after), or, when
-      // FP32 saw no change up to the end of the grid, the last position
-      // (lane 0 in FP64, lane 1 in FP32).  The positions do not depend on
-      // the group size, so neither does the outcome.
+      // FP32 saw no change up to the end of its sweep, the last position it
+      // swept (lane 0).  Lane 0 also counts E at ws - 1 when the segment's
+      // origin lies before it.  The positions do not depend on the group
+      // size, so neither does the outcome.
       const bool at_end = cand < 0;
-      const int ws = at_end ? n_c : max(1, cand - 48);
+      const int ws = at_end ? n32 : max(1, cand - 48);
+      const int origin = (seg_carry == kNoSign) ? 0 : seg_start - 1;
+      const bool certify = ws - 1 > origin;
       if (wave == 0) {
         const int i = ws - 1 + lane;
-        int sg = kNoSign, odd = 0;
-        if (at_end ? lane == 0 : i < n_c) sg = det_sign_parity<double>(r.c64[i], r.k64, r.L64, r.N, &odd);
+        int sg = kNoSign, odd = 0, E = 0;
+        bool bounded = true;
+        if (at_end ? lane == 0 : i < n_c) sg = inertia::det_sign_inertia(r.c64[i], r.k64, r.L64, r.N, &odd, &E, &bounded);
         int last, s_c = 0, p_c = 0;
         const int f = at_end ? -1 : wave_first_change(sg, &s_c, &p_c, &last);
         if (lane == 63) sh.check[6] = (sg == kNoSign) ? kNoSign : sg + 4 * odd;  // sweep code of the window's end
-        if (at_end && lane == 1) sh.check[5] = det_sign<float, false>(r.c32[n_c - 1], k32, r.L32, r.N, nullptr);
         if (lane == 0) {
           sh.check[0] = f;
           sh.check[1] = at_end ? kNoSign : last;
           sh.check[2] = s_c;
           sh.check[3] = p_c;
           sh.check[4] = sg;  // FP64 sign at ws - 1
+          sh.check[5] = E;  // inertia of the pivots at ws - 1 (E there if `bounded`)
+          sh.check[7] = bounded ? 1 : 0;
         }
       }
       __syncthreads();
       const int f = sh.check[0];
       const int last = sh.check[1];
       const int first64 = sh.check[4];
-      const int fp32_last = sh.check[5];
+      int E_p = sh.check[5];
+      const bool bounded = sh.check[7] != 0;
       const int last_code = sh.check[6];
       sig_f = sh.check[2];
       prev_f = sh.check[3];
       __syncthreads();
       wc.check += at_end ? 1ull : (unsigned long long)min(64, n_c - (ws - 1));
-      // The FP64 sign at ws - 1 must be the sign the segment started from.
-      const int ref = (seg_carry != kNoSign) ? seg_carry : (at_end ? fp32_last : fp32_before);
-      if (first64 != ref) {
-        // FP32 missed a change in [seg_start, ws - 1]: continue in FP64.
+      bool ok = seg_carry == kNoSign || first64 == seg_carry;
+      if (ok && certify && !(bounded && E_p == 0)) {
+        // Rare: a layer whose poles need counting at ws - 1, or a change of E
+        // before it (one FP32 did not see, or changes that cancel within one
+        // grid step).  The full counts at ws - 1 and at the origin, by
+        // thread 0.
+        if (tid == 0) {
+          int e = E_p;
+          if (e != inertia::kEvent && !bounded) {
+            bool pok = true;
+            const int P = inertia::poles_below(r.c64[ws - 1], r.k64, r.L64, r.N, &pok);
+            e = pok ? e + 2 * P : inertia::kEvent;
+          }
+          if (e != 0 && e != inertia::kEvent)
+            e = (inertia::count_E_split(r.c64[origin], r.k64, r.L64, r.N) == e) ? 0 : inertia::kEvent;
+          sh.check[5] = e;
+        }
+        __syncthreads();
+        E_p = sh.check[5];
+        __syncthreads();
+        ok = E_p == 0;
+        wc.check += 1ull;
+      }
+      if (!ok) {
+        // FP32 may have missed a change in [seg_start, ws - 1]: continue in FP64.
         fp64 = true;
         st.fp64 = 1;
         start = seg_start;
         carry = seg_carry;
         break;
       }
-      if (at_end) break;  // no change in the grid
+      if (at_end) {
+        // no change below n32; the rest of the grid, at or above the
+        // half-space's S velocity, is walked in FP64
+        if (n32 < n_c) {
+          fp64 = true;
+          st.fp64 = 1;
+          start = n32;
+          carry = first64;
+        }
+        break;
+      }
       if (f >= 0) {
         found = ws - 1 + f;
         break;
       }
       // Rejected: a new segment begins after the window, from the FP64 sign
       // of its last position.  A window that reached the end of the grid
-      // leaves nothing to search.
+      // leaves nothing to search; one that reached n32 leaves an FP64 walk.
       start = ws + 63;
       if (start >= n_c) break;
       seg_carry = last;
       carry = last_code;
       seg_start = start;
+      if (start >= n32) {
+        fp64 = true;
+        st.fp64 = 1;
+        carry = last;
+        break;
+      }
     }
   }
   if (fp64 && MODE == kModeFP64 && co.ci) {
@@ -732,14 +813,17 @@ __device__ __forceinline__ void flush_counts(Counters* c, const WorkCount& wc) {
   }
 }
 
-// The uniform description of the item at queue position `it`.
-__device__ __forceinline__ ItemRef item_ref(const SweepArgs& a, int it, int* g_out) {
+// The uniform description of the item at queue position `it`; *g_out is its
+// wavelength and *m_out (if given) its model.
+__device__ __forceinline__ ItemRef item_ref(const SweepArgs& a, int it, int* g_out, int* m_out = nullptr) {
   const int g = uniform(a.order[it]);
   const int m = uniform(a.lam_model[g]);
+  if (m_out) *m_out = m;
   const ModelDesc d = a.models[m];
   ItemRef r;
   r.N = uniform(d.n_layers);
   r.n_c = uniform(d.n_c);
+  r.n_real = uniform(d.n_real);
   r.k64 = a.lam_k[g];
   r.c64 = a.c64 + uniform(d.c_base);
   r.c32 = a.c32 + uniform(d.c_base);
@@ -825,7 +909,7 @@ __device__ void join_sweeps(const SweepArgs& a, SweepShared<G>& sh, WorkCount& w
       if (!go) break;
       int s0, sl, sa = 0, pa = 0;
       const int f = eval_round<T, G>(r, rd, sh, &s0, &sl, &sa, &pa);
-      const unsigned long long n = (unsigned long long)min(P, r.n_c - rd * P);
+      const unsigned long long n = (unsigned long long)min(P, sweep_len<T>(r) - rd * P);
       wc.sweep += n;
       wc.helper += n;
       if (tid == 0) {
@@ -837,12 +921,54 @@ __device__ void join_sweeps(const SweepArgs& a, SweepShared<G>& sh, WorkCount& w
   }
 }
 
+// Algorithm 2 fused into the batch launch: after an item's outputs are
+// written, the workgroup counts the item off its model, and the workgroup
+// that finishes the model's last wavelength reduces the model's misfit,
+// mean_i |C_t,i - C_e,i| / C_e,i, in the order of misfit_kernel (256 partial
+// sums, each over a stride of 256 wavelengths, then a fixed tree), so the
+// result equals the separate launch's bit for bit.  Agent-scope fences order
+// each item's plain output stores before its count (release) and the last
+// workgroup's reads after it (acquire): the XCDs' L2 caches are not coherent
+// with each other otherwise.
+template <int G>
+__device__ void model_finished(const SweepArgs& a, int m, SweepShared<G>& sh, double* s_mis) {
+  constexpr int P = 64 * G;
+  __syncthreads();  // wavefront 0 has written the item's outputs
+  if (threadIdx.x == 0) {
+    __threadfence();
+    sh.coop[0] = atomicSub(a.model_left + m, 1);
+  }
+  __syncthreads();
+  const bool last = sh.coop[0] == 1;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  const int lo = a.lambda_off[m], hi = a.lambda_off[m + 1];
+  for (int v = threadIdx.x; v < 256; v += P) {
+    double acc = 0.0;
+    for (int i = lo + v; i < hi; i += 256) acc += ::fabs(a.out_ct[i] - a.c_e[i]) / a.c_e[i];
+    s_mis[v] = acc;
+  }
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    for (int v = threadIdx.x; v < w; v += P) s_mis[v] += s_mis[v + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.misfit[m] = s_mis[0] / double(hi - lo);
+  __syncthreads();
+}
+
 // Batch launch: a persistent grid pulls items from the ordered queue and runs
 // each to completion; items at queue positions below n_coop run as shared
-// sweeps that workgroups with an empty queue join.
-template <int MODE, int G>
-__global__ __launch_bounds__(64 * G) void sweep_kernel(SweepArgs a) {
+// sweeps that workgroups with an empty queue join.  MISFIT: Algorithm 2 fused
+// (model_finished), an instantiation of its own so that the plain sweeps
+// keep their register allocation; it is held to 128 VGPRs (4 wavefronts per
+// SIMD, as the plain sweeps), spilling a little outside the layer loop.
+template <int MODE, int G, bool MISFIT>
+__global__ __launch_bounds__(64 * G) __attribute__((amdgpu_waves_per_eu(MISFIT ? 4 : 1)))
+void sweep_kernel(SweepArgs a) {
   __shared__ SweepShared<G> sh;
+  __shared__ double s_mis[MISFIT ? 256 : 1];  // fused misfit reduction
   WorkCount wc;
   constexpr int P = 64 * G;
   for (;;) {
@@ -852,12 +978,13 @@ __global__ __launch_bounds__(64 * G) void sweep_kernel(SweepArgs a) {
     __syncthreads();
     if (it >= a.n_items) break;
 
-    int g;
-    const ItemRef r = item_ref(a, it, &g);
+    int g, m;
+    const ItemRef r = item_ref(a, it, &g, &m);
     const ItemOut o{a.out_ct + g, a.out_idx + g, a.out_status + g, a.out_cref ? a.out_cref + g : nullptr,
                     a.refine, a.refine_rel};
     if (!(r.k64 == r.k64)) {  // invalid model, grid or wavelength
       write_missing<G>(o, MASW_STATUS_INVALID);
+      if constexpr (MISFIT) model_finished<G>(a, m, sh, s_mis);
       continue;
     }
     // Deeper items (earlier queue positions) take issue precedence over the
@@ -874,6 +1001,7 @@ __global__ __launch_bounds__(64 * G) void sweep_kernel(SweepArgs a) {
     }
     ItemState st = item_state_init();
     run_item<MODE, G>(r, st, 0x7fffffff, sh, wc, o, co, a.counters);
+    if constexpr (MISFIT) model_finished<G>(a, m, sh, s_mis);
   }
   __builtin_amdgcn_s_setprio(0);
   if (a.n_coop > 0) join_sweeps<MODE, G>(a, sh, wc);
@@ -1044,13 +1172,15 @@ void tick_kernel(TickArgs a) {
     ItemRef r;
     r.N = uniform(sd.N);
     r.n_c = uniform(sd.n_c);
+    r.n_real = uniform(sd.n_real);
     r.k64 = sd.lam_k[j];
     r.c64 = sd.raw + (r.N + 3 * (r.N + 1) + sd.W);
     r.c32 = sd.c32;
     r.L64 = sd.L64;
     r.L32 = sd.L32;
     const int og = sd.out_base + j;
-    const ItemOut o{a.out_ct + og, a.out_idx + og, a.out_status + og, a.out_cref + og, a.refine, a.refine_rel};
+    const ItemOut o{a.out_ct + og, a.out_idx + og, a.out_status + og, a.out_cref + og,
+                    (a.refine && !(sd.flags & MASW_NO_REFINE)) ? 1 : 0, a.refine_rel};
     bool done;
     if (!(r.k64 == r.k64)) {
       write_missing<G>(o, MASW_STATUS_INVALID);
@@ -1148,20 +1278,21 @@ __global__ __launch_bounds__(256) void sign_map_kernel(SignMapArgs a) {
 }
 
 // --------------------------------------------------------- host launchers --
-template <int MODE>
+template <int MODE, bool MISFIT>
 static const void* sweep_symbol_mode(int G) {
   switch (G) {
-    case 1: return reinterpret_cast<const void*>(&sweep_kernel<MODE, 1>);
-    case 2: return reinterpret_cast<const void*>(&sweep_kernel<MODE, 2>);
-    case 4: return reinterpret_cast<const void*>(&sweep_kernel<MODE, 4>);
-    case 8: return reinterpret_cast<const void*>(&sweep_kernel<MODE, 8>);
-    case 16: return reinterpret_cast<const void*>(&sweep_kernel<MODE, 16>);
+    case 1: return reinterpret_cast<const void*>(&sweep_kernel<MODE, 1, MISFIT>);
+    case 2: return reinterpret_cast<const void*>(&sweep_kernel<MODE, 2, MISFIT>);
+    case 4: return reinterpret_cast<const void*>(&sweep_kernel<MODE, 4, MISFIT>);
+    case 8: return reinterpret_cast<const void*>(&sweep_kernel<MODE, 8, MISFIT>);
+    case 16: return reinterpret_cast<const void*>(&sweep_kernel<MODE, 16, MISFIT>);
   }
   return nullptr;
 }
 
-static const void* sweep_symbol(int mode, int G) {
-  return mode == kModeFP64 ? sweep_symbol_mode<kModeFP64>(G) : sweep_symbol_mode<kModeSplit>(G);
+static const void* sweep_symbol(int mode, int G, bool misfit = false) {
+  if (misfit) return mode == kModeFP64 ? sweep_symbol_mode<kModeFP64, true>(G) : sweep_symbol_mode<kModeSplit, true>(G);
+  return mode == kModeFP64 ? sweep_symbol_mode<kModeFP64, false>(G) : sweep_symbol_mode<kModeSplit, false>(G);
 }
 
 int sweep_blocks_per_cu(int mode, int G) {
@@ -1173,7 +1304,7 @@ int sweep_blocks_per_cu(int mode, int G) {
 }
 
 hipError_t launch_sweep(int mode, int G, int blocks, hipStream_t s, const SweepArgs& a) {
-  const void* f = sweep_symbol(mode, G);
+  const void* f = sweep_symbol(mode, G, a.misfit != nullptr);
   if (!f) return hipErrorInvalidValue;
   void* args[] = {const_cast<SweepArgs*>(&a)};
   return hipLaunchKernel(f, dim3(blocks), dim3(64 * G), args, 0, s);

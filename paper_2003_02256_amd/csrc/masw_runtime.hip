@@ -113,6 +113,8 @@ struct Inputs {
   int32_t n_c = 0;
   int64_t n_layers_total = 0;  // sum N_m
   int64_t n_lam = 0;           // sum W_m
+  const double* c_e = nullptr;  // fused misfit (batch only): experimental curve, [n_lam]
+  double* misfit = nullptr;     // fused misfit: [n_models] (null: no misfit)
 };
 
 // Blocks of the grid check, one flag each.
@@ -127,7 +129,7 @@ size_t workspace_bytes(const Inputs& in, bool stage_inputs, bool stage_outputs) 
   b.take<ModelDesc>(size_t(in.n_models));
   b.take<LayerRec64>(R);
   b.take<LayerRec32>(R);
-  b.take<double>(size_t(in.n_c));
+  if (stage_inputs) b.take<double>(size_t(in.n_c));  // device pointers: the grid is read in place
   b.take<float>(size_t(in.n_c));
   b.take<double>(size_t(in.n_lam));
   b.take<int32_t>(size_t(in.n_lam));
@@ -143,6 +145,13 @@ size_t workspace_bytes(const Inputs& in, bool stage_inputs, bool stage_outputs) 
   if (stage_outputs) {
     b.take<double>(size_t(in.n_lam) * 2);
     b.take<int32_t>(size_t(in.n_lam) * 2);
+  }
+  if (in.misfit) {
+    b.take<int32_t>(size_t(in.n_models));
+    if (stage_inputs) {
+      b.take<double>(size_t(in.n_lam));
+      b.take<double>(size_t(in.n_models));
+    }
   }
   return b.off + kAlign;
 }
@@ -193,19 +202,29 @@ hipError_t resolve_timing(masw_ctx* ctx, masw_ctx::TimingSlot& T) {
   return hipSuccess;
 }
 
+// Where a call's workspace lives: the context's arena (timed, with work
+// counters for masw_get_stats), or the static scratch array of the no-alloc
+// entry point (device pointers only; no arena claim, no events, no stats).
+struct Workspace {
+  char* base;
+  size_t cap;
+  bool noalloc;
+};
+
 // Shared body of the curve and batch calls.
 int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t flags, void* stream,
-               const masw_outputs* out) {
+               const masw_outputs* out, const Workspace& ws) {
   const bool dev = (flags & MASW_DEVICE_PTRS) != 0;
   hipStream_t s = static_cast<hipStream_t>(stream);  // NULL: the default stream
   const size_t need = workspace_bytes(in, !dev, !dev);
-  if (need > ctx->sync_size)
-    return fail(MASW_ENOMEM, "request needs " + std::to_string(need) + " B of device memory, budget is " +
-                                 std::to_string(ctx->sync_size) + " B");
+  if (need > ws.cap)
+    return fail(MASW_ENOMEM, "request needs " + std::to_string(need) + " B of device memory, " +
+                                 (ws.noalloc ? "the no-alloc scratch holds " : "budget is ") +
+                                 std::to_string(ws.cap) + " B");
   MASW_HIP(hipSetDevice(ctx->device));
-  MASW_HIP(claim_arena(ctx, s));
+  if (!ws.noalloc) MASW_HIP(claim_arena(ctx, s));
 
-  Bump b{ctx->arena, ctx->sync_size, 0};
+  Bump b{ws.base, ws.cap, 0};
   const size_t R = size_t(in.n_layers_total + in.n_models);
   PrepArgs p{};
   p.counters = b.take<Counters>(1);
@@ -213,7 +232,7 @@ int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t fl
   p.models = b.take<ModelDesc>(size_t(in.n_models));
   p.layers64 = b.take<LayerRec64>(R);
   p.layers32 = b.take<LayerRec32>(R);
-  double* c_copy = b.take<double>(size_t(in.n_c));
+  double* c_copy = dev ? nullptr : b.take<double>(size_t(in.n_c));
   p.c32 = b.take<float>(size_t(in.n_c));
   p.lam_k = b.take<double>(size_t(in.n_lam));
   p.lam_model = b.take<int32_t>(size_t(in.n_lam));
@@ -276,6 +295,22 @@ int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t fl
     sw.out_idx = b.take<int32_t>(size_t(in.n_lam));
     sw.out_status = b.take<int32_t>(size_t(in.n_lam));
   }
+  // fused misfit: per-model countdown, and the staged C_e and misfit
+  const double* c_e_dev = nullptr;
+  double* misfit_dev = nullptr;
+  if (in.misfit) {
+    p.model_left = b.take<int32_t>(size_t(in.n_models));
+    if (dev) {
+      c_e_dev = in.c_e;
+      misfit_dev = in.misfit;
+    } else {
+      double* ce = b.take<double>(size_t(in.n_lam));
+      misfit_dev = b.take<double>(size_t(in.n_models));
+      if (in.n_lam) MASW_HIP(hipMemcpyAsync(ce, in.c_e, sizeof(double) * in.n_lam, hipMemcpyHostToDevice, s));
+      c_e_dev = ce;
+    }
+    p.misfit = misfit_dev;
+  }
   if (!b.ok()) return fail(MASW_ENOMEM, "workspace exceeds the HBM budget");
 
   const bool inertia = (flags & MASW_SEARCH_INERTIA) != 0;
@@ -302,11 +337,14 @@ int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t fl
     }
   }
 
+  masw_ctx::TimingSlot* T = nullptr;
   const int ts = ctx->tslot_next;
-  masw_ctx::TimingSlot& T = ctx->tslot[ts];
-  if (T.pending) MASW_HIP(resolve_timing(ctx, T));
-  ctx->tslot_next = (ts + 1) % masw_ctx::kTimingSlots;
-  MASW_HIP(hipEventRecord(T.ev[0], s));
+  if (!ws.noalloc) {
+    T = &ctx->tslot[ts];
+    if (T->pending) MASW_HIP(resolve_timing(ctx, *T));
+    ctx->tslot_next = (ts + 1) % masw_ctx::kTimingSlots;
+    MASW_HIP(hipEventRecord(T->ev[0], s));
+  }
   MASW_HIP(launch_prep(p, ci, in.single_N, in.single_W, s));
 
   sw.n_coop = ci.n_coop;
@@ -331,15 +369,24 @@ int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t fl
   sw.refine = (flags & MASW_NO_REFINE) ? 0 : 1;
   sw.refine_rel = ctx->refine_rel;
   sw.counters = p.counters;
-  MASW_HIP(hipEventRecord(T.ev[1], s));
+  if (in.misfit && !inertia) {  // the inertia search takes a separate misfit launch below
+    sw.c_e = c_e_dev;
+    sw.misfit = misfit_dev;
+    sw.model_left = p.model_left;
+    sw.lambda_off = p.lambda_off;
+  }
+  if (T) MASW_HIP(hipEventRecord(T->ev[1], s));
   if (in.n_lam > 0) MASW_HIP(inertia ? launch_inertia(sw, ctx->cus, s, &blocks) : launch_sweep(mode, G, blocks, s, sw));
-  MASW_HIP(hipEventRecord(T.ev[2], s));
+  if (T) MASW_HIP(hipEventRecord(T->ev[2], s));
+  if (in.misfit && inertia)
+    MASW_HIP(launch_misfit(in.n_models, p.lambda_off, sw.out_ct, c_e_dev, misfit_dev, s));
   // optional diagnostic after the timed sweep: the FP64 noise band of each
   // pick's bracket
   if ((flags & MASW_CHECK_NOISE) && in.n_lam > 0)
     MASW_HIP(launch_noise_check(p.models, p.layers64, p.c64, p.lam_k, p.lam_model, sw.out_idx, sw.out_status,
                                 in.n_lam, ctx->noise_threshold, s));
-  T.pending = true;
+  if (ws.noalloc) return MASW_OK;
+  T->pending = true;
   ctx->tslot_last = ts;
   ctx->last = masw_stats{};
   ctx->last.n_lambda = uint64_t(in.n_lam);
@@ -360,6 +407,8 @@ int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t fl
       if (out->c_ref)
         MASW_HIP(hipMemcpyAsync(out->c_ref, sw.out_cref, sizeof(double) * W, hipMemcpyDeviceToHost, s));
     }
+    if (in.misfit)
+      MASW_HIP(hipMemcpyAsync(in.misfit, misfit_dev, sizeof(double) * in.n_models, hipMemcpyDeviceToHost, s));
     MASW_HIP(hipStreamSynchronize(s));
   }
   return MASW_OK;
@@ -504,12 +553,14 @@ int masw_dispersion_curve(masw_ctx* ctx, const double* c_test, int32_t n_c, cons
   in.n_layers_total = model->n_layers;
   in.n_lam = n_lambda;
   masw_outputs o{C_t, idx, status, c_ref};
-  return run_curves(ctx, in, prec, flags, stream, &o);
+  return run_curves(ctx, in, prec, flags, stream, &o, Workspace{ctx->arena, ctx->sync_size, false});
 }
 
-int masw_dispersion_batch(masw_ctx* ctx, const double* c_test, int32_t n_c, const masw_batch* batch,
-                          masw_precision prec, uint32_t flags, void* stream, const masw_outputs* out) {
-  TraceRange trace("masw_dispersion_batch");
+// Shared body of masw_dispersion_batch and masw_dispersion_batch_misfit
+// (C_e, misfit null for the former).
+static int batch_impl(masw_ctx* ctx, const double* c_test, int32_t n_c, const masw_batch* batch,
+                      masw_precision prec, uint32_t flags, void* stream, const masw_outputs* out,
+                      const double* C_e, double* misfit) {
   const bool dev = (flags & MASW_DEVICE_PTRS) != 0;
   int rc;
   if (!batch) return fail(MASW_EINVAL, "batch: null pointer");
@@ -551,6 +602,9 @@ int masw_dispersion_batch(masw_ctx* ctx, const double* c_test, int32_t n_c, cons
         return rc;
     }
     if ((rc = check_lambda(batch->lambda, int32_t(W), true))) return rc;
+    if (misfit)
+      for (int64_t i = 0; i < W; ++i)
+        if (!(std::isfinite(C_e[i]) && C_e[i] > 0.0)) return fail(MASW_EINVAL, "C_e must be finite and > 0");
     if ((rc = check_common(ctx, prec, flags))) return rc;
   }
   std::lock_guard<std::mutex> lock(ctx->mu);
@@ -567,7 +621,23 @@ int masw_dispersion_batch(masw_ctx* ctx, const double* c_test, int32_t n_c, cons
   in.n_c = n_c;
   in.n_layers_total = L;
   in.n_lam = W;
-  return run_curves(ctx, in, prec, flags, stream, out);
+  in.c_e = C_e;
+  in.misfit = misfit;
+  return run_curves(ctx, in, prec, flags, stream, out, Workspace{ctx->arena, ctx->sync_size, false});
+}
+
+int masw_dispersion_batch(masw_ctx* ctx, const double* c_test, int32_t n_c, const masw_batch* batch,
+                          masw_precision prec, uint32_t flags, void* stream, const masw_outputs* out) {
+  TraceRange trace("masw_dispersion_batch");
+  return batch_impl(ctx, c_test, n_c, batch, prec, flags, stream, out, nullptr, nullptr);
+}
+
+int masw_dispersion_batch_misfit(masw_ctx* ctx, const double* c_test, int32_t n_c, const masw_batch* batch,
+                                 masw_precision prec, uint32_t flags, void* stream, const masw_outputs* out,
+                                 const double* C_e, double* misfit) {
+  TraceRange trace("masw_dispersion_batch_misfit");
+  if (!C_e || !misfit) return fail(MASW_EINVAL, "C_e, misfit: null array");
+  return batch_impl(ctx, c_test, n_c, batch, prec, flags, stream, out, C_e, misfit);
 }
 
 int masw_sign_map(masw_ctx* ctx, const double* c_test, int32_t n_c, const double* lambda, int32_t n_lambda,

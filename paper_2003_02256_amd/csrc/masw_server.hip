@@ -94,6 +94,8 @@ struct Request {
   uint64_t ticket = 0;
   int prec = 0;
   int N = 0, W = 0, n_c = 0;
+  int n_real = 0;           // grid points below the half-space's S velocity
+  uint32_t flags = 0;       // MASW_CHECK_NOISE, MASW_NO_REFINE
   std::vector<double> raw;  // h[N], alpha, beta, rho [N+1], lambda[W], c[n_c]
   std::vector<double> ct, cref;
   std::vector<int32_t> idx, status;
@@ -150,6 +152,9 @@ struct Server {
   int32_t* out_idx = nullptr;
   int32_t* out_status = nullptr;
   int32_t* host_done = nullptr;
+  int32_t* out_idx_dev = nullptr;   // device views of out_idx, out_status
+  int32_t* out_status_dev = nullptr;
+  double noise_threshold = 1e-2;    // MASW_CHECK_NOISE band of served requests
   char* staging = nullptr;          // pinned: admit list, then raw inputs
   char* staging_dev = nullptr;      // device copy of the same
   size_t staging_size = 0;
@@ -181,6 +186,7 @@ struct Server {
   void watch();
   void fail_all(const std::string& msg);  // with mu held
   void release_all();
+  hipError_t check_noise_of_finished();  // driver thread, after a tick
 };
 
 void Server::fail_all(const std::string& msg) {
@@ -258,6 +264,8 @@ void Server::run() {
       d.W = r->W;
       d.n_c = r->n_c;
       d.prec = r->prec;
+      d.n_real = r->n_real;
+      d.flags = r->flags;
       d.out_base = slot * opt.max_lambda;
       desc_host->slot[slot] = d;
       admit_host->slot[n_admit] = slot;
@@ -301,6 +309,7 @@ void Server::run() {
       queue_base += uint32_t(units) + uint32_t(blocks[gi]);  // one final claim per workgroup
     }
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e == hipSuccess) e = check_noise_of_finished();
     roctxRangePop();
     const uint64_t t1 = now_ns();
 
@@ -335,6 +344,31 @@ void Server::run() {
     }
     cv_done.notify_all();
   }
+}
+
+// The noise band of the picks of requests with MASW_CHECK_NOISE that the
+// tick just finished, before their results are harvested: one launch per 16
+// such requests, then one synchronisation.
+hipError_t Server::check_noise_of_finished() {
+  ServeNoiseList list{};
+  bool launched = false;
+  hipError_t e = hipSuccess;
+  for (int s = 0; s < kMaxSlots && e == hipSuccess; ++s) {
+    const Request* r = slot_req[s];
+    if (!r || !host_done[s] || !(r->flags & MASW_CHECK_NOISE)) continue;
+    list.slot[list.n++] = desc_host->slot[s];
+    if (list.n == kNoiseList) {
+      e = launch_serve_noise(list, out_idx_dev, out_status_dev, noise_threshold, stream);
+      launched = true;
+      list.n = 0;
+    }
+  }
+  if (e == hipSuccess && list.n > 0) {
+    e = launch_serve_noise(list, out_idx_dev, out_status_dev, noise_threshold, stream);
+    launched = true;
+  }
+  if (e == hipSuccess && launched) e = hipStreamSynchronize(stream);
+  return e;
 }
 
 void Server::release_all() {
@@ -456,6 +490,7 @@ int masw_server_start(masw_ctx* ctx, const masw_server_opts* opts) {
   ta.refine = 1;
   ta.inertia = o.search_inertia;
   ta.refine_rel = ctx->refine_rel;
+  s->noise_threshold = ctx->noise_threshold;
   void* dp = nullptr;
   if (hipHostGetDevicePointer(&dp, s->out_ct, 0) != hipSuccess) return bail("hipHostGetDevicePointer failed");
   ta.out_ct = static_cast<double*>(dp);
@@ -463,8 +498,10 @@ int masw_server_start(masw_ctx* ctx, const masw_server_opts* opts) {
   ta.out_cref = static_cast<double*>(dp);
   if (hipHostGetDevicePointer(&dp, s->out_idx, 0) != hipSuccess) return bail("hipHostGetDevicePointer failed");
   ta.out_idx = static_cast<int32_t*>(dp);
+  s->out_idx_dev = ta.out_idx;
   if (hipHostGetDevicePointer(&dp, s->out_status, 0) != hipSuccess) return bail("hipHostGetDevicePointer failed");
   ta.out_status = static_cast<int32_t*>(dp);
+  s->out_status_dev = ta.out_status;
   if (hipHostGetDevicePointer(&dp, s->host_done, 0) != hipSuccess) return bail("hipHostGetDevicePointer failed");
   ta.host_done = static_cast<int32_t*>(dp);
   for (int gi = 0; gi < 4; ++gi) {
@@ -509,7 +546,7 @@ int masw_server_stop(masw_ctx* ctx) {
 }
 
 int masw_submit(masw_ctx* ctx, const double* c_test, int32_t n_c, const double* lambda, int32_t n_lambda,
-                const masw_model* model, masw_precision prec, uint64_t* ticket) {
+                const masw_model* model, masw_precision prec, uint32_t flags, uint64_t* ticket) {
   int rc;
   if (!model) return fail(MASW_EINVAL, "model: null pointer");
   if (!ticket) return fail(MASW_EINVAL, "ticket: null pointer");
@@ -518,6 +555,8 @@ int masw_submit(masw_ctx* ctx, const double* c_test, int32_t n_c, const double* 
   if ((rc = check_model_values(model->n_layers, model->h, model->alpha, model->beta, model->rho, "model")))
     return rc;
   if (prec != MASW_PREC_FP64 && prec != MASW_PREC_SPLIT) return fail(MASW_EINVAL, "prec: unknown precision");
+  if (flags & ~(MASW_CHECK_NOISE | MASW_NO_REFINE))
+    return fail(MASW_EINVAL, "flags: a request takes only MASW_CHECK_NOISE and MASW_NO_REFINE");
   if (!ctx) return fail(MASW_EINVAL, "ctx: null context");
   Server* s = ctx->server;
   if (!s) return fail(MASW_EBUSY, "server not running");
@@ -528,9 +567,23 @@ int masw_submit(masw_ctx* ctx, const double* c_test, int32_t n_c, const double* 
     return fail(MASW_ENOMEM, "request can never fit the serving pool");
   auto r = std::make_unique<Request>();
   r->prec = prec;
+  r->flags = flags;
   r->N = N;
   r->W = n_lambda;
   r->n_c = n_c;
+  {
+    // first grid point with c^2 / beta_hs^2 >= 1, in the arithmetic of the
+    // device's inertia-count test (the grid rises, checked above)
+    const double be = model->beta[N];
+    const double ib2 = 1.0 / (be * be);
+    int lo = 0, hi = n_c;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      const double c = c_test[mid];
+      if (c * c * ib2 < 1.0) lo = mid + 1; else hi = mid;
+    }
+    r->n_real = lo;
+  }
   r->raw.reserve(size_t(N) + 3 * size_t(N + 1) + size_t(n_lambda) + size_t(n_c));
   r->raw.insert(r->raw.end(), model->h, model->h + N);
   r->raw.insert(r->raw.end(), model->alpha, model->alpha + N + 1);

@@ -5,9 +5,9 @@ many candidate models with the experimental one (Section 2.1; Algorithm 2
 gives the misfit of one model), and quantifying uncertainty needs more of
 them still.  This client runs a population of chains.  At every step each
 chain proposes a perturbed model.  All proposals go through one batched
-dispersion-curve launch and one misfit launch on the device
-(`masw_dispersion_batch`, `masw_misfit`), and only the misfits come back to
-the host.  Each chain then accepts its proposal with the Metropolis rule for
+launch on the device that computes their dispersion curves and reduces
+Algorithm 2's misfit of each (`masw_dispersion_batch_misfit`), and only the
+misfits come back to the host.  Each chain then accepts its proposal with the Metropolis rule for
 the target density exp(-misfit / temperature).
 
 The chain logic (`perturb`, `metropolis_accept`, `run_chains`) is plain host
@@ -23,8 +23,7 @@ from typing import Callable, List, Sequence
 
 import numpy as np
 
-from . import (MASW_NO_REFINE, MASW_PREC_FP64, MASW_PREC_SPLIT, MASW_SEARCH_INERTIA, masw_dispersion_batch,
-               masw_misfit)
+from . import MASW_NO_REFINE, MASW_PREC_FP64, MASW_PREC_SPLIT, MASW_SEARCH_INERTIA, masw_dispersion_batch_misfit
 
 
 @dataclass
@@ -158,8 +157,9 @@ class DeviceEvaluator:
     All models share the test-velocity grid and the wavelengths of the
     experimental curve C_e.  One call flattens the models, runs the batched
     sweep with device-resident outputs (C_t only: the misfit uses the grid
-    velocity of each pick, so the root refinement is skipped), reduces the
-    misfits on the device and copies back only the misfits.  With
+    velocity of each pick, so the root refinement is skipped) with Algorithm
+    2's misfit reduced in the same launch (masw_dispersion_batch_misfit), and
+    copies back only the misfits.  With
     inertia=True the picks come from the FP64 inertia-count search
     (MASW_SEARCH_INERTIA; prec is then FP64), whose C_t equal the FP64 walk's
     bit for bit."""
@@ -201,10 +201,9 @@ class DeviceEvaluator:
         ct = torch.empty(W, dtype=f64, device=dev)
         idx = torch.empty(W, dtype=i32, device=dev)
         st = torch.empty(W, dtype=i32, device=dev)
-        masw_dispersion_batch(self.ctx, self.c, layer_off, t(pop.h), t(pop.alpha), t(pop.beta), t(pop.rho),
-                              lam_off, lam, self.prec, self.flags, None, ct, idx, st, None)
         mis = torch.empty(n, dtype=f64, device=dev)
-        masw_misfit(self.ctx, lam_off, ct, ce, 0, None, mis)
+        masw_dispersion_batch_misfit(self.ctx, self.c, layer_off, t(pop.h), t(pop.alpha), t(pop.beta), t(pop.rho),
+                                     lam_off, lam, self.prec, self.flags, None, ct, idx, st, None, ce, mis)
         self.models_evaluated += n
         return mis.cpu().numpy()
 

@@ -29,6 +29,9 @@ hipError_t launch_misfit(int, const int32_t*, const double*, const double*, doub
   return reached("misfit");
 }
 hipError_t launch_classify(const ClassifyArgs&, hipStream_t) { return reached("classify"); }
+hipError_t launch_serve_noise(const ServeNoiseList&, const int32_t*, int32_t*, double, hipStream_t) {
+  return reached("serve noise");
+}
 hipError_t launch_noise_check(const ModelDesc*, const LayerRec64*, const double*, const double*, const int32_t*,
                               const int32_t*, int32_t*, int64_t, double, hipStream_t) {
   return reached("noise");
@@ -124,7 +127,9 @@ int main() {
 
   // serving without a server, stats and timing without a context
   uint64_t t = 0;
-  expect(masw_submit(nullptr, c.data(), 801, lam.data(), 30, &m, MASW_PREC_FP64, &t), E, "submit null context");
+  expect(masw_submit(nullptr, c.data(), 801, lam.data(), 30, &m, MASW_PREC_FP64, 0, &t), E, "submit null context");
+  expect(masw_submit(nullptr, c.data(), 801, lam.data(), 30, &m, MASW_PREC_FP64, MASW_DEVICE_PTRS, &t), E,
+         "submit with a flag requests do not take");
   expect(masw_server_start(nullptr, nullptr), E, "server start null context");
   masw_stats s;
   expect(masw_get_stats(nullptr, &s), E, "stats null context");

@@ -152,13 +152,17 @@ def test_serving_calls_validate_without_a_device(lib):
     mod = M._model_struct(m.h, m.alpha, m.beta, m.rho)
     t = ctypes.c_uint64()
     rc = lib.masw_submit(None, M._ptr(c, np.float64), int(c.shape[0]), M._ptr(lam, np.float64), int(lam.shape[0]),
-                         ctypes.byref(mod), M.MASW_PREC_FP64, ctypes.byref(t))
+                         ctypes.byref(mod), M.MASW_PREC_FP64, 0, ctypes.byref(t))
     assert rc == M.MASW_EINVAL and "ctx" in M.masw_last_error()
     c2 = c.copy()
     c2[3] = c2[2]
     rc = lib.masw_submit(None, M._ptr(c2, np.float64), int(c2.shape[0]), M._ptr(lam, np.float64),
-                         int(lam.shape[0]), ctypes.byref(mod), M.MASW_PREC_FP64, ctypes.byref(t))
+                         int(lam.shape[0]), ctypes.byref(mod), M.MASW_PREC_FP64, 0, ctypes.byref(t))
     assert rc == M.MASW_EINVAL and "increasing" in M.masw_last_error()
+    for bad in (M.MASW_DEVICE_PTRS, M.MASW_SEARCH_INERTIA, 0x100):
+        rc = lib.masw_submit(None, M._ptr(c, np.float64), int(c.shape[0]), M._ptr(lam, np.float64),
+                             int(lam.shape[0]), ctypes.byref(mod), M.MASW_PREC_FP64, bad, ctypes.byref(t))
+        assert rc == M.MASW_EINVAL and "flags" in M.masw_last_error()
     assert lib.masw_server_start(None, None) == M.MASW_EINVAL
     assert lib.masw_server_stop(None) == M.MASW_EINVAL
     info = M.masw_request_info()

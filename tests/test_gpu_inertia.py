@@ -238,18 +238,6 @@ def test_runs_with_predictions_across_models_and_invalid_items(torch_dev, ctx):
     assert st["check_evals"] < 64 * len(got[1]) // 2   # runs of 4 here: most wavelengths were predicted
 
 
-def _random_model(rng, N):
-    """A layered model outside the workloads' recipes: thicknesses over two
-    decades, velocities that may fall with depth (several low-velocity
-    layers, a half-space slower than some layers), Poisson ratios 0.05-0.45."""
-    h = np.exp(rng.uniform(np.log(0.2), np.log(20.0), size=N))
-    beta = rng.uniform(80.0, 600.0, size=N + 1)
-    nu = rng.uniform(0.05, 0.45, size=N + 1)
-    alpha = WL.alpha_from_poisson(beta, nu)
-    rho = rng.uniform(1500.0, 2600.0, size=N + 1)
-    return WL.Model(h, alpha, beta, rho)
-
-
 @pytest.mark.parametrize("seed,dc,n_c,lo", [(101, 0.5, 3001, 40.0), (102, 0.05, 12001, 60.0),
                                             (103, 0.01, 40001, 90.0)])
 def test_random_models_equal_the_walk(torch_dev, ctx, seed, dc, n_c, lo):
@@ -258,7 +246,7 @@ def test_random_models_equal_the_walk(torch_dev, ctx, seed, dc, n_c, lo):
     # Outputs equal the walk's bit for bit; an index that differs would be
     # excused only inside the FP64 noise band (none has been seen).
     rng = np.random.Generator(np.random.PCG64(seed))
-    models = [_random_model(rng, int(rng.integers(1, 41))) for _ in range(96)]
+    models = [WL.random_model(rng, int(rng.integers(1, 41))) for _ in range(96)]
     lambdas = [np.sort(np.exp(rng.uniform(np.log(0.3), np.log(150.0), size=int(rng.integers(20, 400)))))
                for _ in models]
     c = WL.uniform_grid(lo, dc, n_c)
@@ -282,31 +270,24 @@ def test_random_models_equal_the_walk(torch_dev, ctx, seed, dc, n_c, lo):
 def test_random_stress_thirty_configurations(torch_dev, ctx):
     # 30 configurations of 96 random models each (about 730,000 wavelengths):
     # grids of 0.5 to 0.01 m/s up to 60,000 points, wavelengths 0.2-200 m,
-    # some models' wavelengths in reverse order.  Every output equals the
-    # walk's; an index difference would be excused only in the noise band.
+    # some models' wavelengths in reverse order.  Every output of the inertia
+    # search and of the split path equals the walk's; an index difference
+    # would be excused only in the noise band.
     total = 0
     for seed in range(1000, 1030):
-        rng = np.random.Generator(np.random.PCG64(seed))
-        dc = [0.5, 0.1, 0.05, 0.02, 0.01][seed % 5]
-        lo = rng.uniform(20.0, 120.0)
-        n_c = int(min(60000, (rng.uniform(600.0, 1500.0) - lo) / dc))
-        c = WL.uniform_grid(lo, dc, n_c)
-        models = [_random_model(rng, int(rng.integers(1, 41))) for _ in range(96)]
-        lambdas = [np.sort(np.exp(rng.uniform(np.log(0.2), np.log(200.0), size=int(rng.integers(10, 500)))))
-                   for _ in models]
-        if seed % 3 == 0:
-            for l in lambdas[::4]:
-                l[:] = l[::-1]
+        wl = WL.random_stress_config(seed)
+        c, models, lambdas = wl.c_test, wl.models, wl.lambdas
         walk = dev_batch(torch_dev, ctx, c, models, lambdas, FP64)
-        got = dev_batch(torch_dev, ctx, c, models, lambdas, FP64, INERTIA)
         off = np.concatenate([[0], np.cumsum([len(l) for l in lambdas])])
-        for w in np.nonzero(got[1] != walk[1])[0]:
-            mi = int(np.searchsorted(off, w, side="right") - 1)
-            pts = {p for i in (int(got[1][w]), int(walk[1][w])) if i > 0 for p in (i - 1, i)}
-            assert any(O.in_noise_band(float(lambdas[mi][w - off[mi]]), float(c[p]), models[mi]) for p in pts), \
-                (seed, w, got[1][w], walk[1][w])
-        same = got[1] == walk[1]
-        for x, y, what in zip(walk, got, ("C_t", "idx", "status", "c_ref")):
-            np.testing.assert_array_equal(y[same], x[same], err_msg=f"seed {seed}: {what}")
-        total += len(got[1])
+        for name, got in (("inertia", dev_batch(torch_dev, ctx, c, models, lambdas, FP64, INERTIA)),
+                          ("split", dev_batch(torch_dev, ctx, c, models, lambdas, M.MASW_PREC_SPLIT))):
+            for w in np.nonzero(got[1] != walk[1])[0]:
+                mi = int(np.searchsorted(off, w, side="right") - 1)
+                pts = {p for i in (int(got[1][w]), int(walk[1][w])) if i > 0 for p in (i - 1, i)}
+                assert any(O.in_noise_band(float(lambdas[mi][w - off[mi]]), float(c[p]), models[mi]) for p in pts), \
+                    (name, seed, mi, w - off[mi], got[1][w], walk[1][w])
+            same = got[1] == walk[1]
+            for x, y, what in zip(walk, got, ("C_t", "idx", "status", "c_ref")):
+                np.testing.assert_array_equal(y[same], x[same], err_msg=f"{name} seed {seed}: {what}")
+        total += len(walk[1])
     print(f"random stress: {total} wavelengths over 30 configurations", flush=True)

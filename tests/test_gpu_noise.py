@@ -87,3 +87,48 @@ def test_flag_at_and_near_a_root(ctx, case):
         seen.append(flags[0])
     print(f"{case}: flagged at relative distance 0, 1e-15 .. 1e-11, 1e-9 from the root: {seen}", flush=True)
     assert seen[0] and not seen[-1], seen       # the root itself is in the band, 1e-9 away is not
+
+
+def test_served_requests_carry_the_flag(ctx):
+    # requests submitted with MASW_CHECK_NOISE get the same flag as the
+    # synchronous call (and MASW_NO_REFINE the same NaN roots), in a mix of
+    # flagged and unflagged requests sharing ticks
+    model = WL.fine_scale_case().models[0]
+    lam = 7.0
+    coarse = WL.uniform_grid(50.0, 0.5, 2000)
+    p = O.dispersion_point(lam, coarse, model, refine=False)
+    root = _exact_root(lam, float(coarse[p.idx - 1]), float(coarse[p.idx]), model)
+    grids = [root * (1.0 + d) + 0.01 * (np.arange(300) - 100.0) for d in (0.0, 1e-13, 1e-9)]
+    lams = np.array([lam, 5.0, 9.0])
+    M.masw_server_start(ctx.ctx, rounds_per_tick=1)
+    try:
+        jobs = []
+        for g in grids:
+            for prec in (M.MASW_PREC_FP64, M.MASW_PREC_SPLIT):
+                for flags in (M.MASW_CHECK_NOISE, 0, M.MASW_CHECK_NOISE | M.MASW_NO_REFINE):
+                    t = M.masw_submit(ctx.ctx, g, lams, model.h, model.alpha, model.beta, model.rho, prec, flags)
+                    jobs.append((t, g, prec, flags))
+        got_flags = []
+        for t, g, prec, flags in jobs:
+            o = (np.empty(3), np.empty(3, np.int32), np.empty(3, np.int32), np.empty(3))
+            M.masw_wait(ctx.ctx, t, 60_000_000, *o)
+            sync = ctx.curve(g, lams, model, prec=prec, flags=flags & M.MASW_CHECK_NOISE)
+            np.testing.assert_array_equal(o[1], sync[1])
+            np.testing.assert_array_equal(o[2], sync[2])
+            np.testing.assert_array_equal(o[0], sync[0])
+            if flags & M.MASW_NO_REFINE:
+                assert np.all(np.isnan(o[3]))
+            else:
+                np.testing.assert_array_equal(o[3], sync[3])
+            if flags & M.MASW_CHECK_NOISE:
+                got_flags.append(bool(o[2][0] & M.MASW_FLAG_NOISE))
+            else:
+                assert not np.any(o[2] & M.MASW_FLAG_NOISE)
+        # the grid point at the root is in the band, 1e-9 away is not
+        assert got_flags[0] and not got_flags[-1], got_flags
+        with pytest.raises(M.MaswError) as e:
+            M.masw_submit(ctx.ctx, grids[0], lams, model.h, model.alpha, model.beta, model.rho,
+                          M.MASW_PREC_FP64, M.MASW_SEARCH_INERTIA)
+        assert e.value.code == M.MASW_EINVAL
+    finally:
+        M.masw_server_stop(ctx.ctx)

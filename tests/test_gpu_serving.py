@@ -228,3 +228,35 @@ def test_watchdog_fails_the_server_and_restart_recovers(ctx):
     with pytest.raises(M.MaswError) as e:
         M.masw_server_start(ctx.ctx, tick_timeout_us=-5)
     assert e.value.code == M.MASW_EINVAL
+
+
+def test_served_sample_of_the_trace_matches_the_oracle(ctx):
+    # 64 requests sampled evenly from the 2000 req/s serving trace, every
+    # wavelength against the oracle (tests/golden/serving_sample.json), each
+    # served twice in one mix, split and plain FP64, a few sweep rounds per
+    # tick so that searches span many ticks.  No index difference is excused.
+    import json
+    import os
+    from test_gpu_parity import compare
+    g = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "serving_sample.json")))
+    times, reqs = WL.serving_trace(g["rate"], g["duration"], g["seed"])
+    assert len(times) == g["n_requests"]
+    c = WL.serving_grid()
+    M.masw_server_start(ctx.ctx, rounds_per_tick=3)
+    try:
+        jobs = []
+        for e in g["requests"]:
+            m, lam = reqs[e["index"]]
+            assert m.n_layers == e["n_layers"]
+            for prec in (M.MASW_PREC_SPLIT, M.MASW_PREC_FP64):
+                jobs.append((submit(ctx, c, lam, m, prec), e, m, lam, prec))
+        n_total = 0
+        for t, e, m, lam, prec in jobs:
+            got, info = wait(ctx, t, len(lam))
+            n, n_noise, _ = compare(f"served request {e['index']} prec={prec}", got, e["idx"], e["status"],
+                                    [float(x) for x in e["c_ref"]], lam, c, m)
+            assert n_noise == 0 and n == len(lam)
+            n_total += n
+        print(f"served sample: {len(jobs)} requests, {n_total} wavelengths equal to the oracle", flush=True)
+    finally:
+        M.masw_server_stop(ctx.ctx)

@@ -232,3 +232,63 @@ def poisson_arrivals(rate: float, duration: float, seed: int = 55) -> np.ndarray
     n = int(rate * duration * 1.5) + 16
     t = np.cumsum(rng.exponential(1.0 / rate, size=n))
     return t[t < duration]
+
+
+# --------------------------------------------------------------------------
+# Random models outside the recipes above (stress and parity cases).
+# --------------------------------------------------------------------------
+def random_model(rng: np.random.Generator, n_layers: int) -> Model:
+    """A layered model outside the workloads' recipes: thicknesses over two
+    decades (0.2-20 m, log-uniform), S velocities U(80, 600) that may fall
+    with depth (low-velocity layers, a half-space slower than some layers),
+    Poisson ratios U(0.05, 0.45), densities U(1500, 2600).  Draw order:
+    h[N], beta[N+1], nu[N+1], rho[N+1]."""
+    N = n_layers
+    h = np.exp(rng.uniform(np.log(0.2), np.log(20.0), size=N))
+    beta = rng.uniform(80.0, 600.0, size=N + 1)
+    nu = rng.uniform(0.05, 0.45, size=N + 1)
+    alpha = alpha_from_poisson(beta, nu)
+    rho = rng.uniform(1500.0, 2600.0, size=N + 1)
+    return Model(h, alpha, beta, rho)
+
+
+def random_stress_config(seed: int, n_models: int = 96) -> Workload:
+    """One configuration of the random-model stress: a grid of 0.5, 0.1,
+    0.05, 0.02 or 0.01 m/s (by seed mod 5) from U(20, 120) m/s up to
+    U(600, 1500) m/s (at most 60,000 points); n_models random models with
+    N ~ U{1..40}; per model U{10..499} wavelengths log-uniform in 0.2-200 m,
+    sorted, and for seeds divisible by 3 every fourth model's list reversed.
+    Draw order: grid start, grid end, then per model N and the model, then
+    per model the wavelength count and the wavelengths."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    dc = [0.5, 0.1, 0.05, 0.02, 0.01][seed % 5]
+    lo = rng.uniform(20.0, 120.0)
+    n_c = int(min(60000, (rng.uniform(600.0, 1500.0) - lo) / dc))
+    c = uniform_grid(lo, dc, n_c)
+    models = [random_model(rng, int(rng.integers(1, 41))) for _ in range(n_models)]
+    lambdas = [np.sort(np.exp(rng.uniform(np.log(0.2), np.log(200.0), size=int(rng.integers(10, 500)))))
+               for _ in models]
+    if seed % 3 == 0:
+        for l in lambdas[::4]:
+            l[:] = l[::-1]
+    return Workload(f"random_stress_{seed}", models, lambdas, c)
+
+
+def serving_trace(rate: float, duration: float, seed: int = 55):
+    """The serving workload's request stream: Poisson arrival times (s) over
+    `duration` at `rate` per second, and for each arrival the model and
+    wavelengths of its request.  Each arrival picks one of the 64 chains of
+    chain_bases() uniformly and advances it one chain_step.  Draw order: the
+    arrival times (seed), then from PCG64(seed + 1) the chain of every
+    arrival, then the steps in arrival order."""
+    bases = chain_bases(64, 5)
+    times = poisson_arrivals(rate, duration, seed)
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    pick = rng.integers(0, len(bases), size=len(times))
+    state = [b.model for b in bases]
+    reqs = []
+    for i in range(len(times)):
+        ch = int(pick[i])
+        state[ch] = chain_step(rng, state[ch])
+        reqs.append((state[ch], bases[ch].lambdas))
+    return times, reqs
