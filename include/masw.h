@@ -244,6 +244,34 @@ int masw_dispersion_curve(masw_ctx *ctx, const double *c_test, int32_t n_c,
                           double *C_t, int32_t *idx, int32_t *status,
                           double *c_ref);
 
+/* masw_dispersion_curve without allocation, for callers that cannot call
+ * hipMalloc: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation.  Same arguments, meaning and outputs as
+ * masw_dispersion_curve, with every array a device pointer in stream order
+ * (MASW_DEVICE_PTRS is required; MASW_EINVAL otherwise).  The call's device
+ * workspace (layer records, the FP32 grid, k and the work order per
+ * wavelength, counters, shared-sweep state) lives in a static device array
+ * of the library, MASW_NOALLOC_SCRATCH_BYTES on each device that loads the
+ * library (held until the process ends), instead of the context's arena; the
+ * call allocates nothing, synchronises nothing and records no events.  The
+ * context supplies its device and options only; masw_create set the array up
+ * on that device.
+ * Limit: a request whose workspace exceeds MASW_NOALLOC_SCRATCH_BYTES (about
+ * 4 B per grid point, 17 B per wavelength and 96 B per layer, plus, when
+ * they fit, 8 B per round of 64 G grid points per wavelength for shared
+ * sweeps) fails with MASW_ENOMEM before anything is queued.
+ * Sharing: every call on one device uses that device's one array, which
+ * keeps the last call's contents (the call's first kernel clears what must
+ * start at zero).  Calls whose work overlaps on the device (other streams,
+ * threads or contexts) race on it: the caller orders them.  These calls are
+ * not counted by masw_get_stats or masw_get_timing. */
+#define MASW_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+int masw_dispersion_curve_noalloc(masw_ctx *ctx, const double *c_test, int32_t n_c,
+                                  const double *lambda, int32_t n_lambda,
+                                  const masw_model *model, masw_precision prec,
+                                  uint32_t flags, void *stream, double *C_t,
+                                  int32_t *idx, int32_t *status, double *c_ref);
+
 /* Dispersion curves of a batch of models sharing one c grid, in one
  * persistent launch whose work queue hands out (model, wavelength) items
  * longest-expected-first.  Same rules as masw_dispersion_curve. */

@@ -48,6 +48,7 @@ MASW_NO_REFINE = 0x2
 MASW_CHECK_NOISE = 0x4
 MASW_SEARCH_INERTIA = 0x8
 MASW_MAX_LAYERS = 1024
+MASW_NOALLOC_SCRATCH_BYTES = 32 << 20
 
 
 class MaswError(RuntimeError):
@@ -151,6 +152,8 @@ def library() -> ctypes.CDLL:
             "masw_destroy": (None, [vp]),
             "masw_dispersion_curve": (ctypes.c_int, [vp, vp, i32, vp, i32, ctypes.POINTER(masw_model),
                                                      ctypes.c_int, u32, vp, vp, vp, vp, vp]),
+            "masw_dispersion_curve_noalloc": (ctypes.c_int, [vp, vp, i32, vp, i32, ctypes.POINTER(masw_model),
+                                                             ctypes.c_int, u32, vp, vp, vp, vp, vp]),
             "masw_dispersion_batch_misfit": (ctypes.c_int, [vp, vp, i32, ctypes.POINTER(masw_batch), ctypes.c_int,
                                                             u32, vp, ctypes.POINTER(masw_outputs), vp, vp]),
             "masw_dispersion_batch": (ctypes.c_int, [vp, vp, i32, ctypes.POINTER(masw_batch),
@@ -271,6 +274,19 @@ def masw_dispersion_curve(ctx, c_test, lam, h, alpha, beta, rho, prec: int, flag
         ctypes.byref(m), prec, fl, _stream(stream, fl & MASW_DEVICE_PTRS),
         _ptr(C_t, np.float64), _ptr(idx, np.int32), _ptr(status, np.int32), _ptr(c_ref, np.float64)),
         "masw_dispersion_curve")
+
+
+def masw_dispersion_curve_noalloc(ctx, c_test, lam, h, alpha, beta, rho, prec: int, flags: int,
+                                  stream, C_t, idx, status, c_ref=None) -> int:
+    """Marshals to the C function of the same name (see include/masw.h):
+    device tensors only, the workspace in the library's static scratch."""
+    fl = flags | _device_flag(c_test, lam, h, alpha, beta, rho, C_t, idx, status, c_ref)
+    m = _model_struct(h, alpha, beta, rho)
+    return _check(library().masw_dispersion_curve_noalloc(
+        ctx, _ptr(c_test, np.float64), int(c_test.shape[0]), _ptr(lam, np.float64), int(lam.shape[0]),
+        ctypes.byref(m), prec, fl, _stream(stream, fl & MASW_DEVICE_PTRS),
+        _ptr(C_t, np.float64), _ptr(idx, np.int32), _ptr(status, np.int32), _ptr(c_ref, np.float64)),
+        "masw_dispersion_curve_noalloc")
 
 
 def _batch_structs(layer_off, h, alpha, beta, rho, lambda_off, lam, C_t, idx, status, c_ref):

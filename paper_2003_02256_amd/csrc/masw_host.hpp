@@ -64,6 +64,12 @@ hipError_t launch_noise_check(const ModelDesc* models, const LayerRec64* layers6
                               const double* lam_k, const int32_t* lam_model, const int32_t* idx,
                               int32_t* status, int64_t n_lam, double threshold, hipStream_t s);
 
+// The no-alloc entry point's static scratch array (masw_kernels.hip): looks
+// up its address on `device`, which must be current, once; then returns it
+// (nullptr before the lookup).
+hipError_t setup_scratch(int device);
+void* scratch_of(int device);
+
 // Records `msg` as the calling thread's last error and returns `code`.
 int fail(int code, const std::string& msg);
 

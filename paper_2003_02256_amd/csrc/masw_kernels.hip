@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include "masw_inertia.hpp"
@@ -1275,6 +1276,33 @@ __global__ __launch_bounds__(256) void sign_map_kernel(SignMapArgs a) {
     }
   }
   a.sigma[o] = int8_t(sg);
+}
+
+// ------------------------------------------------------- no-alloc scratch --
+// Workspace of masw_dispersion_curve_noalloc: one static array per device
+// (each device that loads the library holds its own copy until the process
+// ends).  Host code never uses the array's name as an address: masw_create
+// looks up each device's copy once, with that device current, and the entry
+// point hands the kernels that address in their argument structs.
+constexpr int kMaxScratchDevices = 64;
+static __device__ __align__(256) unsigned char scratch[MASW_NOALLOC_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static void* g_scratch[kMaxScratchDevices] = {};
+
+hipError_t setup_scratch(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch[device]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e == hipSuccess) g_scratch[device] = p;
+  return e;
+}
+
+void* scratch_of(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch[device];
 }
 
 // --------------------------------------------------------- host launchers --

@@ -466,6 +466,8 @@ int masw_create(int device, size_t hbm_budget_bytes, masw_ctx** out) {
     return fail(code, msg);
   };
   if (hipSetDevice(device) != hipSuccess) return cleanup(MASW_EDEVICE, "hipSetDevice failed");
+  if (setup_scratch(device) != hipSuccess)
+    return cleanup(MASW_EDEVICE, "cannot look up the no-alloc scratch array on this device");
   if (hipDeviceGetAttribute(&ctx->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
     return cleanup(MASW_EDEVICE, "cannot query compute units");
   for (auto& t : ctx->tslot)
@@ -554,6 +556,42 @@ int masw_dispersion_curve(masw_ctx* ctx, const double* c_test, int32_t n_c, cons
   in.n_lam = n_lambda;
   masw_outputs o{C_t, idx, status, c_ref};
   return run_curves(ctx, in, prec, flags, stream, &o, Workspace{ctx->arena, ctx->sync_size, false});
+}
+
+int masw_dispersion_curve_noalloc(masw_ctx* ctx, const double* c_test, int32_t n_c, const double* lambda,
+                                  int32_t n_lambda, const masw_model* model, masw_precision prec, uint32_t flags,
+                                  void* stream, double* C_t, int32_t* idx, int32_t* status, double* c_ref) {
+  TraceRange trace("masw_dispersion_curve_noalloc");
+  int rc;
+  if (!(flags & MASW_DEVICE_PTRS)) return fail(MASW_EINVAL, "flags: MASW_DEVICE_PTRS is required");
+  if (!model) return fail(MASW_EINVAL, "model: null pointer");
+  if ((rc = check_grid(c_test, n_c, false))) return rc;
+  if ((rc = check_lambda(lambda, n_lambda, false))) return rc;
+  if (model->n_layers < 0 || model->n_layers > MASW_MAX_LAYERS)
+    return fail(MASW_EINVAL, "model: n_layers out of range [0, MASW_MAX_LAYERS]");
+  if ((model->n_layers > 0 && !model->h) || !model->alpha || !model->beta || !model->rho)
+    return fail(MASW_EINVAL, "model: null model array");
+  if (n_lambda > 0 && (!C_t || !idx || !status)) return fail(MASW_EINVAL, "outputs: C_t, idx, status required");
+  if ((rc = check_common(ctx, prec, flags))) return rc;
+  void* sp = scratch_of(ctx->device);
+  if (!sp) return fail(MASW_EDEVICE, "the no-alloc scratch array is not set up on this device");
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  Inputs in;
+  in.n_models = 1;
+  in.single_N = model->n_layers;
+  in.single_W = n_lambda;
+  in.h = model->h;
+  in.alpha = model->alpha;
+  in.beta = model->beta;
+  in.rho = model->rho;
+  in.lambda = lambda;
+  in.c = c_test;
+  in.n_c = n_c;
+  in.n_layers_total = model->n_layers;
+  in.n_lam = n_lambda;
+  masw_outputs o{C_t, idx, status, c_ref};
+  return run_curves(ctx, in, prec, flags, stream, &o,
+                    Workspace{static_cast<char*>(sp), size_t(MASW_NOALLOC_SCRATCH_BYTES), true});
 }
 
 // Shared body of masw_dispersion_batch and masw_dispersion_batch_misfit

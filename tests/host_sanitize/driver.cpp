@@ -32,6 +32,11 @@ hipError_t launch_classify(const ClassifyArgs&, hipStream_t) { return reached("c
 hipError_t launch_serve_noise(const ServeNoiseList&, const int32_t*, int32_t*, double, hipStream_t) {
   return reached("serve noise");
 }
+hipError_t setup_scratch(int) { return reached("scratch set-up"); }
+void* scratch_of(int) {
+  reached("scratch address");
+  return nullptr;
+}
 hipError_t launch_noise_check(const ModelDesc*, const LayerRec64*, const double*, const double*, const int32_t*,
                               const int32_t*, int32_t*, int64_t, double, hipStream_t) {
   return reached("noise");
@@ -91,6 +96,16 @@ int main() {
                                nullptr, ct.data(), idx.data(), st.data(), cref.data()), E, "null context");
   expect(masw_dispersion_curve(nullptr, c.data(), 801, lam.data(), 30, &m, MASW_PREC_SPLIT, MASW_SEARCH_INERTIA,
                                nullptr, ct.data(), idx.data(), st.data(), cref.data()), E, "inertia with split");
+  expect(masw_dispersion_curve_noalloc(nullptr, c.data(), 801, lam.data(), 30, &m, MASW_PREC_FP64, 0, nullptr,
+                                       ct.data(), idx.data(), st.data(), cref.data()), E, "noalloc host pointers");
+  expect(masw_dispersion_curve_noalloc(nullptr, c.data(), 1, lam.data(), 30, &m, MASW_PREC_FP64, MASW_DEVICE_PTRS,
+                                       nullptr, ct.data(), idx.data(), st.data(), cref.data()), E, "noalloc short grid");
+  expect(masw_dispersion_curve_noalloc(nullptr, c.data(), 801, lam.data(), 30, &big, MASW_PREC_FP64,
+                                       MASW_DEVICE_PTRS, nullptr, ct.data(), idx.data(), st.data(), cref.data()), E,
+         "noalloc too many layers");
+  expect(masw_dispersion_curve_noalloc(nullptr, c.data(), 801, lam.data(), 30, &m, MASW_PREC_FP64,
+                                       MASW_DEVICE_PTRS, nullptr, ct.data(), idx.data(), st.data(), cref.data()), E,
+         "noalloc null context");
 
   // batch: offsets
   const int32_t loff[3] = {0, 2, 4}, woff_bad[3] = {0, 30, 20};

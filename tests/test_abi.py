@@ -222,3 +222,29 @@ def test_opts_validate_on_host(lib):
         assert e.value.code == M.MASW_EINVAL and msg in str(e.value), (kwargs, str(e.value))
     out = M.masw_opts()
     assert lib.masw_get_opts(None, ctypes.byref(out)) == M.MASW_EINVAL
+
+
+def test_noalloc_entry_point_validates_on_host(lib):
+    # the no-alloc variant takes device pointers only, and checks sizes and
+    # flags before it looks at the context
+    c, lam, m = _good()
+    W = lam.shape[0]
+    out = (np.empty(W), np.empty(W, np.int32), np.empty(W, np.int32), np.empty(W))
+    mod = M._model_struct(m.h, m.alpha, m.beta, m.rho)
+
+    def call(flags, n_c=None, prec=M.MASW_PREC_FP64):
+        rc = lib.masw_dispersion_curve_noalloc(None, M._ptr(c, np.float64), int(c.shape[0] if n_c is None else n_c),
+                                               M._ptr(lam, np.float64), W, ctypes.byref(mod), prec, flags, None,
+                                               *[M._ptr(o, o.dtype.type) for o in out])
+        return rc, M.masw_last_error()
+
+    rc, msg = call(0)
+    assert rc == M.MASW_EINVAL and "MASW_DEVICE_PTRS" in msg
+    rc, msg = call(M.MASW_DEVICE_PTRS, n_c=1)
+    assert rc == M.MASW_EINVAL and "n_c" in msg
+    rc, msg = call(M.MASW_DEVICE_PTRS, prec=5)
+    assert rc == M.MASW_EINVAL and "prec" in msg
+    rc, msg = call(M.MASW_DEVICE_PTRS | 0x40)
+    assert rc == M.MASW_EINVAL and "flags" in msg
+    rc, msg = call(M.MASW_DEVICE_PTRS)
+    assert rc == M.MASW_EINVAL and "ctx" in msg
