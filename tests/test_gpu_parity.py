@@ -694,3 +694,54 @@ def test_fused_misfit_equals_algorithm_2(torch_dev, ctx, prec, flags):
     keep = np.ones(W, bool)
     keep[lam_off[5]:lam_off[6]] = False
     np.testing.assert_array_equal(hout[1][keep], got[1][keep])
+
+
+def check_refined_root(lam, c_lo, c_hi, model, got_ref, want_ref, what):
+    """The refined root in [c_lo, c_hi]: with one sign change of the oracle's
+    determinant in the step, within REL_TOL of the oracle's root; with
+    several (poles and zeros closer than the grid, reading 10), any of them
+    is a valid refinement, so the device's root must be one of them."""
+    if abs(got_ref - want_ref) <= REL_TOL * want_ref:
+        return
+    k = 2 * math.pi / lam
+    fine = O.det_sign(k, np.linspace(c_lo, c_hi, 2001), model)
+    if np.count_nonzero(fine[1:] != fine[:-1]) <= 1:
+        assert abs(got_ref - want_ref) <= REL_TOL * want_ref, (what, got_ref, want_ref)
+    else:
+        d = 2e-9 * got_ref
+        assert c_lo <= got_ref <= c_hi, what
+        assert O.det_sign(k, got_ref - d, model)[0] != O.det_sign(k, got_ref + d, model)[0], what
+
+
+def test_random_sample_matches_the_oracle(torch_dev, ctx):
+    # 510 wavelengths of the random stress configurations (17 per
+    # configuration, spread over each), against the oracle: the FP64 walk, the
+    # split path and the inertia search, each in a batch of the sampled
+    # models with only the sampled wavelengths.  Index, status and C_t are
+    # compared exactly (no noise-band excuse); the refined root as in
+    # check_refined_root.
+    g = _golden("random_sample.json")
+    by_seed = {}
+    for e in g["cases"]:
+        by_seed.setdefault(e["seed"], []).append(e)
+    n_total = 0
+    for seed, cases in sorted(by_seed.items()):
+        wl = WL.random_stress_config(seed)
+        c = wl.c_test
+        models = [wl.models[e["model"]] for e in cases]
+        lambdas = [np.array([wl.lambdas[e["model"]][e["lambda_index"]]]) for e in cases]
+        for prec, flags, name in ((M.MASW_PREC_FP64, 0, "walk"), (M.MASW_PREC_SPLIT, 0, "split"),
+                                  (M.MASW_PREC_FP64, M.MASW_SEARCH_INERTIA, "inertia")):
+            ct, idx, st, cr = dev_batch(torch_dev, ctx, c, models, lambdas, prec, flags)
+            for k, e in enumerate(cases):
+                what = (seed, e["model"], e["lambda_index"], name)
+                assert (int(idx[k]), int(st[k])) == (e["idx"], e["status"]), (what, idx[k], st[k])
+                i = e["idx"]
+                if i < 1:
+                    assert math.isnan(ct[k]) and math.isnan(cr[k])
+                    continue
+                assert ct[k] == c[i]
+                check_refined_root(float(lambdas[k][0]), float(c[i - 1]), float(c[i]), models[k], float(cr[k]),
+                                   float(e["c_ref"]), what)
+                n_total += 1
+    print(f"random sample: {n_total} (wavelength, path) pairs equal to the oracle", flush=True)
