@@ -104,7 +104,7 @@ DEFAULT_STEPS = {"fine_scale": (200, 50), "two_layer": (200, 50), "batch": (5, 1
 KERNEL_SOURCES = ["masw_internal.hpp", "masw_math.hpp", "masw_special.hpp", "masw_pick.hpp", "masw_kernels.hip"]
 CLASSIFY_SOURCES = ["masw_classify.hip"]
 INERTIA_SOURCES = ["masw_internal.hpp", "masw_math.hpp", "masw_special.hpp", "masw_pick.hpp", "masw_inertia.hpp",
-                   "masw_inertia.hip"]
+                   "masw_inertia_kernel.hpp", "masw_inertia.hip", "masw_inertia_lone.hip"]
 
 
 def kernel_source_hash(files=KERNEL_SOURCES) -> str:
@@ -149,6 +149,7 @@ class DeviceJob:
         self.c = torch.as_tensor(wl.c_test, device=dev)
         self.W = int(arrs[-1].shape[0])
         self.single = len(wl.models) == 1
+        self.prepared = {}
         f64, i32 = torch.float64, torch.int32
         self.out = {p: (torch.empty(self.W, dtype=f64, device=dev), torch.empty(self.W, dtype=i32, device=dev),
                         torch.empty(self.W, dtype=i32, device=dev), torch.empty(self.W, dtype=f64, device=dev))
@@ -157,12 +158,18 @@ class DeviceJob:
         self.lam_model = np.repeat(np.arange(len(wl.models)), [len(l) for l in wl.lambdas])
 
     def run(self, ctx, prec):
-        """prec: a precision, or "inertia" for the FP64 inertia-count search."""
+        """prec: a precision, or "inertia" for the FP64 inertia-count search.
+        A single curve goes through a PreparedCurve (arguments marshalled
+        once), so that a small job's time is not the binding's."""
         M, a = self.M, self.arrs
         flags = M.MASW_SEARCH_INERTIA if prec == "inertia" else 0
         p = M.MASW_PREC_FP64 if prec == "inertia" else prec
         if self.single:
-            M.masw_dispersion_curve(ctx, self.c, a[6], a[1], a[2], a[3], a[4], p, flags, None, *self.out[prec])
+            key = (ctx.value, prec)
+            if key not in self.prepared:
+                self.prepared[key] = M.PreparedCurve(ctx, self.c, a[6], a[1], a[2], a[3], a[4], p, flags, None,
+                                                     *self.out[prec])
+            self.prepared[key]()
         else:
             M.masw_dispersion_batch(ctx, self.c, *a, p, flags, None, *self.out[prec])
 
@@ -203,16 +210,22 @@ def serving_trace(rate: float, warm_s: float, dur_s: float, seed: int = 55):
     return times, reqs
 
 
+SPIN_NS = 1_000_000  # the load generator spins for the last 1 ms before each arrival
+
+
 def run_serving(M, ctx, prec, times, reqs, c, warm_s: float, search_inertia: int = 0):
     """Replay the trace against the serving loop: a submitter thread at the
-    arrival times, a collector waiting on tickets in order.  Latency = the
-    library's completion timestamp - the scheduled arrival (CLOCK_MONOTONIC).
-    search_inertia: FP64 requests take the inertia-count search."""
+    arrival times; the results are collected after the last submission (the
+    library stamps each completion itself, and a collector thread running
+    meanwhile would compete with the submitter for the interpreter lock).
+    Latency = the library's completion timestamp - the scheduled arrival
+    (CLOCK_MONOTONIC); submit_lag_us says how late the submitter reached
+    masw_submit.  search_inertia: FP64 requests take the inertia-count
+    search."""
     import threading
     n = len(times)
     tickets = [None] * n
     sched = [0] * n
-    ready = threading.Semaphore(0)
     M.masw_server_start(ctx, search_inertia=search_inertia)
     # the submitter must keep to the arrival times: no collector pauses
     # during the replay (latency counts from the scheduled arrival)
@@ -221,32 +234,39 @@ def run_serving(M, ctx, prec, times, reqs, c, warm_s: float, search_inertia: int
     gc.disable()
     t0 = time.monotonic_ns() + 50_000_000
 
+    lag = [0] * n
+
     def submitter():
+        # sleep to within SPIN_NS of the arrival, then spin: time.sleep alone
+        # wakes tens to hundreds of microseconds late (timer slack), which
+        # would count as latency of the server
         for i in range(n):
             at = t0 + int(times[i] * 1e9)
-            dt = (at - time.monotonic_ns()) / 1e9
+            dt = (at - SPIN_NS - time.monotonic_ns()) / 1e9
             if dt > 0:
                 time.sleep(dt)
+            while time.monotonic_ns() < at:
+                pass
             h, a, b, r, lam, _ = reqs[i]
             sched[i] = at
+            lag[i] = time.monotonic_ns() - at
             tickets[i] = M.masw_submit(ctx, c, lam, h, a, b, r, prec)
-            ready.release()
 
     results = [None] * n
     th = threading.Thread(target=submitter)
     th.start()
+    th.join()
     for i in range(n):
-        ready.acquire()
         W = len(reqs[i][4])
         out = (np.empty(W), np.empty(W, np.int32), np.empty(W, np.int32), np.empty(W))
         info = M.masw_wait(ctx, tickets[i], -1, *out)
         results[i] = (info, out[1])
-    th.join()
     gc.enable()
     stats = M.masw_server_get_stats(ctx)
     M.masw_server_stop(ctx)
     meas = [i for i in range(n) if times[i] >= warm_s]
     lat = np.array([(results[i][0]["done_ns"] - sched[i]) / 1e6 for i in meas])
+    sub_lag = np.array([lag[i] / 1e3 for i in meas])
     t_first = min(sched[i] for i in meas)
     t_last = max(results[i][0]["done_ns"] for i in meas)
     span = (t_last - t_first) / 1e9
@@ -255,7 +275,9 @@ def run_serving(M, ctx, prec, times, reqs, c, warm_s: float, search_inertia: int
             "mean_ms": float(lat.mean()), "max_ms": float(lat.max()), "curves_per_s": len(meas) / span,
             "det_evals_per_s": useful / span, "useful_evals": useful, "span_s": span,
             "ticks": stats["ticks"], "max_resident": stats["max_resident"], "admit_waits": stats["admit_waits"],
-            "busy_frac": stats["busy_ms"] / (span * 1e3)}, [r[1] for r in results]
+            "busy_frac": stats["busy_ms"] / (span * 1e3),
+            "submit_lag_us": {"p50": float(np.percentile(sub_lag, 50)), "p99": float(np.percentile(sub_lag, 99)),
+                              "max": float(sub_lag.max())}}, [r[1] for r in results]
 
 
 def serving_bench(M, torch, a):
@@ -309,16 +331,15 @@ def uniform_bench(M, torch, a):
             args = [t64(c), t64(lam), t64(m.h), t64(m.alpha), t64(m.beta), t64(m.rho)]
             out = (torch.empty(L, dtype=torch.float64, device=dev), torch.empty(L, dtype=torch.int32, device=dev),
                    torch.empty(L, dtype=torch.int32, device=dev), torch.empty(L, dtype=torch.float64, device=dev))
+            out2 = tuple(torch.empty_like(o) for o in out)
             sig = torch.empty(L * c.shape[0], dtype=torch.int8, device=dev)
 
-            def curve():
-                M.masw_dispersion_curve(ctx, *args, M.MASW_PREC_FP64, 0, None, *out)
-
-            def smap():
-                M.masw_sign_map(ctx, *args, M.MASW_PREC_FP64, 0, None, sig)
+            curve = M.PreparedCurve(ctx, *args, M.MASW_PREC_FP64, 0, None, *out)
+            pick_only = M.PreparedCurve(ctx, *args, M.MASW_PREC_FP64, M.MASW_NO_REFINE, None, *out2)
+            smap = M.PreparedSignMap(ctx, *args, M.MASW_PREC_FP64, 0, None, sig)
 
             res = {}
-            for name, fn in (("early_exit", curve), ("sign_map", smap)):
+            for name, fn in (("early_exit", curve), ("early_exit_no_refine", pick_only), ("sign_map", smap)):
                 for _ in range(a.warmup):
                     fn()
                 torch.cuda.synchronize()
@@ -332,6 +353,7 @@ def uniform_bench(M, torch, a):
             tot_useful += useful
             tot_s += res["early_exit"] * 1e-3
             rows.append({"c_pick": c_pick, "length": L, "idx": int(idx[0]), "early_exit_ms": res["early_exit"],
+                         "early_exit_no_refine_ms": res["early_exit_no_refine"],
                          "sign_map_ms": res["sign_map"], "useful_evals": useful,
                          "grid_evals": L * int(c.shape[0])})
     ctx_obj.close()
@@ -562,6 +584,11 @@ def inertia_leg(wl, r64, r_i, wall64, wall_i, sweep_i, st_i, n_lay, n_curves):
     flops = (inertia_flops(st_i["inertia_evals"], st_i["inertia_entries"], st_i["inertia_pivots"])
              + det_evals * flops_per_eval(nbar))
     achieved = flops / (sweep_i * 1e-3) / 1e12
+    # the library runs the variant for at most one wavefront per SIMD when the
+    # wavelengths, four per workgroup (one per SIMD), need no more workgroups
+    # than there are CUs
+    lone = st_i["workgroups"] <= st_i["cus"]
+    kname = "inertia_lone_kernel" if lone else "inertia_kernel"
     return {
         "value": wl.n_lambda_total / wall_i, "unit": "wavelengths/s",
         "ms_per_step": wall_i * 1e3, "dtype": "f64", "speedup_vs_fp64_walk": wall64 / wall_i,
@@ -576,8 +603,8 @@ def inertia_leg(wl, r64, r_i, wall64, wall_i, sweep_i, st_i, n_lay, n_curves):
         "kernel_ms": sweep_i,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS,
-                     "traffic": MEASURED_TRAFFIC.get((kernel_source_hash(INERTIA_SOURCES), wl.name, "inertia_kernel")),
-                     "kernel": "inertia_kernel",
+                     "traffic": MEASURED_TRAFFIC.get((kernel_source_hash(INERTIA_SOURCES), wl.name, kname)),
+                     "kernel": kname,
                      "kernel_ms": sweep_i, "flops_per_launch": flops},
     }
 
@@ -608,7 +635,9 @@ def measure_curves(M, torch, wl, steps: int, warmup: int, inertia: bool = True) 
     if inertia:
         log(f"{wl.name}: timing the inertia-count search")
         wall_i, sweep_i, total_i, st_i = time_path(job, ctx, "inertia", steps, warmup)
+        st_i["cus"] = torch.cuda.get_device_properties(0).multi_processor_count
         r_i = job.results("inertia")
+    graph = graph_replay(M, torch, job, ctx, steps, warmup, r64) if job.single and wl.n_lambda_total <= 1024 else None
     ctx_obj.close()
 
     idx64, idx32 = r64[1], r32[1]
@@ -661,26 +690,65 @@ def measure_curves(M, torch, wl, steps: int, warmup: int, inertia: bool = True) 
     }
     if inertia:
         res["inertia"] = inertia_leg(wl, r64, r_i, wall64, wall_i, sweep_i, st_i, n_lay, n_curves)
+    if graph:
+        res["graph"] = graph
     return res
+
+
+def graph_replay(M, torch, job, ctx, steps: int, warmup: int, r64) -> dict:
+    """A small job as one captured hipGraph: the FP64 curve call without
+    allocation (masw_dispersion_curve_noalloc: staging and sweep, two kernel
+    nodes) captured once on a side stream and replayed back to back.  Every
+    output of the last replay must equal the eager FP64 call's."""
+    a = job.arrs
+    W = job.W
+    out = (torch.empty(W, dtype=torch.float64, device="cuda:0"), torch.empty(W, dtype=torch.int32, device="cuda:0"),
+           torch.empty(W, dtype=torch.int32, device="cuda:0"), torch.empty(W, dtype=torch.float64, device="cuda:0"))
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    call = M.PreparedCurve(ctx, job.c, a[6], a[1], a[2], a[3], a[4], M.MASW_PREC_FP64, 0, side.cuda_stream, *out,
+                           noalloc=True)
+    with torch.cuda.stream(side):
+        call()                      # eager once on the side stream
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        call()
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.replay()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    same = all(np.array_equal(o.cpu().numpy(), x, equal_nan=True) for o, x in zip(out, r64))
+    return {"ms_per_step": wall * 1e3, "entry": "masw_dispersion_curve_noalloc replayed as a captured hipGraph",
+            "outputs_equal_eager_fp64": bool(same)}
 
 
 def serving_leg(M, torch, seconds: float) -> dict:
     """A short replay of the serving trace (2000 req/s Poisson arrivals from
     64 random-walk chains, 1 s warm-up): p50/p99 latency and curves/s of the
-    split path and of the plain-FP64 server on the identical trace."""
+    split path, of the plain-FP64 server and of the FP64 server with the
+    inertia-count search, on the identical trace."""
     import workloads as WL
     c = WL.serving_grid()
     warm = 1.0
     times, reqs = serving_trace(2000.0, warm, seconds)
-    log(f"serving leg: {len(times)} requests over {warm + seconds:.0f} s, split then FP64")
+    log(f"serving leg: {len(times)} requests over {warm + seconds:.0f} s, split, FP64, FP64 inertia search")
     ctx_obj = M.Context(0, 4 << 30)
     split, idx_s = run_serving(M, ctx_obj.ctx, M.MASW_PREC_SPLIT, times, reqs, c, warm)
     fp64, idx_d = run_serving(M, ctx_obj.ctx, M.MASW_PREC_FP64, times, reqs, c, warm)
+    inertia, idx_i = run_serving(M, ctx_obj.ctx, M.MASW_PREC_FP64, times, reqs, c, warm, search_inertia=1)
     ctx_obj.close()
-    keep = ("requests", "p50_ms", "p99_ms", "mean_ms", "max_ms", "curves_per_s", "det_evals_per_s", "busy_frac")
+    keep = ("requests", "p50_ms", "p99_ms", "mean_ms", "max_ms", "curves_per_s", "det_evals_per_s", "busy_frac",
+            "submit_lag_us")
     return {"workload": "serving_64chains_2000rps", "seconds": seconds, "n_c": int(c.shape[0]),
             "split": {k: split[k] for k in keep}, "fp64": {k: fp64[k] for k in keep},
-            "idx_mismatch_split_vs_fp64": sum(int(np.sum(x != y)) for x, y in zip(idx_s, idx_d))}
+            "fp64_inertia": {k: inertia[k] for k in keep},
+            "idx_mismatch_split_vs_fp64": sum(int(np.sum(x != y)) for x, y in zip(idx_s, idx_d)),
+            "idx_mismatch_inertia_vs_fp64": sum(int(np.sum(x != y)) for x, y in zip(idx_i, idx_d))}
 
 
 def _oracle_curve_points(args):

@@ -334,6 +334,10 @@ typedef struct {
                                 inertia-count search (as MASW_SEARCH_INERTIA),
                                 each within one tick: the tick's wavefronts
                                 sample det K's sign, one wavefront finishes;
+                                where the search falls back to walking (grid
+                                points at or above the half-space's S
+                                velocity), the walk proceeds rounds_per_tick
+                                rounds per tick like a walking request's;
                                 0: they walk.  Split requests always walk.
                                 Other values: MASW_EINVAL                       */
     int32_t reserved;        /* must be 0                                         */

@@ -453,6 +453,49 @@ def flatten_models(models, lambdas):
             cat([np.asarray(l, np.float64) for l in lambdas]))
 
 
+class PreparedCurve:
+    """masw_dispersion_curve (or, with noalloc=True,
+    masw_dispersion_curve_noalloc) with its arguments marshalled once, for
+    calls repeated on the same buffers (device tensors, or host arrays): each
+    call() is the bare C call.  The caller keeps the buffers alive and
+    unmoved while the object is used."""
+
+    def __init__(self, ctx, c_test, lam, h, alpha, beta, rho, prec: int, flags: int, stream,
+                 C_t, idx, status, c_ref=None, noalloc: bool = False):
+        fl = flags | _device_flag(c_test, lam, h, alpha, beta, rho, C_t, idx, status, c_ref)
+        self._model = _model_struct(h, alpha, beta, rho)   # kept alive: the C call reads it
+        self._keep = (c_test, lam, h, alpha, beta, rho, C_t, idx, status, c_ref)
+        lib = library()
+        self._fn = lib.masw_dispersion_curve_noalloc if noalloc else lib.masw_dispersion_curve
+        self._name = "masw_dispersion_curve_noalloc" if noalloc else "masw_dispersion_curve"
+        self._args = (ctx, _ptr(c_test, np.float64), int(c_test.shape[0]), _ptr(lam, np.float64),
+                      int(lam.shape[0]), ctypes.byref(self._model), prec, fl,
+                      _stream(stream, fl & MASW_DEVICE_PTRS), _ptr(C_t, np.float64), _ptr(idx, np.int32),
+                      _ptr(status, np.int32), _ptr(c_ref, np.float64))
+
+    def __call__(self) -> int:
+        rc = self._fn(*self._args)
+        return rc if rc == MASW_OK else _check(rc, self._name)
+
+
+class PreparedSignMap:
+    """masw_sign_map with its arguments marshalled once (see PreparedCurve)."""
+
+    def __init__(self, ctx, c_test, lam, h, alpha, beta, rho, prec: int, flags: int, stream, sigma,
+                 log_abs_det=None):
+        fl = flags | _device_flag(c_test, lam, h, alpha, beta, rho, sigma, log_abs_det)
+        self._model = _model_struct(h, alpha, beta, rho)
+        self._keep = (c_test, lam, h, alpha, beta, rho, sigma, log_abs_det)
+        self._fn = library().masw_sign_map
+        self._args = (ctx, _ptr(c_test, np.float64), int(c_test.shape[0]), _ptr(lam, np.float64),
+                      int(lam.shape[0]), ctypes.byref(self._model), prec, fl,
+                      _stream(stream, fl & MASW_DEVICE_PTRS), _ptr(sigma, np.int8), _ptr(log_abs_det, np.float64))
+
+    def __call__(self) -> int:
+        rc = self._fn(*self._args)
+        return rc if rc == MASW_OK else _check(rc, "masw_sign_map")
+
+
 class Context:
     """A masw_ctx on one device, with helpers that allocate outputs."""
 

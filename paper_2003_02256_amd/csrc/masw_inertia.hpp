@@ -76,6 +76,10 @@ constexpr double kInvPi = 0.318309886183790671537767526745028724;
 // counts its own points); the rest are uniform across the wavefront.
 struct Tally {
   unsigned long long evals = 0, entries = 0, pivots = 0, scan = 0, check = 0, refine = 0, useful = 0;
+  // handoff: a walk (below) is not run but handed back to the caller as
+  // kResume, with the grid index it would start from and its carried sign
+  bool handoff = false;
+  int resume = 0, resume_carry = 0;
 };
 
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
@@ -121,7 +125,7 @@ __device__ __forceinline__ unsigned layer_poles(double c2, double kh, const Laye
 // E(c) = s(c) + 2 P(c), or kEvent (c at or above the half-space's S velocity,
 // a zero or non-finite pivot, or a layer that would need more than kMaxSub
 // sublayers).  The work is added to t if `tally`.
-__device__ inline int count_E(double c, double k, const LayerRec64* __restrict__ L, int N, Tally& t, bool tally) {
+__device__ __forceinline__ int count_E(double c, double k, const LayerRec64* __restrict__ L, int N, Tally& t, bool tally) {
   const double c2 = c * c;
   const LayerRec<double> hs = load_rec<double>(L, N);
   if (!(c2 * hs.ib2 < 1.0)) return kEvent;
@@ -219,11 +223,18 @@ __device__ __forceinline__ int count_E_split(double c, double k, const LayerRec6
   return ok ? E + 2 * P : kEvent;
 }
 
+constexpr int kResume = -3;  // a walk handed back to the caller (Tally::handoff)
+
 // Algorithm 1's walk from grid index `start`, whose predecessor has sign
 // `carry`, one grid point per lane.  Returns the index of the first change
-// (-1 if none) and its signs.
+// (-1 if none) and its signs, or kResume with t.handoff.
 __device__ inline int walk(const double* c64, int n_c, double k, const LayerRec64* L, int N, int start,
                            int carry, int* sig_f, int* prev_f, Tally& t) {
+  if (t.handoff) {
+    t.resume = start;
+    t.resume_carry = carry;
+    return kResume;
+  }
   const int lane = threadIdx.x & 63;
   for (int base = start; base < n_c; base += 64) {
     const int i = base + lane;

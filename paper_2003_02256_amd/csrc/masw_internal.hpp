@@ -58,7 +58,8 @@ struct alignas(64) Counters {
   uint32_t queue_head;        // next work item
   uint32_t grid_bad;          // nonzero if the c grid failed validation
   uint32_t coop_stall;        // cooperative waits that reached their bound
-  uint32_t pad0[13];
+  uint32_t tick_exit;         // serving: workgroups that have left their tick (never cleared)
+  uint32_t pad0[12];
   unsigned long long useful;  // sum of idx + 1
   unsigned long long sweep;   // sweep evaluations
   unsigned long long check;   // FP64 re-check evaluations
@@ -205,7 +206,9 @@ struct TickDesc {
                                  // exactly n_units + (workgroups) from it
   int32_t active[kMaxSlots];     // slot ids
   int32_t prefix[kMaxSlots + 1]; // prefix sums of W over `active`
-  int32_t pad2[3];
+  uint32_t exit_base;            // Counters::tick_exit at the start of this tick
+  uint32_t seq;                  // this tick's number, written to TickArgs::host_tick at its end
+  int32_t pad2;
   SlotDesc slot[kMaxSlots];
 };
 
@@ -241,6 +244,7 @@ struct TickArgs {
   int32_t* out_status;
   double* out_cref;
   int32_t* host_done;        // [kMaxSlots] set to 1 when a slot's last item finishes
+  uint32_t* host_tick;       // pinned: the number of the last tick whose workgroups have all left
 };
 
 struct SignMapArgs {

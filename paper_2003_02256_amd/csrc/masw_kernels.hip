@@ -110,22 +110,38 @@ __device__ void build_model(const PrepArgs& a, int m, int single_N, int single_W
     }
     ok = __ballot(!lok) == 0ull;
   }
-  if (lane == 0) {
-    // Grid points below the half-space's S velocity: the first c with
-    // c^2 / beta_hs^2 >= 1, in the arithmetic of the inertia count's test
-    // (the grid rises; a grid that does not fails its own checks).
-    int n_real = 0;
-    if (ok) {
-      const double be = a.beta[rec0 + N];
-      const double ib2 = 1.0 / (be * be);
-      int lo = 0, hi = a.n_c;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        const double c = a.c_in[mid];
-        if (c * c * ib2 < 1.0) lo = mid + 1; else hi = mid;
+  // Grid points below the half-space's S velocity: the first c with
+  // c^2 / beta_hs^2 >= 1, in the arithmetic of the inertia count's test (the
+  // grid rises; a grid that does not fails its own checks).  A 64-way search
+  // by the wavefront: each round tests 64 evenly spaced points of [lo, hi),
+  // whose outcomes form a prefix, and keeps the gap after the last point
+  // below; two or three dependent loads for the usual grids instead of a
+  // binary search's ten to fifteen.
+  int n_real = 0;
+  if (ok) {
+    const double be = a.beta[rec0 + N];
+    const double ib2 = 1.0 / (be * be);
+    int lo = 0, hi = a.n_c;  // n_real in [lo, hi]
+    while (lo < hi) {
+      const int step = (hi - lo + 63) / 64;
+      const int i = lo + lane * step;
+      bool below = false;
+      if (i < hi) {
+        const double c = a.c_in[i];
+        below = c * c * ib2 < 1.0;
       }
-      n_real = lo;
+      const int t = __popcll(__ballot(below));
+      if (t == 0) {
+        hi = lo;
+      } else {
+        const int last = lo + (t - 1) * step;
+        hi = min(hi, last + step);
+        lo = last + 1;
+      }
     }
+    n_real = lo;
+  }
+  if (lane == 0) {
     ModelDesc d;
     d.n_layers = ok ? N : 0;
     d.layer_base = rec0;
@@ -229,19 +245,25 @@ __global__ __launch_bounds__(kPrepThreads) void prep_front_kernel(PrepArgs a, Co
 // block (at most kLamBlock wavelengths) also finishes the counting sort in
 // LDS; otherwise the histogram goes to the counters for order_scan_kernel and
 // order_scatter_kernel.
-__global__ __launch_bounds__(kLamBlock) void prep_lambda_kernel(PrepArgs a, int nb_grid) {
-  __shared__ uint32_t s_hist[kBuckets];
-  __shared__ uint32_t s_scan[kBuckets];
-  __shared__ double s_c[kBuckets];
+struct LambdaShared {
+  uint32_t hist[kBuckets];
+  uint32_t scan[kBuckets];
+  double c[kBuckets];
+};
+
+// The wavelength part of the staging for the wavelengths of this block;
+// `bad` is the grid's validity (uniform).  LDS arrays in `ls`.
+__device__ void stage_lambdas(const PrepArgs& a, int bad, LambdaShared& ls) {
+  uint32_t* s_hist = ls.hist;
+  uint32_t* s_scan = ls.scan;
+  double* s_c = ls.c;
   const int t = threadIdx.x;
   const int ns = min(kBuckets, a.n_c);  // grid samples: c at index (s * (n_c - 1)) / (ns - 1)
   for (int i = t; i < kBuckets; i += blockDim.x) {
     s_hist[i] = 0u;
     if (i < ns) s_c[i] = a.c64[ns > 1 ? int((int64_t(i) * (a.n_c - 1)) / (ns - 1)) : 0];
   }
-  int bad = 0;
-  for (int i = t; i < nb_grid; i += blockDim.x) bad |= int(a.grid_flags[i]);
-  bad = __syncthreads_or(bad);
+  __syncthreads();
   if (blockIdx.x == 0 && t == 0) a.counters->grid_bad = bad ? 1u : 0u;
   const int g = blockIdx.x * blockDim.x + t;
   int key = 0;
@@ -306,6 +328,45 @@ __global__ __launch_bounds__(kLamBlock) void prep_lambda_kernel(PrepArgs a, int 
     __syncthreads();
   }
   if (g < a.n_lam) a.order[s_scan[key] - s_hist[key] + rank] = g;
+}
+
+__global__ __launch_bounds__(kLamBlock) void prep_lambda_kernel(PrepArgs a, int nb_grid) {
+  __shared__ LambdaShared ls;
+  int bad = 0;
+  for (int i = threadIdx.x; i < nb_grid; i += blockDim.x) bad |= int(a.grid_flags[i]);
+  bad = __syncthreads_or(bad);
+  stage_lambdas(a, bad, ls);
+}
+
+// The whole staging of a small job in one block (one launch instead of
+// two): grid checks and the FP32 copy, the models' records (one wavefront
+// per model), the counters and shared-sweep state, then the wavelengths.
+// For jobs of at most kLamBlock wavelengths, kSmallModels models and
+// kSmallGrid grid points.
+constexpr int kSmallModels = kLamBlock / 64;
+constexpr int kSmallGrid = 16 * kLamBlock;
+
+__global__ __launch_bounds__(kLamBlock) void prep_small_kernel(PrepArgs a, CoopInitArgs ci, int single_N,
+                                                               int single_W) {
+  __shared__ LambdaShared ls;
+  const int t = threadIdx.x;
+  int bad = 0;
+  for (int i = t; i < a.n_c; i += kLamBlock) {
+    const double c = a.c_in[i];
+    if (a.c64 != a.c_in) a.c64[i] = c;
+    a.c32[i] = float(c);
+    bool ok = (c > 0.0) && (c < __builtin_inf());
+    if (i + 1 < a.n_c) ok = ok && (c < a.c_in[i + 1]);
+    bad |= ok ? 0 : 1;
+  }
+  for (int m = t >> 6; m < a.n_models; m += kLamBlock / 64) build_model(a, m, single_N, single_W);
+  uint32_t* cw = reinterpret_cast<uint32_t*>(a.counters);
+  for (int i = t; i < int(sizeof(Counters) / sizeof(uint32_t)); i += kLamBlock) cw[i] = 0u;
+  for (int i = t; i < ci.n_coop; i += kLamBlock) ci.coop[i] = CoopItem{0, 0x7fffffff, 0, 0};
+  for (uint64_t i = t; i < ci.n_sum; i += kLamBlock) ci.coop_sum[i] = 0ull;
+  for (int i = t; i < ci.n_active; i += kLamBlock) ci.coop_active[i] = -1;
+  bad = __syncthreads_or(bad);  // also: records, grid copy and counters are written
+  stage_lambdas(a, bad, ls);
 }
 
 // Exclusive prefix sum of the histogram, in place (one block of kBuckets).
@@ -972,11 +1033,21 @@ void sweep_kernel(SweepArgs a) {
   __shared__ double s_mis[MISFIT ? 256 : 1];  // fused misfit reduction
   WorkCount wc;
   constexpr int P = 64 * G;
-  for (;;) {
-    if (threadIdx.x == 0) sh.item = (int)atomicAdd(&a.counters->queue_head, 1u);
-    __syncthreads();
-    const int it = uniform(sh.item);
-    __syncthreads();
+  // Queue positions below gridDim.x (the launch has at most one workgroup
+  // per item) are taken by workgroup index, the rest from the atomic queue:
+  // a launch with no more items than workgroups makes no claim at all.
+  for (int claim = 0;; ++claim) {
+    int it = int(blockIdx.x);
+    if (claim > 0) {
+      if (int(gridDim.x) >= a.n_items) break;
+      if (threadIdx.x == 0) {
+        const uint32_t q = gridDim.x + atomicAdd(&a.counters->queue_head, 1u);
+        sh.item = q >= uint32_t(a.n_items) ? a.n_items : int(q);
+      }
+      __syncthreads();
+      it = uniform(sh.item);
+      __syncthreads();
+    }
     if (it >= a.n_items) break;
 
     int g, m;
@@ -1080,64 +1151,94 @@ __global__ __launch_bounds__(kAdmitChunk) void admit_kernel(const AdmitList* __r
   if (threadIdx.x == 0) slot_remaining[list->slot[b]] = W;
 }
 
-// One serving tick: every unfinished item of every active request advances by
-// at most desc->budget sweep rounds (then its re-check and refinement if its
-// change was found).  The last item of a request to finish raises the
-// request's completion flag in pinned host memory.
 // One FP64 item of a serving tick by the inertia-count search: the sampling
 // round of the search on all G wavefronts (64 G grid points: c_test[0] and
 // 64 G - 1 spread points), then the counts, the sign at the change and the
 // refinement on wavefront 0.  The sampled bound leaves a bracket of about
 // n_c / (64 G) grid points, which one round of counts resolves.  The other
-// wavefronts wait at the tick's barrier.  Outputs equal the walk's.
+// wavefronts wait at the barrier.  Where the search would fall back to
+// walking, the item is handed to the walking path instead (all G wavefronts,
+// at most `budget` rounds per tick, resumed in later ticks), so that no item
+// holds a tick for a long walk.  Returns true once the outputs are written;
+// they equal the walk's.
 template <int G>
-__device__ void inertia_tick_item(const ItemRef& r, SweepShared<G>& sh, WorkCount& wc, const ItemOut& o) {
-  constexpr int P = 64 * G;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int n = r.n_c - 1;
-  bool va = true;
-  const int pa = (tid == 0) ? 0 : inertia::spread(0, n, tid, 1, &va, P);
-  if (tid == 0) va = true;
-  const int sa = va ? det_sign<double, false>(r.c64[pa], r.k64, r.L64, r.N, nullptr) : kNoSign;
-  if (tid == 0) sh.check[0] = sa;
-  __syncthreads();
-  const int sig0 = sh.check[0];
-  const unsigned long long m = __ballot(tid > 0 && va && sa != sig0);
-  if (lane == 0) sh.first[wave] = m ? wave * 64 + (__ffsll((long long)m) - 1) : P;
-  __syncthreads();
-  if (wave != 0) return;
-  int f = P;
+__device__ bool inertia_tick_item(const ItemRef& r, ItemState& st, int budget, SweepShared<G>& sh, WorkCount& wc,
+                                  const ItemOut& o, Counters* cnt) {
+  if (!st.fp64) {
+    constexpr int P = 64 * G;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n = r.n_c - 1;
+    bool va = true;
+    const int pa = (tid == 0) ? 0 : inertia::spread(0, n, tid, 1, &va, P);
+    if (tid == 0) va = true;
+    const int sa = va ? det_sign<double, false>(r.c64[pa], r.k64, r.L64, r.N, nullptr) : kNoSign;
+    if (tid == 0) sh.check[0] = sa;
+    __syncthreads();
+    const int sig0 = sh.check[0];
+    const unsigned long long m = __ballot(tid > 0 && va && sa != sig0);
+    if (lane == 0) sh.first[wave] = m ? wave * 64 + (__ffsll((long long)m) - 1) : P;
+    __syncthreads();
+    if (wave == 0) {
+      int f = P;
 #pragma unroll
-  for (int w = 0; w < G; ++w) f = min(f, sh.first[w]);
-  inertia::Tally t;
-  t.check = (unsigned long long)min(P, r.n_c);
-  int sig_f = 0, prev_f = 0, found;
-  if (sig0 != 1 && sig0 != -1) {
-    found = inertia::walk(r.c64, r.n_c, r.k64, r.L64, r.N, 1, sig0, &sig_f, &prev_f, t);
-  } else if (f == P) {
-    // no sampled sign differs: the one-wavefront search from the start
-    found = inertia::search(r.c64, r.n_c, r.k64, r.L64, r.N, -1, &sig_f, &prev_f, t);
-  } else {
-    bool v;
-    const int pf = inertia::spread(0, n, f, 1, &v, P);
-    const int pb = (f == 1) ? 0 : inertia::spread(0, n, f - 1, 1, &v, P);
-    inertia::Bracket br;
-    found = inertia::from_sampled_bound(r.c64, r.n_c, r.k64, r.L64, r.N, 0, false, 0, sig0, pb, pf, &br, &sig_f,
-                                        &prev_f, t);
-    if (found == inertia::kLocated)
-      found = inertia::finish(r.c64, r.n_c, r.k64, r.L64, r.N, sig0, br, &sig_f, &prev_f, t);
+      for (int w = 0; w < G; ++w) f = min(f, sh.first[w]);
+      inertia::Tally t;
+      t.handoff = true;  // a walk continues below, G wavefronts wide and within the tick's budget
+      t.check = (unsigned long long)min(P, r.n_c);
+      int sig_f = 0, prev_f = 0, found;
+      if (sig0 != 1 && sig0 != -1) {
+        found = inertia::walk(r.c64, r.n_c, r.k64, r.L64, r.N, 1, sig0, &sig_f, &prev_f, t);
+      } else if (f == P) {
+        // no sampled sign differs: the one-wavefront search from the start
+        found = inertia::search(r.c64, r.n_c, r.k64, r.L64, r.N, -1, &sig_f, &prev_f, t);
+      } else {
+        bool v;
+        const int pf = inertia::spread(0, n, f, 1, &v, P);
+        const int pb = (f == 1) ? 0 : inertia::spread(0, n, f - 1, 1, &v, P);
+        inertia::Bracket br;
+        found = inertia::from_sampled_bound(r.c64, r.n_c, r.k64, r.L64, r.N, 0, false, 0, sig0, pb, pf, &br,
+                                            &sig_f, &prev_f, t);
+        if (found == inertia::kLocated)
+          found = inertia::finish(r.c64, r.n_c, r.k64, r.L64, r.N, sig0, br, &sig_f, &prev_f, t);
+      }
+      wc.sweep += t.scan;
+      wc.check += t.check;
+      if (found == inertia::kResume) {
+        if (lane == 0) {
+          sh.check[1] = t.resume;
+          sh.check[2] = t.resume_carry;
+        }
+      } else {
+        if (found < 0) {
+          write_no_pick(o, MASW_STATUS_NOT_FOUND, lane == 0);
+          wc.useful += (unsigned long long)r.n_c;
+        } else {
+          wc.useful += (unsigned long long)(found + 1);
+          wc.refine += refine_and_write(o, r.c64, r.k64, r.L64, r.N, found, sig_f, prev_f);
+        }
+        if (lane == 0) sh.check[1] = -1;
+      }
+    }
+    __syncthreads();
+    const int resume = sh.check[1], carry = sh.check[2];
+    __syncthreads();
+    if (resume < 0) {
+      st.done = 1;
+      return true;
+    }
+    // the search handed back a walk (after an unusable count, or a first
+    // sign that is not +-1): the walking path takes the item from there
+    st.start = resume;
+    st.carry = carry;
+    st.fp64 = 1;
   }
-  wc.sweep += t.scan;
-  wc.check += t.check;
-  if (found < 0) {
-    write_no_pick(o, MASW_STATUS_NOT_FOUND, lane == 0);
-    wc.useful += (unsigned long long)r.n_c;
-  } else {
-    wc.useful += (unsigned long long)(found + 1);
-    wc.refine += refine_and_write(o, r.c64, r.k64, r.L64, r.N, found, sig_f, prev_f);
-  }
+  return run_item<kModeFP64, G>(r, st, budget, sh, wc, o, kNoCoop, cnt);
 }
 
+// One serving tick: every unfinished item of every active request advances by
+// at most desc->budget sweep rounds (then its re-check and refinement if its
+// change was found).  The last item of a request to finish raises the
+// request's completion flag in pinned host memory.
 // With G = 8 the kernel is held to 128 VGPRs (4 wavefronts per SIMD), so two
 // workgroups fit on a CU, as for the batch sweep.  INERTIA (a server started
 // with search_inertia) runs FP64 items with the inertia-count search instead
@@ -1190,9 +1291,7 @@ void tick_kernel(TickArgs a) {
     } else if (sd.prec == MASW_PREC_SPLIT) {
       done = run_item<kModeSplit, G>(r, st, budget, sh, wc, o, kNoCoop, a.counters);
     } else if (INERTIA) {
-      inertia_tick_item<G>(r, sh, wc, o);  // the whole search in this tick
-      st.done = 1;
-      done = true;
+      done = inertia_tick_item<G>(r, st, budget, sh, wc, o, a.counters);
     } else {
       done = run_item<kModeFP64, G>(r, st, budget, sh, wc, o, kNoCoop, a.counters);
     }
@@ -1206,6 +1305,17 @@ void tick_kernel(TickArgs a) {
     __syncthreads();  // wavefront 0's outputs are written before the next item is fetched
   }
   flush_counts<G>(a.counters, wc);
+  // The last workgroup to leave tells the host, through pinned memory, that
+  // the tick is over: the host waits on this word instead of the stream.
+  // Every workgroup's outputs are released (system scope) before its count.
+  if (threadIdx.x == 0) {
+    __threadfence_system();
+    const uint32_t left = atomicAdd(&a.counters->tick_exit, 1u) + 1u - D->exit_base;
+    if (left == gridDim.x) {
+      __threadfence_system();
+      __hip_atomic_store(a.host_tick, D->seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+  }
 }
 
 // -------------------------------------------------------------- misfit --
@@ -1339,6 +1449,11 @@ hipError_t launch_sweep(int mode, int G, int blocks, hipStream_t s, const SweepA
 }
 
 hipError_t launch_prep(const PrepArgs& a, const CoopInitArgs& ci, int single_N, int single_W, hipStream_t s) {
+  const uint64_t n_clear_small = std::max<uint64_t>(ci.n_sum, uint64_t(std::max(ci.n_coop, ci.n_active)));
+  if (a.n_lam <= kLamBlock && a.n_models <= kSmallModels && a.n_c <= kSmallGrid && n_clear_small <= kSmallGrid) {
+    hipLaunchKernelGGL(prep_small_kernel, dim3(1), dim3(kLamBlock), 0, s, a, ci, single_N, single_W);
+    return hipGetLastError();
+  }
   const int nb_grid = (a.n_c + kPrepThreads - 1) / kPrepThreads;
   const int nb_models = (a.n_models + kPrepThreads / 64 - 1) / (kPrepThreads / 64);
   const uint64_t n_clear = std::max<uint64_t>(ci.n_sum, uint64_t(std::max(ci.n_coop, ci.n_active)));

@@ -14,18 +14,23 @@
 // magnitude overflows FP64 beyond a few tens of layers).
 //
 // Entries are divided by k mu_ref (mu_ref = the half-space's rho beta^2), and
-// every hyperbolic function of a layer is multiplied by
-// E = exp(-t Re sqrt(x)) (t = k h); both are positive factors that cancel in
-// f * numerator / denominator, so every entry is computed with no overflow at
-// any k h, and the result is real for every real c below the half-space's S
-// velocity.  With q = sqrt(|x|) for x = r^2 = 1 - c^2/alpha^2 or
-// x = s^2 = 1 - c^2/beta^2:
-//     x > 0:  E = exp(-t q),  a = E (cosh tq - 1),  Sh = E sinh(tq)/q,  R = E q sinh(tq)
-//     x < 0:  E = 1,          a = cos tq - 1,       Sh = sin(tq)/q,      R = -q sin(tq)
-//     x = 0:  E = 1,          a = 0,                Sh = t,              R = 0
-// (the last row is the removable 0/0 at c = alpha or c = beta).  a and Sh are
-// formed from expm1 or from the half-angle sin/cos so that the long-wavelength
-// cancellation 1 - cosh cosh is never computed as a difference of O(1) terms.
+// the hyperbolic functions of a potential with large t Re sqrt(x) (t = k h)
+// are multiplied by E = exp(-t Re sqrt(x)); both are positive factors that
+// cancel in f * numerator / denominator, so every entry is computed with no
+// overflow at any k h, and the result is real for every real c below the
+// half-space's S velocity.  With q = sqrt(|x|) for x = r^2 = 1 - c^2/alpha^2
+// or x = s^2 = 1 - c^2/beta^2, and z = t^2 x:
+//     |z| <= 1:  E = 1,          a = cosh(tq) - 1 = z ch(z),   Sh = t shc(z),       R = x Sh
+//     z > 1:     E = exp(-t q),  a = E (cosh tq - 1),          Sh = E sinh(tq)/q,   R = E q sinh(tq)
+//     z < -1:    E = 1,          a = cos tq - 1,               Sh = sin(tq)/q,      R = -q sin(tq)
+// where ch and shc are the entire functions (cosh sqrt(z) - 1)/z and
+// sinh(sqrt z)/sqrt(z) (cos and sin for z < 0; masw_special.hpp).  The first
+// row covers c = alpha or c = beta (x = 0, the removable 0/0: a = 0, Sh = t,
+// R = 0) and about two thirds of the layer evaluations of the workloads, with
+// one polynomial pair and no square root, exponential or range reduction.
+// a and Sh are formed from that series, from expm1 or from the half-angle
+// sin/cos, so that the long-wavelength cancellation 1 - cosh cosh is never
+// computed as a difference of O(1) terms.
 // Divisions are reciprocals refined to about 1 ulp (masw_special.hpp): only the
 // sign of the determinant is used, and a last-bit difference in a quotient is
 // far below the rounding of the elimination itself.
@@ -47,27 +52,26 @@ __device__ __forceinline__ float sqrt_(float x) {
   return __builtin_sqrtf(x);
 }
 
-// The four E-scaled functions of one potential (see the file comment).  One
-// reciprocal square root gives both q and 1/q; the half-angle form
+// The four functions of one potential (see the file comment).  For |z| > 1
+// one reciprocal square root gives both q and 1/q, and the half-angle form
 // cos(tq) - 1 = -2 sin^2(tq/2), sin(tq) = 2 sin(tq/2) cos(tq/2) keeps the
-// small-angle end exact.
+// trigonometric side accurate where tq is near a multiple of 2 pi.
 template <typename T>
 struct Terms {
   T E, a, Sh, R;
 };
 
 template <typename T>
-__device__ __forceinline__ Terms<T> potential_terms(T x, T t) {
+__device__ __forceinline__ Terms<T> potential_terms(T x, T t, T t2) {
   Terms<T> o;
-  if (x > T(0)) {
-    const T iq = special::rsqrt(x);
-    const T q = x * iq;
-    const T m = special::expm1_neg(t * q);       // E - 1
-    const T half_sh = T(-0.5) * m * (T(2) + m);  // E sinh(tq) = (1 - E^2) / 2
-    o.E = T(1) + m;
-    o.a = T(0.5) * m * m;                        // E cosh - E = (1 - E)^2 / 2
-    o.Sh = half_sh * iq;
-    o.R = half_sh * q;
+  const T z = t2 * x;  // (t q)^2, with the sign of x
+  if (__builtin_fabs(z) <= T(1)) {
+    T ch, shc;
+    special::ch_shc(z, &ch, &shc);
+    o.E = T(1);
+    o.a = z * ch;
+    o.Sh = t * shc;
+    o.R = x * o.Sh;
   } else if (x < T(0)) {
     const T iq = special::rsqrt(-x);
     const T q = -x * iq;
@@ -79,10 +83,14 @@ __device__ __forceinline__ Terms<T> potential_terms(T x, T t) {
     o.Sh = sn * iq;
     o.R = -q * sn;
   } else {
-    o.E = T(1);
-    o.a = T(0);
-    o.Sh = t;
-    o.R = T(0);
+    const T iq = special::rsqrt(x);
+    const T q = x * iq;
+    const T m = special::expm1_neg(t * q);       // E - 1
+    const T half_sh = T(-0.5) * m * (T(2) + m);  // E sinh(tq) = (1 - E^2) / 2
+    o.E = T(1) + m;
+    o.a = T(0.5) * m * m;                        // E cosh - E = (1 - E)^2 / 2
+    o.Sh = half_sh * iq;
+    o.R = half_sh * q;
   }
   return o;
 }
@@ -102,8 +110,9 @@ template <typename T>
 __device__ __forceinline__ LayerK<T> layer_entries(T c2, T t, T ia2, T ib2, T rh, T mh) {
   const T xr = T(1) - c2 * ia2;  // r^2
   const T xs = T(1) - c2 * ib2;  // s^2
-  const Terms<T> P = potential_terms(xr, t);
-  const Terms<T> S = potential_terms(xs, t);
+  const T t2 = t * t;
+  const Terms<T> P = potential_terms(xr, t, t2);
+  const Terms<T> S = potential_terms(xs, t, t2);
   const T Cr = P.E + P.a;        // E_r cosh(t r)
   const T Cs = S.E + S.a;
   const T u = P.E * S.a + P.a * S.E + P.a * S.a;  // E_r E_s (C_r C_s - 1)
@@ -157,12 +166,29 @@ __device__ __forceinline__ T schur_layer(Block2<T>& S, const LayerK<T>& K) {
 //     h12 = mh ((1 - s^2)/(1 - r s) - 2),
 // where r and s are taken on the principal branch from their real squares
 // (x < 0 gives +i sqrt(-x)).  H is complex only above the half-space's S
-// velocity.  With a_out, *a_out receives Re of the (1,1) entry of S_N.
+// velocity; below it a real-only form is taken (no complex products, r and s
+// from the refined reciprocal square root).  With a_out, *a_out receives Re
+// of the (1,1) entry of S_N.
 template <typename T>
 __device__ __forceinline__ void halfspace_det(const Block2<T>& S, T c2, T ia2, T ib2, T mh,
                                               T* re, T* im, T* a_out = nullptr) {
   const T xr = T(1) - c2 * ia2;
   const T xs = T(1) - c2 * ib2;
+  if (xs > T(0)) {
+    // Below the half-space's S velocity (then also below its P velocity):
+    // r, s and H are real, and so is det S_N.  The choice is per lane, so a
+    // grid point's value does not depend on the wavefront that evaluates it.
+    const T qr = xr * special::rsqrt(xr);
+    const T qs = xs * special::rsqrt(xs);
+    const T mz = mh * (c2 * ib2) * special::rcp(T(1) - qr * qs);  // mh (1 - s^2) / (1 - r s)
+    const T ar = S.s11 + mz * qr;
+    const T br = S.s22 + mz * qs;
+    const T er = S.s12 + (mz - T(2) * mh);
+    *re = ar * br - er * er;
+    *im = T(0);
+    if (a_out) *a_out = ar;
+    return;
+  }
   const T qr = sqrt_<T>(xr < T(0) ? -xr : xr);  // may be exactly 0 (c = alpha)
   const T qs = sqrt_<T>(xs < T(0) ? -xs : xs);
   const T rr = xr >= T(0) ? qr : T(0), ri = xr >= T(0) ? T(0) : qr;

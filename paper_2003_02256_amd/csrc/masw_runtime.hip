@@ -74,6 +74,7 @@ int masw::check_lambda(const double* lam, int32_t n, bool values) {
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr int64_t kMinSharedRounds = 4;  // shared sweeps only on grids of more rounds than this
 
 // Every synchronous call reuses the front of the arena.  A call on a stream
 // other than the previous call's first waits for that stream, so the previous
@@ -320,10 +321,13 @@ int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t fl
 
   // Shared sweeps when items are few enough that the deepest ones decide the
   // launch time: every item, with one summary word per round of its grid,
-  // if that fits in what is left of the budget.
+  // if that fits in what is left of the budget.  Not on grids of a few
+  // rounds, where a joining workgroup could take at most one round and the
+  // claims and summaries only add latency.
   CoopInitArgs ci{};
   const int64_t stride = (int64_t(in.n_c) + 64 * G - 1) / (64 * G);
-  if (!inertia && ctx->shared_sweeps && blocks > 1 && in.n_lam > 0 && in.n_lam <= 4 * int64_t(blocks)) {
+  if (!inertia && ctx->shared_sweeps && blocks > 1 && in.n_lam > 0 && in.n_lam <= 4 * int64_t(blocks) &&
+      stride > kMinSharedRounds) {
     const size_t save = b.off;
     ci.n_coop = int32_t(in.n_lam);
     ci.coop = b.take<CoopItem>(size_t(ci.n_coop));
@@ -470,11 +474,16 @@ int masw_create(int device, size_t hbm_budget_bytes, masw_ctx** out) {
     return cleanup(MASW_EDEVICE, "cannot look up the no-alloc scratch array on this device");
   if (hipDeviceGetAttribute(&ctx->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
     return cleanup(MASW_EDEVICE, "cannot query compute units");
+  // The timing events only time launches (outputs reach the host through
+  // their own copies and synchronisations): a device-scope release spares
+  // each of them a system-scope cache writeback between the kernels.
   for (auto& t : ctx->tslot)
     for (auto& e : t.ev)
-      if (hipEventCreate(&e) != hipSuccess) return cleanup(MASW_EDEVICE, "hipEventCreate failed");
+      if (hipEventCreateWithFlags(&e, hipEventReleaseToDevice) != hipSuccess)
+        return cleanup(MASW_EDEVICE, "hipEventCreate failed");
   for (auto& e : ctx->cls_ev)
-    if (hipEventCreate(&e) != hipSuccess) return cleanup(MASW_EDEVICE, "hipEventCreate failed");
+    if (hipEventCreateWithFlags(&e, hipEventReleaseToDevice) != hipSuccess)
+      return cleanup(MASW_EDEVICE, "hipEventCreate failed");
   if (hipMalloc(&ctx->arena, budget) != hipSuccess) return cleanup(MASW_ENOMEM, "cannot allocate the HBM budget");
   ctx->arena_size = budget;
   ctx->sync_size = budget;

@@ -22,6 +22,7 @@
 #include <time.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -152,6 +153,7 @@ struct Server {
   int32_t* out_idx = nullptr;
   int32_t* out_status = nullptr;
   int32_t* host_done = nullptr;
+  uint32_t* host_tick = nullptr;    // the kernel's end-of-tick word (TickArgs::host_tick)
   int32_t* out_idx_dev = nullptr;   // device views of out_idx, out_status
   int32_t* out_status_dev = nullptr;
   double noise_threshold = 1e-2;    // MASW_CHECK_NOISE band of served requests
@@ -164,6 +166,8 @@ struct Server {
   int bpc[4] = {};
   int blocks[4] = {};
   uint32_t queue_base = 0;  // value of the tick queue counter at the next tick
+  uint32_t exit_base = 0;   // value of Counters::tick_exit at the next tick
+  uint32_t tick_seq = 0;    // number of the last tick launched
   // host state
   std::mutex mu;
   std::condition_variable cv_work, cv_done, cv_watch;
@@ -172,6 +176,7 @@ struct Server {
   bool stop = false;
   bool stop_watch = false;
   bool failed = false;
+  std::atomic<bool> failed_flag{false};  // `failed`, readable without mu (the tick wait)
   std::string fail_msg;
   std::deque<Request*> pending;
   std::unordered_map<uint64_t, std::unique_ptr<Request>> requests;
@@ -191,6 +196,7 @@ struct Server {
 
 void Server::fail_all(const std::string& msg) {
   failed = true;
+  failed_flag.store(true, std::memory_order_release);
   fail_msg = msg;
   for (auto& kv : requests) kv.second->done = true;
   cv_done.notify_all();
@@ -292,6 +298,8 @@ void Server::run() {
     desc_host->n_units = units;
     desc_host->budget = opt.rounds_per_tick;
     desc_host->base = queue_base;
+    desc_host->exit_base = exit_base;
+    desc_host->seq = ++tick_seq;
     const int gi = units > 0 ? pick_graph(units) : 0;
     stats.resident = uint32_t(resident);
     stats.max_resident = std::max(stats.max_resident, uint32_t(resident));
@@ -307,8 +315,20 @@ void Server::run() {
     if (e == hipSuccess && units > 0) {
       e = hipGraphLaunch(exec[gi], stream);
       queue_base += uint32_t(units) + uint32_t(blocks[gi]);  // one final claim per workgroup
+      exit_base += uint32_t(blocks[gi]);
     }
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e == hipSuccess && units > 0) {
+      // the tick kernel's last workgroup writes the tick's number to pinned
+      // memory; spinning on it returns sooner than a stream synchronisation.
+      // The watchdog ends the wait by failing the server.
+      while (__atomic_load_n(host_tick, __ATOMIC_ACQUIRE) != tick_seq &&
+             !failed_flag.load(std::memory_order_acquire))
+        __builtin_ia32_pause();
+      const hipError_t q = hipStreamQuery(stream);  // an error of the tick's work, if any
+      if (q != hipSuccess && q != hipErrorNotReady) e = q;
+    } else if (e == hipSuccess) {
+      e = hipStreamSynchronize(stream);
+    }
     if (e == hipSuccess) e = check_noise_of_finished();
     roctxRangePop();
     const uint64_t t1 = now_ns();
@@ -379,7 +399,7 @@ void Server::release_all() {
   if (stream) (void)hipStreamDestroy(stream);
   for (void* p : {static_cast<void*>(desc_host), static_cast<void*>(out_ct),
                   static_cast<void*>(out_cref), static_cast<void*>(out_idx), static_cast<void*>(out_status),
-                  static_cast<void*>(host_done), static_cast<void*>(staging)})
+                  static_cast<void*>(host_done), static_cast<void*>(host_tick), static_cast<void*>(staging)})
     if (p) (void)hipHostFree(p);
 }
 
@@ -470,12 +490,14 @@ int masw_server_start(masw_ctx* ctx, const masw_server_opts* opts) {
       hipHostMalloc(reinterpret_cast<void**>(&s->out_idx), sizeof(int32_t) * n_out, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&s->out_status), sizeof(int32_t) * n_out, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&s->host_done), sizeof(int32_t) * kMaxSlots, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&s->host_tick), sizeof(uint32_t), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&s->staging), s->staging_size, hipHostMallocDefault) != hipSuccess)
     return bail("hipHostMalloc failed for the serving buffers");
   std::memset(s->desc_host, 0, sizeof(TickDesc));
   s->admit_host = reinterpret_cast<AdmitList*>(s->staging);
   std::memset(s->admit_host, 0, sizeof(AdmitList));
   std::memset(s->host_done, 0, sizeof(int32_t) * kMaxSlots);
+  *s->host_tick = 0;
   if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess)
     return bail("hipStreamCreate failed");
   // the tick counters start at zero once; ticks never clear them (TickDesc::base)
@@ -504,6 +526,8 @@ int masw_server_start(masw_ctx* ctx, const masw_server_opts* opts) {
   s->out_status_dev = ta.out_status;
   if (hipHostGetDevicePointer(&dp, s->host_done, 0) != hipSuccess) return bail("hipHostGetDevicePointer failed");
   ta.host_done = static_cast<int32_t*>(dp);
+  if (hipHostGetDevicePointer(&dp, s->host_tick, 0) != hipSuccess) return bail("hipHostGetDevicePointer failed");
+  ta.host_tick = static_cast<uint32_t*>(dp);
   for (int gi = 0; gi < 4; ++gi) {
     const int G = 1 << gi;
     s->bpc[gi] = tick_blocks_per_cu(G, o.search_inertia != 0);
@@ -527,6 +551,8 @@ int masw_server_start(masw_ctx* ctx, const masw_server_opts* opts) {
     if (hipGraphLaunch(s->exec[gi], s->stream) != hipSuccess || hipStreamSynchronize(s->stream) != hipSuccess)
       return bail("warming the tick graphs failed");
     s->queue_base += uint32_t(s->blocks[gi]);
+    s->exit_base += uint32_t(s->blocks[gi]);
+    s->desc_host->exit_base = s->exit_base;
   }
   s->stats.pool_bytes = s->pool_size;
   ctx->sync_size = (ctx->arena_size - region) & ~(kAlign - 1);

@@ -9,7 +9,7 @@
 
 namespace {
 
-enum { kExpm1Neg = 0, kSin2Sincos = 1, kRcp = 2, kRsqrt = 3, kRcpSeed = 4, kRsqrtSeed = 5 };
+enum { kExpm1Neg = 0, kSin2Sincos = 1, kRcp = 2, kRsqrt = 3, kRcpSeed = 4, kRsqrtSeed = 5, kChShc = 6 };
 
 template <typename T>
 __global__ void probe_kernel(int kind, const double* __restrict__ x, double* __restrict__ y0,
@@ -25,6 +25,11 @@ __global__ void probe_kernel(int kind, const double* __restrict__ x, double* __r
     masw::special::sin2_sincos(v, &s2, &sc);
     a = double(s2);
     b = double(sc);
+  } else if (kind == kChShc) {
+    T ch, shc;
+    masw::special::ch_shc(v, &ch, &shc);
+    a = double(ch);
+    b = double(shc);
   } else if (kind == kRcp) {
     a = double(masw::special::rcp(v));
   } else if (kind == kRsqrt) {
@@ -41,8 +46,9 @@ __global__ void probe_kernel(int kind, const double* __restrict__ x, double* __r
 }  // namespace
 
 // Host arrays in and out: x[n] -> y0[n], y1[n] (y1 is sin x cos x for
-// kind 1, else 0; kinds 4 and 5 are the raw hardware reciprocal and
-// reciprocal square root estimates).  fp32 != 0 evaluates the FP32 variant on float(x).
+// kind 1, sinh(sqrt x)/sqrt(x) for kind 6 (y0: (cosh sqrt(x) - 1)/x), else 0;
+// kinds 4 and 5 are the raw hardware reciprocal and reciprocal square root
+// estimates).  fp32 != 0 evaluates the FP32 variant on float(x).
 // Returns 0 or a hipError_t code.
 extern "C" int probe_special(int fp32, int kind, const double* x, double* y0, double* y1, int n) {
   if (n <= 0) return 0;

@@ -745,3 +745,38 @@ def test_random_sample_matches_the_oracle(torch_dev, ctx):
                                    float(e["c_ref"]), what)
                 n_total += 1
     print(f"random sample: {n_total} (wavelength, path) pairs equal to the oracle", flush=True)
+
+
+def test_noalloc_call_replays_in_a_captured_graph(torch_dev, ctx):
+    # The no-alloc curve call captured once in a hipGraph (its staging and
+    # sweep kernels, no allocation, no memset node) and replayed several
+    # times, with other eager library work and synchronisations in between:
+    # every replay's outputs equal the eager call's, for two precisions.
+    torch, dev = torch_dev
+    wl = WL.two_layer_case()
+    other = WL.fine_scale_case()
+    m, lam, c = wl.models[0], wl.lambdas[0], wl.c_test
+    t = lambda x: torch.as_tensor(np.ascontiguousarray(x, np.float64), device=dev)
+    args = [t(c), t(lam), t(m.h), t(m.alpha), t(m.beta), t(m.rho)]
+    W = len(lam)
+    for prec in (M.MASW_PREC_FP64, M.MASW_PREC_SPLIT):
+        want = dev_curve(torch_dev, ctx, c, lam, m, prec)
+        out = (torch.empty(W, dtype=torch.float64, device=dev), torch.empty(W, dtype=torch.int32, device=dev),
+               torch.empty(W, dtype=torch.int32, device=dev), torch.empty(W, dtype=torch.float64, device=dev))
+        side = torch.cuda.Stream()
+        call = M.PreparedCurve(ctx.ctx, *args, prec, 0, side.cuda_stream, *out, noalloc=True)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=side):
+            call()
+        for rep in range(4):
+            for o in out:
+                o.fill_(-3)
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            got = [o.cpu().numpy() for o in out]
+            for x, y, what in zip(want, got, ("C_t", "idx", "status", "c_ref")):
+                np.testing.assert_array_equal(y, x, err_msg=f"replay {rep} prec {prec}: {what}")
+            # eager work between replays: another curve through the arena
+            dev_curve(torch_dev, ctx, other.c_test, other.lambdas[0][:50], other.models[0], M.MASW_PREC_FP64)

@@ -18,7 +18,9 @@ for FP32):
 * sin^2 x and sin x cos x: error <= 4u |ref| + 2u (FP64) and 8u |ref| + 4u
   (FP32), i.e. relative where the value is of order one or small like x^2 or
   x near 0, absolute near the other zeros, whose position the rounded
-  argument itself only fixes to about u x.
+  argument itself only fixes to about u x;
+* (cosh sqrt(z) - 1)/z and sinh(sqrt z)/sqrt(z) for |z| <= 1 (cos and sin
+  for z < 0): relative error <= 4u (FP64) / 8u (FP32).
 """
 import ctypes
 import os
@@ -109,6 +111,44 @@ def test_sin2_sincos(probe, fp32):
     if np.any(sel):
         _report(f"sin^2 small x fp32={fp32}", np.abs(s2[sel] - want_s2[sel]) / want_s2[sel], k_rel * u)
         _report(f"sin cos small x fp32={fp32}", np.abs(sc[sel] - want_sc[sel]) / want_sc[sel], k_rel * u)
+
+
+def _ch(v):
+    # (cosh sqrt(v) - 1)/v = sum_n v^n/(2n+2)!, summed at 40 digits (the
+    # closed form cancels completely for tiny |v|)
+    v = mpmath.mpf(v)
+    return mpmath.fsum(v ** n / mpmath.factorial(2 * n + 2) for n in range(30))
+
+
+def _shc(v):
+    # sinh(sqrt v)/sqrt(v) = sum_n v^n/(2n+1)!
+    v = mpmath.mpf(v)
+    return mpmath.fsum(v ** n / mpmath.factorial(2 * n + 1) for n in range(30))
+
+
+@pytest.mark.parametrize("fp32", [0, 1])
+def test_cosh_sinh_series(probe, fp32):
+    """(cosh sqrt(z) - 1)/z and sinh(sqrt z)/sqrt(z) on |z| <= 1, both signs:
+    relative error <= 4u (FP64) / 8u (FP32); both lie in [0.45, 1.2] there."""
+    rng = np.random.default_rng(14)
+    tiny = 10.0 ** rng.uniform(-30 if fp32 else -300, 0, 1000)
+    z = np.concatenate([[0.0, 1.0, -1.0], rng.uniform(-1, 1, 4000), tiny, -tiny,
+                        1.0 - 10.0 ** rng.uniform(-16, -1, 200), -1.0 + 10.0 ** rng.uniform(-16, -1, 200)])
+    if fp32:
+        z = z.astype(np.float32).astype(np.float64)
+    z = z[np.abs(z) <= 1.0]
+    ch, shc = probe(fp32, 6, z)
+    # the series against the closed forms where those do not cancel
+    mpmath.mp.dps = 40
+    for v in (1.0, -1.0, 0.5, -0.5):
+        r = mpmath.sqrt(abs(mpmath.mpf(v)))
+        assert abs(_ch(v) - ((mpmath.cosh(r) if v > 0 else mpmath.cos(r)) - 1) / v) < 1e-35
+        assert abs(_shc(v) - (mpmath.sinh(r) if v > 0 else mpmath.sin(r)) / r) < 1e-35
+    u = U32 if fp32 else U64
+    k = 8 if fp32 else 4
+    want_ch, want_shc = _ref(_ch, z), _ref(_shc, z)
+    _report(f"ch fp32={fp32}", np.abs(ch - want_ch) / want_ch, k * u)
+    _report(f"shc fp32={fp32}", np.abs(shc - want_shc) / want_shc, k * u)
 
 
 @pytest.mark.parametrize("fp32", [0, 1])
