@@ -101,7 +101,8 @@ MEASURED_TRAFFIC = {
 DEFAULT_STEPS = {"fine_scale": (200, 50), "two_layer": (200, 50), "batch": (5, 1), "uniform": (20, 3),
                  "chains": (100, 3), "classify": (5, 2)}
 
-KERNEL_SOURCES = ["masw_internal.hpp", "masw_math.hpp", "masw_special.hpp", "masw_pick.hpp", "masw_kernels.hip"]
+KERNEL_SOURCES = ["masw_internal.hpp", "masw_math.hpp", "masw_special.hpp", "masw_pick.hpp", "masw_sweep.hpp",
+                  "masw_kernels.hip", "masw_sweep_split.hip"]
 CLASSIFY_SOURCES = ["masw_classify.hip"]
 INERTIA_SOURCES = ["masw_internal.hpp", "masw_math.hpp", "masw_special.hpp", "masw_pick.hpp", "masw_inertia.hpp",
                    "masw_inertia_kernel.hpp", "masw_inertia.hip", "masw_inertia_lone.hip"]

@@ -19,9 +19,9 @@ PROBE_SRC = os.path.join(ROOT, "tests", "special_probe.hip")
 PROBE_LIB = os.path.join(ROOT, "tests", "libspecial_probe.so")
 
 SOURCES = ["masw_kernels.hip", "masw_runtime.hip", "masw_server.hip", "masw_classify.hip", "masw_noise.hip", "masw_inertia.hip",
-           "masw_inertia_lone.hip"]
+           "masw_inertia_lone.hip", "masw_sweep_split.hip"]
 HEADERS = ["masw_internal.hpp", "masw_math.hpp", "masw_special.hpp", "masw_host.hpp", "masw_pick.hpp", "masw_inertia.hpp",
-           "masw_inertia_kernel.hpp", "masw_noise.hpp"]
+           "masw_inertia_kernel.hpp", "masw_noise.hpp", "masw_sweep.hpp"]
 
 # Packed FP32 instructions stay disabled; the compiler would otherwise form
 # v_pk_* from ordinary float code.

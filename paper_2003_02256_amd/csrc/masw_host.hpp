@@ -94,6 +94,9 @@ struct masw_ctx {
   int device = -1;
   hipStream_t last_stream = nullptr;  // stream of the last synchronous call (may be the null stream)
   bool last_valid = false;
+  // per-workgroup work counts of the last timed sweep or inertia launch
+  unsigned long long* wg_counts = nullptr;
+  int wg_rows = 0;
   char* arena = nullptr;
   size_t arena_size = 0;          // whole HBM budget
   size_t sync_size = 0;           // front part used by the synchronous calls

@@ -112,13 +112,19 @@ void MASW_INERTIA_KERNEL(SweepArgs a, int chunk) {
     s_cnt[wave][6] = t.useful;
   }
   __syncthreads();
-  if (threadIdx.x < 7) {
+  if (threadIdx.x < 8) {  // this workgroup's row of a.wg_counts (see SweepArgs)
     unsigned long long sum = 0;
-    for (int w = 0; w < kInertiaWaves; ++w) sum += s_cnt[w][threadIdx.x];
-    Counters* c = a.counters;
-    unsigned long long* dst[7] = {&c->inertia_evals, &c->inertia_entries, &c->inertia_pivots, &c->sweep,
-                                  &c->check,         &c->refine,          &c->useful};
-    if (sum) atomicAdd(dst[threadIdx.x], sum);
+    if (threadIdx.x < 7)
+      for (int w = 0; w < kInertiaWaves; ++w) sum += s_cnt[w][threadIdx.x];
+    constexpr int kCol[8] = {5, 6, 7, 0, 1, 2, 3, 4};  // s_cnt order to the row's
+    if (a.wg_counts) {
+      a.wg_counts[size_t(blockIdx.x) * kWgCounts + kCol[threadIdx.x]] = sum;
+    } else if (sum) {
+      Counters* c = a.counters;
+      unsigned long long* dst[8] = {&c->inertia_evals, &c->inertia_entries, &c->inertia_pivots, &c->sweep,
+                                    &c->check,         &c->refine,          &c->useful,          &c->helper};
+      atomicAdd(dst[threadIdx.x], sum);
+    }
   }
 }
 

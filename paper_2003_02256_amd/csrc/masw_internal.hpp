@@ -120,7 +120,13 @@ struct SweepArgs {
   double* misfit;             // [n_models]
   int32_t* model_left;        // [n_models] wavelengths not finished (set by the staging)
   const int32_t* lambda_off;  // [n_models + 1]
+  // Work counts of each workgroup, [gridDim.x][kWgCounts] (plain stores; the
+  // host sums them for masw_get_stats): one atomic add per workgroup and
+  // counter on a shared cache line serialises at the end of a launch.
+  unsigned long long* wg_counts;
 };
+constexpr int kWgCounts = 8;  // sweep, check, refine, useful, helper, inertia evals, entries, pivots
+constexpr int kMaxWgRows = 65536;  // workgroup rows reserved for wg_counts (above any launch's grid)
 
 // Zero-state of the cooperative arrays (one launch before the sweep).
 struct CoopInitArgs {

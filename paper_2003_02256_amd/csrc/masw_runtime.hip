@@ -122,6 +122,12 @@ struct Inputs {
 size_t grid_blocks(int64_t n_c) { return size_t((n_c + kPrepThreads - 1) / kPrepThreads); }
 
 // Total device bytes of one call's workspace.
+// Rows of per-workgroup work counts a launch may write: one per workgroup,
+// and a launch has at most one workgroup per wavelength.
+size_t wg_rows(const Inputs& in) {
+  return size_t(std::min<int64_t>(std::max<int64_t>(in.n_lam, 1), kMaxWgRows));
+}
+
 size_t workspace_bytes(const Inputs& in, bool stage_inputs, bool stage_outputs) {
   Bump b{nullptr, ~size_t(0), 0};
   const size_t R = size_t(in.n_layers_total + in.n_models);
@@ -154,6 +160,7 @@ size_t workspace_bytes(const Inputs& in, bool stage_inputs, bool stage_outputs) 
       b.take<double>(size_t(in.n_models));
     }
   }
+  b.take<unsigned long long>(wg_rows(in) * kWgCounts);
   return b.off + kAlign;
 }
 
@@ -312,6 +319,7 @@ int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t fl
     }
     p.misfit = misfit_dev;
   }
+  sw.wg_counts = b.take<unsigned long long>(wg_rows(in) * kWgCounts);
   if (!b.ok()) return fail(MASW_ENOMEM, "workspace exceeds the HBM budget");
 
   const bool inertia = (flags & MASW_SEARCH_INERTIA) != 0;
@@ -396,6 +404,8 @@ int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t fl
   ctx->last.n_lambda = uint64_t(in.n_lam);
   ctx->last.waves_per_item = G;
   ctx->last.workgroups = in.n_lam > 0 ? blocks : 0;
+  ctx->wg_counts = sw.wg_counts;
+  ctx->wg_rows = in.n_lam > 0 ? blocks : 0;
   ctx->last.shared_items = ci.n_coop;
   ctx->stats_pending = true;
   ctx->cls_pending = false;
@@ -1007,6 +1017,21 @@ int masw_get_stats(masw_ctx* ctx, masw_stats* out) {
     ctx->last.inertia_entries = c.inertia_entries;
     ctx->last.inertia_pivots = c.inertia_pivots;
     ctx->last.shared_stalls = c.coop_stall;
+    if (ctx->wg_rows > 0) {  // the launch's per-workgroup rows (SweepArgs::wg_counts)
+      std::vector<unsigned long long> rows(size_t(ctx->wg_rows) * kWgCounts);
+      MASW_HIP(hipMemcpy(rows.data(), ctx->wg_counts, rows.size() * sizeof(unsigned long long),
+                         hipMemcpyDeviceToHost));
+      unsigned long long sum[kWgCounts] = {};
+      for (size_t i = 0; i < rows.size(); ++i) sum[i % kWgCounts] += rows[i];
+      ctx->last.sweep_evals += sum[0];
+      ctx->last.check_evals += sum[1];
+      ctx->last.refine_evals += sum[2];
+      ctx->last.useful_evals += sum[3];
+      ctx->last.helper_evals += sum[4];
+      ctx->last.inertia_evals += sum[5];
+      ctx->last.inertia_entries += sum[6];
+      ctx->last.inertia_pivots += sum[7];
+    }
     if (ctx->tslot_last >= 0) {
       masw_ctx::TimingSlot& T = ctx->tslot[ctx->tslot_last];
       if (T.pending) MASW_HIP(resolve_timing(ctx, T));
