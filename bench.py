@@ -659,7 +659,8 @@ def measure_curves(M, torch, wl, steps: int, warmup: int, inertia: bool = True) 
     algorithmic32 = st32["useful_evals"] + st32["check_evals"] + st32["refine_evals"]
     achieved32 = algorithmic32 * flops_per_eval(nbar) / (sweep32 * 1e-3) / 1e12
     n_curves = len(wl.models)
-    kname = f"sweep_kernel<FP64,G={st64['waves_per_item']}>"
+    kname = ("fused_sweep_kernel<FP64>" if st64.get("fused_staging")
+             else f"sweep_kernel<FP64,G={st64['waves_per_item']}>")
     traffic = MEASURED_TRAFFIC.get((kernel_source_hash(), wl.name, kname))
     res = {
         "value": useful / wall64, "unit": "det evals/s", "ms_per_step": wall64 * 1e3, "dtype": "f64",
@@ -678,7 +679,8 @@ def measure_curves(M, torch, wl, steps: int, warmup: int, inertia: bool = True) 
             "curves_per_s": n_curves / wall32, "wavelengths_per_s": wl.n_lambda_total / wall32,
             "sweep_evals": st32["sweep_evals"], "check_evals": st32["check_evals"],
             "refine_evals": st32["refine_evals"], "sweep_kernel_ms": sweep32,
-            "kernel": f"sweep_kernel<split,G={st32['waves_per_item']}>",
+            "kernel": ("fused_sweep_kernel<split>" if st32.get("fused_staging")
+                       else f"sweep_kernel<split,G={st32['waves_per_item']}>"),
             "achieved_tflops_fp64_counted": achieved32,
             "idx_mismatch_vs_fp64": int(np.sum((idx64 != idx32))),
             "root_rel_err_vs_fp64_max": float(root_rel.max()) if root_rel.size else None,

@@ -195,6 +195,10 @@ typedef struct {
     uint64_t inertia_evals;   /* inertia counts evaluated                      */
     uint64_t inertia_entries; /* layer and sublayer element matrices formed    */
     uint64_t inertia_pivots;  /* 2x2 block pivots eliminated                   */
+    int32_t fused_staging;    /* 1: a small single-curve launch that staged its
+                                 model, grid and wavelengths inside the sweep
+                                 kernel (one launch; sweep_ms = total_ms)      */
+    int32_t reserved;         /* 0                                             */
 } masw_stats;
 
 /* Options of a context.  A zero field keeps its default, so a

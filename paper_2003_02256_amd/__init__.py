@@ -86,10 +86,11 @@ class masw_stats(ctypes.Structure):
                 ("helper_evals", ctypes.c_uint64), ("classify_evals", ctypes.c_uint64),
                 ("classify_layers", ctypes.c_uint64), ("classify_steps", ctypes.c_uint64),
                 ("inertia_evals", ctypes.c_uint64), ("inertia_entries", ctypes.c_uint64),
-                ("inertia_pivots", ctypes.c_uint64)]
+                ("inertia_pivots", ctypes.c_uint64), ("fused_staging", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
 class masw_opts(ctypes.Structure):

@@ -26,6 +26,9 @@ struct TraceRange {
 int sweep_blocks_per_cu(int mode, int G);
 int tick_blocks_per_cu(int G, bool inertia);
 hipError_t launch_sweep(int mode, int G, int blocks, hipStream_t s, const SweepArgs& a);
+// A fused small launch (SweepArgs::fused): `blocks` workgroups of kFusedG
+// wavefronts, one wavelength each.
+hipError_t launch_fused(int mode, int blocks, hipStream_t s, const SweepArgs& a);
 // The inertia-count search (masw_inertia.hip), one wavefront per wavelength.
 hipError_t launch_inertia(const SweepArgs& a, int cus, hipStream_t s, int* blocks_out);
 hipError_t launch_prep(const PrepArgs& a, const CoopInitArgs& ci, int single_N, int single_W, hipStream_t s);
@@ -97,6 +100,8 @@ struct masw_ctx {
   // per-workgroup work counts of the last timed sweep or inertia launch
   unsigned long long* wg_counts = nullptr;
   int wg_rows = 0;
+  bool last_fused = false;  // the last timed launch staged inside the sweep (SweepArgs::fused)
+  bool fused_small = true;  // small single-curve launches fuse the staging (MASW_FUSED_SMALL=0: never)
   char* arena = nullptr;
   size_t arena_size = 0;          // whole HBM budget
   size_t sync_size = 0;           // front part used by the synchronous calls
@@ -123,6 +128,7 @@ struct masw_ctx {
   struct TimingSlot {
     hipEvent_t ev[3] = {};
     bool pending = false;
+    bool fused = false;  // a fused launch: no staging, no ev[1]
     float sweep_ms = 0.f, total_ms = 0.f;
   };
   static constexpr int kTimingSlots = 64;

@@ -124,7 +124,26 @@ struct SweepArgs {
   // host sums them for masw_get_stats): one atomic add per workgroup and
   // counter on a shared cache line serialises at the end of a launch.
   unsigned long long* wg_counts;
+  // A small single-model launch with the staging folded in (fused != 0, one
+  // item per workgroup, the item of workgroup w is wavelength w): each
+  // workgroup checks the raw model and grid itself, builds the model's layer
+  // records in its LDS and takes k from its wavelength, so no staging launch
+  // runs before the sweep.  Raw device inputs, as masw_model and the curve
+  // call take them; models, layers64/32, c32, lam_k, lam_model and order are
+  // unused.
+  int32_t fused;
+  int32_t fused_N;  // layers of the model (at most kFusedMaxLayers)
+  const double* f_h;
+  const double* f_alpha;
+  const double* f_beta;
+  const double* f_rho;
+  const double* f_lambda;
+  const double* f_c;
+  int32_t f_n_c;
 };
+constexpr int kFusedG = 8;              // wavefronts per workgroup of a fused launch
+constexpr int kFusedMaxLayers = 64;     // layers of a model that a fused launch stages in LDS
+constexpr int kFusedMaxGrid = 16384;    // grid points that each workgroup of a fused launch checks
 constexpr int kWgCounts = 8;  // sweep, check, refine, useful, helper, inertia evals, entries, pivots
 constexpr int kMaxWgRows = 65536;  // workgroup rows reserved for wg_counts (above any launch's grid)
 

@@ -531,8 +531,8 @@ void tick_kernel(TickArgs a) {
     r.k64 = sd.lam_k[j];
     r.c64 = sd.raw + (r.N + 3 * (r.N + 1) + sd.W);
     r.c32 = sd.c32;
-    r.L64 = sd.L64;
-    r.L32 = sd.L32;
+    r.L64 = as_global(sd.L64);
+    r.L32 = as_global(sd.L32);
     const int og = sd.out_base + j;
     const ItemOut o{a.out_ct + og, a.out_idx + og, a.out_status + og, a.out_cref + og,
                     (a.refine && !(sd.flags & MASW_NO_REFINE)) ? 1 : 0, a.refine_rel};
@@ -700,6 +700,14 @@ hipError_t launch_sweep(int mode, int G, int blocks, hipStream_t s, const SweepA
   if (!f) return hipErrorInvalidValue;
   void* args[] = {const_cast<SweepArgs*>(&a)};
   return hipLaunchKernel(f, dim3(blocks), dim3(64 * G), args, 0, s);
+}
+
+hipError_t launch_fused(int mode, int blocks, hipStream_t s, const SweepArgs& a) {
+  const void* f = mode == kModeFP64 ? reinterpret_cast<const void*>(&fused_sweep_kernel<kModeFP64>)
+                                    : split_fused_symbol();
+  if (!f || a.fused_N < 0 || a.fused_N > kFusedMaxLayers) return hipErrorInvalidValue;
+  void* args[] = {const_cast<SweepArgs*>(&a)};
+  return hipLaunchKernel(f, dim3(blocks), dim3(64 * kFusedG), args, unsigned(fused_lds_bytes(a.fused_N)), s);
 }
 
 hipError_t launch_prep(const PrepArgs& a, const CoopInitArgs& ci, int single_N, int single_W, hipStream_t s) {

@@ -212,20 +212,43 @@ __device__ __forceinline__ void halfspace_det(const Block2<T>& S, T c2, T ia2, T
 // Layer records are read-only for a whole launch and uniform across a
 // wavefront; reading them through the constant address space lets the
 // compiler use scalar loads into SGPRs, which VALU instructions take as
-// operands without occupying vector registers.
+// operands without occupying vector registers.  A fused small launch keeps
+// its records in LDS (a workgroup writes them itself): those are read as
+// LDS, since a scalar load of an LDS address would read global memory at a
+// meaningless address.  The compiler knows each pointer's address space
+// after inlining, so the test costs nothing at run time.
 template <typename T>
 using ConstRec = const __attribute__((address_space(4))) LayerRec<T>;
 
+// A pointer read from memory (a serving slot's records) is declared not to
+// point into LDS, so that load_rec's address-space test folds at compile
+// time.
+template <typename T>
+__device__ __forceinline__ const T* as_global(const T* p) {
+  __builtin_assume(!__builtin_amdgcn_is_shared((const __attribute__((address_space(0))) void*)(p)));
+  return p;
+}
+
 template <typename T>
 __device__ __forceinline__ LayerRec<T> load_rec(const LayerRec<T>* L, int j) {
-  ConstRec<T>* p = (ConstRec<T>*)(L) + j;  // address-space cast (generic -> constant)
   LayerRec<T> r;
-  r.ia2 = p->ia2;
-  r.ib2 = p->ib2;
-  r.rh = p->rh;
-  r.mh = p->mh;
-  r.h = p->h;
-  r.aux = p->aux;
+  if (__builtin_amdgcn_is_shared((const __attribute__((address_space(0))) void*)(L))) {
+    const LayerRec<T>& q = L[j];
+    r.ia2 = q.ia2;
+    r.ib2 = q.ib2;
+    r.rh = q.rh;
+    r.mh = q.mh;
+    r.h = q.h;
+    r.aux = q.aux;
+  } else {
+    ConstRec<T>* p = (ConstRec<T>*)(L) + j;  // address-space cast (generic -> constant)
+    r.ia2 = p->ia2;
+    r.ib2 = p->ib2;
+    r.rh = p->rh;
+    r.mh = p->mh;
+    r.h = p->h;
+    r.aux = p->aux;
+  }
   r.zb = r.pad2 = T(0);
   return r;
 }

@@ -93,7 +93,8 @@ __global__ __launch_bounds__(kNoiseThreads) void serve_noise_kernel(ServeNoiseLi
     bool band = false;
     if ((status & 0xFF) == MASW_STATUS_FOUND && i >= 1 && i < d.n_c) {
       const double c = c64[i - 1 + end];
-      if (c * c * d.L64[d.N].ib2 < 1.0) band = in_band(c, d.lam_k[g], d.L64, d.N, threshold);
+      const LayerRec64* L = as_global(d.L64);
+      if (c * c * L[d.N].ib2 < 1.0) band = in_band(c, d.lam_k[g], L, d.N, threshold);
     }
     const int other = __shfl_xor(int(band), 1, 64);
     if (end == 0 && (band || other)) out_status[o] = status | MASW_FLAG_NOISE;

@@ -121,12 +121,13 @@ struct Inputs {
 // Blocks of the grid check, one flag each.
 size_t grid_blocks(int64_t n_c) { return size_t((n_c + kPrepThreads - 1) / kPrepThreads); }
 
-// Total device bytes of one call's workspace.
 // Rows of per-workgroup work counts a launch may write: one per workgroup,
 // and a launch has at most one workgroup per wavelength.
 size_t wg_rows(const Inputs& in) {
   return size_t(std::min<int64_t>(std::max<int64_t>(in.n_lam, 1), kMaxWgRows));
 }
+
+// Total device bytes of one call's workspace.
 
 size_t workspace_bytes(const Inputs& in, bool stage_inputs, bool stage_outputs) {
   Bump b{nullptr, ~size_t(0), 0};
@@ -197,9 +198,10 @@ int pick_waves_per_item(masw_ctx* ctx, int mode, int64_t n_items, int* blocks) {
 // Waits for a timed call's last event and adds its durations to the sums.
 hipError_t resolve_timing(masw_ctx* ctx, masw_ctx::TimingSlot& T) {
   hipError_t e = hipEventSynchronize(T.ev[2]);
-  if (e == hipSuccess) e = hipEventElapsedTime(&T.sweep_ms, T.ev[1], T.ev[2]);
   if (e == hipSuccess) e = hipEventElapsedTime(&T.total_ms, T.ev[0], T.ev[2]);
+  if (e == hipSuccess && !T.fused) e = hipEventElapsedTime(&T.sweep_ms, T.ev[1], T.ev[2]);
   if (e != hipSuccess) return e;
+  if (T.fused) T.sweep_ms = T.total_ms;  // one launch: the sweep with its staging
   T.pending = false;
   masw_timing& t = ctx->timing;
   t.sweep_ms_min = t.launches ? std::min(t.sweep_ms_min, T.sweep_ms) : T.sweep_ms;
@@ -349,15 +351,37 @@ int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t fl
     }
   }
 
+  // A small single-curve launch stages inside the sweep kernel
+  // (SweepArgs::fused): one launch instead of a staging launch and a sweep,
+  // on grids short enough that no shared sweep would run.
+  const bool fused = ctx->fused_small && !inertia && !in.misfit && !(flags & MASW_CHECK_NOISE) && !in.layer_off &&
+                     in.n_models == 1 && in.n_lam > 0 && in.n_lam <= kLamBlock && in.single_N <= kFusedMaxLayers &&
+                     int64_t(in.n_c) <= int64_t(kMinSharedRounds) * 64 * kFusedG &&
+                     (ctx->forced_waves == 0 || ctx->forced_waves == kFusedG);
+  if (fused) {
+    ci = CoopInitArgs{};
+    blocks = int(in.n_lam);
+    sw.fused = 1;
+    sw.fused_N = in.single_N;
+    sw.f_h = p.h;
+    sw.f_alpha = p.alpha;
+    sw.f_beta = p.beta;
+    sw.f_rho = p.rho;
+    sw.f_lambda = p.lambda;
+    sw.f_c = p.c_in;
+    sw.f_n_c = in.n_c;
+  }
+
   masw_ctx::TimingSlot* T = nullptr;
   const int ts = ctx->tslot_next;
   if (!ws.noalloc) {
     T = &ctx->tslot[ts];
     if (T->pending) MASW_HIP(resolve_timing(ctx, *T));
     ctx->tslot_next = (ts + 1) % masw_ctx::kTimingSlots;
+    T->fused = fused;
     MASW_HIP(hipEventRecord(T->ev[0], s));
   }
-  MASW_HIP(launch_prep(p, ci, in.single_N, in.single_W, s));
+  if (!fused) MASW_HIP(launch_prep(p, ci, in.single_N, in.single_W, s));
 
   sw.n_coop = ci.n_coop;
   sw.coop_stride = int32_t(stride);
@@ -387,8 +411,11 @@ int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t fl
     sw.model_left = p.model_left;
     sw.lambda_off = p.lambda_off;
   }
-  if (T) MASW_HIP(hipEventRecord(T->ev[1], s));
-  if (in.n_lam > 0) MASW_HIP(inertia ? launch_inertia(sw, ctx->cus, s, &blocks) : launch_sweep(mode, G, blocks, s, sw));
+  if (T && !fused) MASW_HIP(hipEventRecord(T->ev[1], s));
+  if (fused)
+    MASW_HIP(launch_fused(mode, blocks, s, sw));
+  else if (in.n_lam > 0)
+    MASW_HIP(inertia ? launch_inertia(sw, ctx->cus, s, &blocks) : launch_sweep(mode, G, blocks, s, sw));
   if (T) MASW_HIP(hipEventRecord(T->ev[2], s));
   if (in.misfit && inertia)
     MASW_HIP(launch_misfit(in.n_models, p.lambda_off, sw.out_ct, c_e_dev, misfit_dev, s));
@@ -402,7 +429,9 @@ int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t fl
   ctx->tslot_last = ts;
   ctx->last = masw_stats{};
   ctx->last.n_lambda = uint64_t(in.n_lam);
-  ctx->last.waves_per_item = G;
+  ctx->last.waves_per_item = fused ? kFusedG : G;
+  ctx->last_fused = fused;
+  ctx->last.fused_staging = fused ? 1 : 0;
   ctx->last.workgroups = in.n_lam > 0 ? blocks : 0;
   ctx->wg_counts = sw.wg_counts;
   ctx->wg_rows = in.n_lam > 0 ? blocks : 0;
@@ -505,6 +534,7 @@ int masw_create(int device, size_t hbm_budget_bytes, masw_ctx** out) {
     if (g == 1 || g == 2 || g == 4 || g == 8 || g == 16) ctx->forced_waves = g;
   }
   if (const char* f = std::getenv("MASW_SHARED_SWEEPS")) ctx->shared_sweeps = std::atoi(f) != 0;
+  if (const char* f = std::getenv("MASW_FUSED_SMALL")) ctx->fused_small = std::atoi(f) != 0;
   if (const char* f = std::getenv("MASW_PRIO")) {
     // "hi,mid" queue positions (tuning; "0,0" = off)
     int hi = 0, mid = 0;
@@ -1006,8 +1036,8 @@ int masw_get_stats(masw_ctx* ctx, masw_stats* out) {
   if (ctx->stats_pending) {
     MASW_HIP(hipSetDevice(ctx->device));
     if (ctx->last_valid) MASW_HIP(hipStreamSynchronize(ctx->last_stream));
-    Counters c;
-    MASW_HIP(hipMemcpy(&c, ctx->counters, sizeof(Counters), hipMemcpyDeviceToHost));
+    Counters c{};  // a fused launch has no staging, which is what clears the counters
+    if (!ctx->last_fused) MASW_HIP(hipMemcpy(&c, ctx->counters, sizeof(Counters), hipMemcpyDeviceToHost));
     ctx->last.useful_evals = c.useful;
     ctx->last.sweep_evals = c.sweep;
     ctx->last.check_evals = c.check;

@@ -120,6 +120,10 @@ struct ItemRef {
 
 // Extent of a sweep in precision T: the whole grid in FP64; in FP32 the
 // points below the half-space's S velocity, where inertia counts certify it.
+// FP32 grid point i: the staged copy, or (c32 null: a fused launch) the FP64
+// value rounded here, which is the value the staging stores.
+__device__ __forceinline__ float c32_at(const ItemRef& r, int i) { return r.c32 ? r.c32[i] : float(r.c64[i]); }
+
 template <typename T>
 __device__ __forceinline__ int sweep_len(const ItemRef& r) {
   return sizeof(T) == 8 ? r.n_c : r.n_real;
@@ -198,7 +202,7 @@ __device__ __forceinline__ int eval_round(const ItemRef& r, int rd, SweepShared<
     if constexpr (sizeof(T) == 8)
       sg = det_sign<double, false>(r.c64[i], r.k64, r.L64, r.N, nullptr);
     else
-      sg = sweep_code32(r.c32[i], float(r.k64), r.L32, r.N);
+      sg = sweep_code32(c32_at(r, i), float(r.k64), r.L32, r.N);
   }
   *s0 = sg;
   return round_first_change<G>(sg, kNoSign, sh.last, sh.first, sh.pair, sl, sa, pa);
@@ -398,7 +402,7 @@ __device__ bool run_item(const ItemRef& r, ItemState& st, int budget, SweepShare
           }
           ++rounds;
           const int i = base + tid;
-          const int sg = (i < n32) ? sweep_code32(r.c32[i], k32, r.L32, r.N) : kNoSign;
+          const int sg = (i < n32) ? sweep_code32(c32_at(r, i), k32, r.L32, r.N) : kNoSign;
           int s_c, p_c;
           const int f = round_first_change<G>(sg, carry, sh.last, sh.first, sh.pair, &carry, &s_c, &p_c);
           wc.sweep += (unsigned long long)min(P, n32 - base);
@@ -777,8 +781,102 @@ void sweep_kernel(SweepArgs a) {
 }
 
 
+// A small single-model launch with the staging folded in (SweepArgs::fused):
+// the workgroup of index w takes wavelength w.  It checks the raw model (as
+// the staging does), writes the layer records into its LDS, checks the grid
+// and counts its points below the half-space's S velocity, and computes k,
+// all with the staging's arithmetic, so outputs equal those of the staged
+// launch bit for bit.  A kernel of its own: its records are read from LDS,
+// while the staged kernels read theirs with scalar loads.
+template <int MODE>
+__global__ __launch_bounds__(64 * kFusedG) void fused_sweep_kernel(SweepArgs a) {
+  constexpr int G = kFusedG;
+  __shared__ SweepShared<G> sh;
+  __shared__ int s_below;
+  extern __shared__ __attribute__((aligned(64))) unsigned char fused_lds[];
+  const int N = a.fused_N, n_c = a.f_n_c, tid = threadIdx.x;
+  LayerRec64* L64 = reinterpret_cast<LayerRec64*>(fused_lds);
+  LayerRec32* L32 = reinterpret_cast<LayerRec32*>(fused_lds + sizeof(LayerRec64) * size_t(N + 1));
+  if (tid == 0) s_below = 0;
+  // the model: checks and records (build_model's)
+  const double be_hs = a.f_beta[N];
+  const double mu_ref = a.f_rho[N] * be_hs * be_hs;
+  bool lok = (N >= 0) && (N <= kFusedMaxLayers);
+  for (int j = tid; j <= N; j += 64 * G) {
+    const double al = a.f_alpha[j], be = a.f_beta[j], rh = a.f_rho[j];
+    const bool finite = (al < __builtin_inf()) && (rh < __builtin_inf());
+    bool ok = finite && (be > 0.0) && (al > be) && (rh > 0.0);
+    const double h = (j < N) ? a.f_h[j] : 0.0;
+    if (j < N) ok = ok && (h > 0.0) && (h < __builtin_inf());
+    lok = lok && ok;
+    LayerRec64 r;
+    r.ia2 = 1.0 / (al * al);
+    r.ib2 = 1.0 / (be * be);
+    r.rh = rh / mu_ref;
+    r.mh = rh * be * be / mu_ref;
+    r.h = h;
+    r.aux = (j == N) ? mu_ref : 0.0;
+    r.zb = 0.0;  // only the batch staging's work order reads it
+    r.pad2 = 0.0;
+    L64[j] = r;
+    LayerRec32 q;
+    q.ia2 = float(r.ia2);
+    q.ib2 = float(r.ib2);
+    q.rh = float(r.rh);
+    q.mh = float(r.mh);
+    q.h = float(r.h);
+    q.aux = float(mu_ref);
+    q.zb = 0.0f;
+    q.pad2 = 0.0f;
+    L32[j] = q;
+  }
+  // the grid: finite, > 0, strictly increasing (the staging's checks), and
+  // its points below beta_hs in the arithmetic of build_model's search
+  const double ib2 = 1.0 / (be_hs * be_hs);
+  bool gok = true;
+  int below = 0;
+  for (int i = tid; i < n_c; i += 64 * G) {
+    const double c = a.f_c[i];
+    bool ok = (c > 0.0) && (c < __builtin_inf());
+    if (i + 1 < n_c) ok = ok && (c < a.f_c[i + 1]);
+    gok = gok && ok;
+    below += (c * c * ib2 < 1.0) ? 1 : 0;
+  }
+  const int bad = __syncthreads_or((lok && gok) ? 0 : 1);
+  for (int o = 32; o > 0; o >>= 1) below += __shfl_xor(below, o, 64);
+  if ((tid & 63) == 0 && below) atomicAdd(&s_below, below);
+  __syncthreads();
+  const int n_real = s_below;
+  const int g = int(blockIdx.x);
+  const double lam = a.f_lambda[g];
+  const bool ok = !bad && (lam > 0.0) && (lam < __builtin_inf());
+  ItemRef r;
+  r.N = bad ? 0 : N;
+  r.n_c = n_c;
+  r.n_real = bad ? 0 : n_real;
+  r.k64 = ok ? (2.0 * M_PI / lam) : __builtin_nan("");
+  r.c64 = a.f_c;
+  r.c32 = nullptr;  // rounded from c64 where read
+  r.L64 = L64;
+  r.L32 = L32;
+  const ItemOut o{a.out_ct + g, a.out_idx + g, a.out_status + g, a.out_cref ? a.out_cref + g : nullptr, a.refine,
+                  a.refine_rel};
+  WorkCount wc;
+  if (!ok) {
+    write_missing<G>(o, MASW_STATUS_INVALID);
+  } else {
+    ItemState st = item_state_init();
+    run_item<MODE, G>(r, st, 0x7fffffff, sh, wc, o, kNoCoop, a.counters);
+  }
+  flush_counts(a.counters, a.wg_counts, wc);
+}
+
+// Dynamic LDS of a fused launch: the model's FP64 and FP32 records.
+inline size_t fused_lds_bytes(int N) { return (sizeof(LayerRec64) + sizeof(LayerRec32)) * size_t(N + 1); }
+
 // The split kernels (masw_sweep_split.hip): sweep_kernel<kModeSplit, G,
-// misfit> for G in 1, 2, 4, 8, 16, or null.
+// misfit> for G in 1, 2, 4, 8, 16, or null; fused_sweep_kernel<kModeSplit>.
 const void* split_sweep_symbol(int G, bool misfit);
+const void* split_fused_symbol();
 
 }  // namespace masw

@@ -24,4 +24,6 @@ const void* split_sweep_symbol(int G, bool misfit) {
   return misfit ? split_symbol<true>(G) : split_symbol<false>(G);
 }
 
+const void* split_fused_symbol() { return reinterpret_cast<const void*>(&fused_sweep_kernel<kModeSplit>); }
+
 }  // namespace masw

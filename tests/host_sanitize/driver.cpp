@@ -20,6 +20,7 @@ static hipError_t reached(const char* what) {
 int sweep_blocks_per_cu(int, int) { return 1; }
 int tick_blocks_per_cu(int, bool) { return 1; }
 hipError_t launch_sweep(int, int, int, hipStream_t, const SweepArgs&) { return reached("sweep"); }
+hipError_t launch_fused(int, int, hipStream_t, const SweepArgs&) { return reached("fused sweep"); }
 hipError_t launch_inertia(const SweepArgs&, int, hipStream_t, int*) { return reached("inertia"); }
 hipError_t launch_prep(const PrepArgs&, const CoopInitArgs&, int, int, hipStream_t) { return reached("prep"); }
 hipError_t launch_sign_map(bool, const SignMapArgs&, hipStream_t) { return reached("sign map"); }

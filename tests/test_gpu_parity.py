@@ -220,6 +220,57 @@ def test_device_side_validation_marks_invalid(torch_dev, ctx):
     assert st[3] == M.MASW_STATUS_INVALID and np.all(np.delete(st, 3) == 0)
 
 
+def test_fused_small_launches_equal_staged_launches(torch_dev, ctx):
+    # Small single-curve launches stage the model, grid and wavelengths inside
+    # the sweep kernel (one launch); with MASW_FUSED_SMALL=0 a context stages
+    # them in a launch of their own.  Outputs must be equal bit for bit, for
+    # both precisions, with and without refinement, at the limits of the fused
+    # launch (64 layers, 2048 grid points, 1024 wavelengths), on a bare
+    # half-space, and on inputs the device checks reject.
+    os.environ["MASW_FUSED_SMALL"] = "0"
+    try:
+        staged = M.Context(0, 1 << 30)
+    finally:
+        del os.environ["MASW_FUSED_SMALL"]
+    rng = np.random.Generator(np.random.PCG64(31))
+    wl = WL.two_layer_case()
+    two, lam2, c2 = wl.models[0], wl.lambdas[0], wl.c_test
+    uni = WL.uniform_case(238.0, 100)
+    deep = WL.increasing_profile(rng, 64)
+    c_deep = WL.uniform_grid(60.0, 0.25, 2048)
+    hs = WL.Model(np.zeros(0), np.array([math.sqrt(3) * 400.0]), np.array([400.0]), np.array([2000.0]))
+    bad_model = two.copy()
+    bad_model.alpha[1] = 0.5 * bad_model.beta[1]
+    bad_grid = c2.copy()
+    bad_grid[10] = bad_grid[9]
+    bad_lam = lam2.copy()
+    bad_lam[3] = -1.0
+    cases = [("two-layer", c2, lam2, two), ("uniform", uni.c_test, uni.lambdas[0], uni.models[0]),
+             ("64 layers, 2048 points", c_deep, WL.log_spaced(1.0, 120.0, 30), deep),
+             ("1024 wavelengths", WL.uniform_grid(50.0, 1.0, 400), WL.log_spaced(0.5, 60.0, 1024), two),
+             ("two points, one wavelength", c2[:2], lam2[:1], two),
+             ("half-space", WL.uniform_grid(300.0, 0.5, 300), np.array([1.0, 10.0]), hs),
+             ("invalid model", c2, lam2, bad_model), ("invalid grid", bad_grid, lam2, two),
+             ("one invalid wavelength", c2, bad_lam, two)]
+    try:
+        for name, c, lam, m in cases:
+            for prec in (M.MASW_PREC_FP64, M.MASW_PREC_SPLIT):
+                for flags in (0, M.MASW_NO_REFINE):
+                    got = dev_curve(torch_dev, ctx, c, lam, m, prec, flags)
+                    assert M.masw_get_stats(ctx.ctx)["fused_staging"] == 1, name
+                    want = dev_curve(torch_dev, staged, c, lam, m, prec, flags)
+                    assert M.masw_get_stats(staged.ctx)["fused_staging"] == 0, name
+                    for x, y in zip(got, want):
+                        np.testing.assert_array_equal(x, y, err_msg=f"{name} prec {prec} flags {flags}")
+            print(f"fused = staged: {name}", flush=True)
+        # and the fused launch's picks against the oracle on the two-layer case
+        idx, st, cr = oracle_curve(lam2, c2, two)
+        compare("fused two-layer", dev_curve(torch_dev, ctx, c2, lam2, two, M.MASW_PREC_SPLIT), idx, st, cr,
+                lam2, c2, two)
+    finally:
+        staged.close()
+
+
 def test_many_layers(torch_dev, ctx):
     rng = np.random.Generator(np.random.PCG64(21))
     m = WL.increasing_profile(rng, 120)
