@@ -85,14 +85,14 @@ def classify_flops(evals: int, layers: int, steps: int) -> float:
 # classification), the workload and the
 # launch, so a changed kernel reports null until it is measured again.
 MEASURED_TRAFFIC = {
-    ("9eafcc39db7e92e4", "fine_scale_N20_1000lam_115001c", "sweep_kernel<FP64,G=8>"):
-        4824.69 * 1024 * 2.000 + 2597.37 * 1024 * 1.000,
-    ("9eafcc39db7e92e4", "batch_4096models_19001c", "sweep_kernel<FP64,G=1>"):
-        266847.0 * 1024 * 2.000 + 148185.0 * 1024 * 1.000,
-    ("de7b31af11e39fb6", "fine_scale_N20_1000lam_115001c", "inertia_kernel"):
-        881.0 * 1024 * 2.000 + 1546.88 * 1024 * 1.000,
-    ("de7b31af11e39fb6", "batch_4096models_19001c", "inertia_kernel"):
-        41416.2 * 1024 * 2.000 + 34320.4 * 1024 * 1.000,
+    ("7719019f9aab8756", "fine_scale_N20_1000lam_115001c", "sweep_kernel<FP64,G=8>"):
+        4882.62 * 1024 * 2.000 + 2580.70 * 1024 * 1.000,
+    ("7719019f9aab8756", "batch_4096models_19001c", "sweep_kernel<FP64,G=1>"):
+        267403.88 * 1024 * 2.000 + 146929.11 * 1024 * 1.000,
+    ("488b5ea3547bd222", "fine_scale_N20_1000lam_115001c", "inertia_lone_kernel"):
+        906.83 * 1024 * 2.000 + 46.875 * 1024 * 1.000,
+    ("488b5ea3547bd222", "batch_4096models_19001c", "inertia_kernel"):
+        39633.06 * 1024 * 2.000 + 28600.91 * 1024 * 1.000,
     ("ef681d38c885d05d", "classify_batch_4096models_19001c", "classify_kernel"):
         14642.625 * 1024 * 2.000 + 21872.34 * 1024 * 1.000,
 }
