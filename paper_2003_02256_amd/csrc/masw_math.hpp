@@ -44,6 +44,15 @@ namespace masw {
 
 // ---------------------------------------------------------------- helpers --
 template <typename T>
+__device__ __forceinline__ T fma_(T a, T b, T c) {
+  return __builtin_fma(a, b, c);
+}
+template <>
+__device__ __forceinline__ float fma_(float a, float b, float c) {
+  return __builtin_fmaf(a, b, c);
+}
+
+template <typename T>
 __device__ __forceinline__ T sqrt_(T x) {
   return __builtin_sqrt(x);
 }
@@ -101,9 +110,14 @@ __device__ __forceinline__ Terms<T> potential_terms(T x, T t, T t2) {
 //      [k13, -k14,  k11, -k12],
 //      [k14,  k24, -k12,  k22]]  / (k mu_ref)
 // and gD = E_r E_s D, whose sign is the sign of the layer's denominator D.
+// The coupling entries k13, k14, k24 are also kept without the factor F
+// (q13 = k13 / F, ...): the block elimination takes F^2 into the reciprocal
+// of its pivot's determinant instead (schur_layer), one product fewer per
+// layer; kernels that need the entries themselves read k13, k14, k24.
 template <typename T>
 struct LayerK {
   T k11, k12, k13, k14, k22, k24, gD;
+  T F, q13, q14, q24;
 };
 
 template <typename T>
@@ -119,12 +133,17 @@ __device__ __forceinline__ LayerK<T> layer_entries(T c2, T t, T ia2, T ib2, T rh
   LayerK<T> o;
   o.gD = T(-2) * u + P.Sh * S.Sh + P.R * S.R;
   const T F = rh * c2 * special::rcp(o.gD);  // f / (k mu_ref), E factors cancelled
+  o.F = F;
   o.k11 = F * (Cr * S.Sh - P.R * Cs);
-  o.k12 = F * (u - P.R * S.R) - mh * (T(1) + xs);
-  o.k13 = F * (P.R * S.E - S.Sh * P.E);
-  o.k14 = F * (S.a * P.E - P.a * S.E);
+  // F (u - R_r R_s) - mh (1 + s^2), with mh folded into the two FMAs
+  o.k12 = fma_(-mh, xs, fma_(F, u - P.R * S.R, -mh));
+  o.q13 = P.R * S.E - S.Sh * P.E;
+  o.q14 = S.a * P.E - P.a * S.E;
+  o.q24 = S.R * P.E - P.Sh * S.E;
+  o.k13 = F * o.q13;
+  o.k14 = F * o.q14;
   o.k22 = F * (P.Sh * Cs - S.R * Cr);
-  o.k24 = F * (S.R * P.E - P.Sh * S.E);
+  o.k24 = F * o.q24;
   return o;
 }
 
@@ -144,9 +163,10 @@ __device__ __forceinline__ T schur_layer(Block2<T>& S, const LayerK<T>& K) {
   const T s12 = S.s12 + K.k12;
   const T s22 = S.s22 + K.k22;
   const T d = s11 * s22 - s12 * s12;
-  const T id = special::rcp(d);
-  // Q_j = [[k13, k14], [-k14, k24]];  W = adj(S_j) Q_j;  M = Q_j^T W
-  const T q11 = K.k13, q12 = K.k14, q21 = -K.k14, q22 = K.k24;
+  // Q_j = F [[q13, q14], [-q14, q24]];  W = adj(S_j) Q_j / F;  M = Q_j^T W / F,
+  // so that Q_j^T S_j^{-1} Q_j = M F^2 / d
+  const T g = K.F * (K.F * special::rcp(d));
+  const T q11 = K.q13, q12 = K.q14, q21 = -K.q14, q22 = K.q24;
   const T w11 = s22 * q11 - s12 * q21;
   const T w12 = s22 * q12 - s12 * q22;
   const T w21 = s11 * q21 - s12 * q11;
@@ -154,9 +174,9 @@ __device__ __forceinline__ T schur_layer(Block2<T>& S, const LayerK<T>& K) {
   const T m11 = q11 * w11 + q21 * w21;
   const T m12 = q11 * w12 + q21 * w22;
   const T m22 = q12 * w12 + q22 * w22;
-  S.s11 = K.k11 - m11 * id;
-  S.s12 = -K.k12 - m12 * id;
-  S.s22 = K.k22 - m22 * id;
+  S.s11 = K.k11 - m11 * g;
+  S.s12 = -K.k12 - m12 * g;
+  S.s22 = K.k22 - m22 * g;
   return d;
 }
 

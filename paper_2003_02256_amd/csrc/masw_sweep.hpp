@@ -725,9 +725,11 @@ __device__ void model_finished(const SweepArgs& a, int m, SweepShared<G>& sh, do
 // sweeps that workgroups with an empty queue join.  MISFIT: Algorithm 2 fused
 // (model_finished), an instantiation of its own so that the plain sweeps
 // keep their register allocation; it is held to 128 VGPRs (4 wavefronts per
-// SIMD, as the plain sweeps), spilling a little outside the layer loop.
+// SIMD, as the plain FP64 sweeps), spilling a little outside the layer loop.
+// The plain split sweeps are held to 96 VGPRs (5 wavefronts per SIMD), which
+// their FP32 loop fits without spilling.
 template <int MODE, int G, bool MISFIT>
-__global__ __launch_bounds__(64 * G) __attribute__((amdgpu_waves_per_eu(MISFIT ? 4 : 1)))
+__global__ __launch_bounds__(64 * G) __attribute__((amdgpu_waves_per_eu(MISFIT ? 4 : (MODE == kModeSplit ? 5 : 1))))
 void sweep_kernel(SweepArgs a) {
   __shared__ SweepShared<G> sh;
   __shared__ double s_mis[MISFIT ? 256 : 1];  // fused misfit reduction
