@@ -1,7 +1,7 @@
 // The inertia-count search as a launch of its own (MASW_SEARCH_INERTIA on the
 // curve and batch calls): the kernel, compiled by two translation units.
 // masw_inertia.hip builds the variant for many wavelengths per SIMD (FP64
-// polynomial coefficients materialised in SGPRs where used, three wavefronts
+// polynomial coefficients materialised in SGPRs where used, four wavefronts
 // per SIMD: MASW_COEFF_POLICY 1); masw_inertia_lone.hip builds the variant
 // for launches of at most one wavefront per SIMD, with every coefficient in
 // VGPRs (MASW_COEFF_POLICY 2), where scalar moves would take issue slots from
@@ -23,7 +23,7 @@
 #define MASW_INERTIA_WAVES_PER_EU 1
 #else
 #define MASW_INERTIA_KERNEL inertia_kernel
-#define MASW_INERTIA_WAVES_PER_EU 3
+#define MASW_INERTIA_WAVES_PER_EU 4
 #endif
 
 namespace masw {
@@ -67,11 +67,14 @@ __device__ __forceinline__ int run_wavelength(const SweepArgs& a, int g, int pre
 // takes wavelengths w, w + W, ...  Otherwise each wavefront claims runs of
 // `chunk` consecutive wavelengths from an atomic queue, and within a run the
 // picks of the previous wavelengths of the same model predict the next pick
-// (round P of search()).  The variant for many wavelengths is held to three
-// wavefronts per SIMD (at most 168 VGPRs), which ran the 4096-model batch 6%
-// faster than the two that an unconstrained allocation of 173 VGPRs allowed;
-// the variant for launches of at most one wavefront per SIMD is not held,
-// and takes its polynomial coefficients from VGPRs (masw_special.hpp).
+// (round P of search()).  The variant for many wavelengths is held to four
+// wavefronts per SIMD (at most 128 VGPRs; it spills some values outside its
+// hot loops), which ran the 4096-model batch 2.7% faster than three
+// wavefronts (153 VGPRs, no spill); with the earlier coefficient placement,
+// three wavefronts had run it 6% faster than the two of an unconstrained
+// allocation.  The variant for launches of at most one wavefront per SIMD is
+// not held, and takes its polynomial coefficients from VGPRs
+// (masw_special.hpp).
 __global__ __launch_bounds__(64 * kInertiaWaves) __attribute__((amdgpu_waves_per_eu(MASW_INERTIA_WAVES_PER_EU)))
 void MASW_INERTIA_KERNEL(SweepArgs a, int chunk) {
   __shared__ unsigned long long s_cnt[kInertiaWaves][7];
