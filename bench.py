@@ -85,14 +85,14 @@ def classify_flops(evals: int, layers: int, steps: int) -> float:
 # classification), the workload and the
 # launch, so a changed kernel reports null until it is measured again.
 MEASURED_TRAFFIC = {
-    ("7719019f9aab8756", "fine_scale_N20_1000lam_115001c", "sweep_kernel<FP64,G=8>"):
-        4882.62 * 1024 * 2.000 + 2580.70 * 1024 * 1.000,
-    ("7719019f9aab8756", "batch_4096models_19001c", "sweep_kernel<FP64,G=1>"):
-        267403.88 * 1024 * 2.000 + 146929.11 * 1024 * 1.000,
-    ("488b5ea3547bd222", "fine_scale_N20_1000lam_115001c", "inertia_lone_kernel"):
-        906.83 * 1024 * 2.000 + 46.875 * 1024 * 1.000,
-    ("488b5ea3547bd222", "batch_4096models_19001c", "inertia_kernel"):
-        39633.06 * 1024 * 2.000 + 28600.91 * 1024 * 1.000,
+    ("e60705128af84d5c", "fine_scale_N20_1000lam_115001c", "sweep_kernel<FP64,G=8>"):
+        4939.56 * 1024 * 2.000 + 2579.36 * 1024 * 1.000,
+    ("e60705128af84d5c", "batch_4096models_19001c", "sweep_kernel<FP64,G=1>"):
+        267717.09 * 1024 * 2.000 + 147027.62 * 1024 * 1.000,
+    ("17b17b04f332626b", "fine_scale_N20_1000lam_115001c", "inertia_lone_kernel"):
+        889.90 * 1024 * 2.000 + 46.875 * 1024 * 1.000,
+    ("17b17b04f332626b", "batch_4096models_19001c", "inertia_kernel"):
+        49503.25 * 1024 * 2.000 + 1010303.53 * 1024 * 1.000,
     ("ef681d38c885d05d", "classify_batch_4096models_19001c", "classify_kernel"):
         14642.625 * 1024 * 2.000 + 21872.34 * 1024 * 1.000,
 }
