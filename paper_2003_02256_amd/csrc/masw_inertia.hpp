@@ -133,8 +133,10 @@ __device__ __forceinline__ int count_E(double c, double k, const LayerRec64* __r
   Block2<double> S{0.0, 0.0, 0.0};
   int s = 0, P = 0;
   bool ok = true;
+  LayerRec<double> nxt = load_rec<double>(L, 0);
   for (int j = 0; j < N; ++j) {
-    const LayerRec<double> rec = load_rec<double>(L, j);
+    const LayerRec<double> rec = nxt;
+    nxt = load_rec<double>(L, j + 1);  // one layer ahead
     const double kh = k * rec.h;
     const LayerK<double> K = layer_entries<double>(c2, kh, rec.ia2, rec.ib2, rec.rh, rec.mh);
     const double a = S.s11 + K.k11;
@@ -172,8 +174,10 @@ __device__ __forceinline__ int det_sign_inertia(double c, double k, const LayerR
   Block2<double> S{0.0, 0.0, 0.0};
   bool neg = false, par = false, ok = true, bounded = true;
   int s = 0;
+  LayerRec<double> nxt = load_rec<double>(L, 0);
   for (int j = 0; j < N; ++j) {
-    const LayerRec<double> rec = load_rec<double>(L, j);
+    const LayerRec<double> rec = nxt;
+    nxt = load_rec<double>(L, j + 1);  // one layer ahead; after the last layer, the half-space
     const double kh = k * rec.h;
     const LayerK<double> K = layer_entries<double>(c2, kh, rec.ia2, rec.ib2, rec.rh, rec.mh);
     par ^= (K.gD < 0.0);
@@ -187,7 +191,7 @@ __device__ __forceinline__ int det_sign_inertia(double c, double k, const LayerR
     const double x = c2 * rec.ib2 - 1.0;
     bounded = bounded && !(x > 0.0 && kh * kh * x >= 9.86);
   }
-  const LayerRec<double> hs = load_rec<double>(L, N);
+  const LayerRec<double> hs = nxt;
   double re, im, ar;
   halfspace_det<double>(S, c2, hs.ia2, hs.ib2, hs.mh, &re, &im, &ar);
   ok = ok && usable(re) && (c2 * hs.ib2 < 1.0);
@@ -205,8 +209,10 @@ __device__ __forceinline__ int det_sign_inertia(double c, double k, const LayerR
 __device__ __forceinline__ int poles_below(double c, double k, const LayerRec64* __restrict__ L, int N, bool* ok) {
   const double c2 = c * c;
   int P = 0;
+  LayerRec<double> nxt = load_rec<double>(L, 0);
   for (int j = 0; j < N; ++j) {
-    const LayerRec<double> rec = load_rec<double>(L, j);
+    const LayerRec<double> rec = nxt;
+    nxt = load_rec<double>(L, j + 1);
     layer_poles(c2, k * rec.h, rec, &P, ok);
   }
   return P;

@@ -236,7 +236,11 @@ __device__ __forceinline__ void halfspace_det(const Block2<T>& S, T c2, T ia2, T
 // its records in LDS (a workgroup writes them itself): those are read as
 // LDS, since a scalar load of an LDS address would read global memory at a
 // meaningless address.  The compiler knows each pointer's address space
-// after inlining, so the test costs nothing at run time.
+// after inlining, so the test costs nothing at run time.  The loops over
+// layers read each record one layer ahead (the record after the last layer
+// is the half-space's), so that the load's latency overlaps the previous
+// layer's arithmetic: a wavefront alone on its SIMD otherwise waits for it
+// at every layer.
 template <typename T>
 using ConstRec = const __attribute__((address_space(4))) LayerRec<T>;
 
@@ -290,14 +294,16 @@ __device__ __forceinline__ int det_sign(T c, T k, const LayerRec<T>* __restrict_
   Block2<T> S{T(0), T(0), T(0)};
   bool neg = false;
   uint64_t mask = 0;
+  LayerRec<T> nxt = load_rec<T>(L, 0);
   for (int j = 0; j < N; ++j) {
-    const LayerRec<T> rec = load_rec<T>(L, j);
+    const LayerRec<T> rec = nxt;
+    nxt = load_rec<T>(L, j + 1);  // one layer ahead; after the last layer, the half-space
     const LayerK<T> K = layer_entries<T>(c2, k * rec.h, rec.ia2, rec.ib2, rec.rh, rec.mh);
     if (kMask) mask ^= uint64_t(K.gD < T(0)) << (j & 63);
     const T d = schur_layer<T>(S, K);
     neg ^= (d < T(0));
   }
-  const LayerRec<T> hs = load_rec<T>(L, N);
+  const LayerRec<T> hs = nxt;
   T re, im;
   halfspace_det<T>(S, c2, hs.ia2, hs.ib2, hs.mh, &re, &im);
   if (kMask) *dmask = mask;
@@ -315,8 +321,10 @@ __device__ __forceinline__ int det_sign_value(double c, double k, const LayerRec
   uint64_t mask = 0;
   double m = 1.0;
   int e = 0;
+  LayerRec<double> nxt = load_rec<double>(L, 0);
   for (int j = 0; j < N; ++j) {
-    const LayerRec<double> rec = load_rec<double>(L, j);
+    const LayerRec<double> rec = nxt;
+    nxt = load_rec<double>(L, j + 1);
     const LayerK<double> K = layer_entries<double>(c2, k * rec.h, rec.ia2, rec.ib2, rec.rh, rec.mh);
     mask ^= uint64_t(K.gD < 0.0) << (j & 63);
     const double d = schur_layer<double>(S, K);
@@ -325,7 +333,7 @@ __device__ __forceinline__ int det_sign_value(double c, double k, const LayerRec
     m = __builtin_frexp(m * d, &ex);
     e += ex;
   }
-  const LayerRec<double> hs = load_rec<double>(L, N);
+  const LayerRec<double> hs = nxt;
   double re, im;
   halfspace_det<double>(S, c2, hs.ia2, hs.ib2, hs.mh, &re, &im);
   *dmask = mask;
@@ -343,14 +351,16 @@ __device__ __forceinline__ int det_sign_parity(T c, T k, const LayerRec<T>* __re
   const T c2 = c * c;
   Block2<T> S{T(0), T(0), T(0)};
   bool neg = false, par = false;
+  LayerRec<T> nxt = load_rec<T>(L, 0);
   for (int j = 0; j < N; ++j) {
-    const LayerRec<T> rec = load_rec<T>(L, j);
+    const LayerRec<T> rec = nxt;
+    nxt = load_rec<T>(L, j + 1);
     const LayerK<T> K = layer_entries<T>(c2, k * rec.h, rec.ia2, rec.ib2, rec.rh, rec.mh);
     par ^= (K.gD < T(0));
     const T d = schur_layer<T>(S, K);
     neg ^= (d < T(0));
   }
-  const LayerRec<T> hs = load_rec<T>(L, N);
+  const LayerRec<T> hs = nxt;
   T re, im;
   halfspace_det<T>(S, c2, hs.ia2, hs.ib2, hs.mh, &re, &im);
   *odd = par ? 1 : 0;
@@ -366,14 +376,16 @@ __device__ __forceinline__ int det_sign_logabs(T c, T k, const LayerRec<T>* __re
   Block2<T> S{T(0), T(0), T(0)};
   bool neg = false;
   double acc = 0.0;
+  LayerRec<T> nxt = load_rec<T>(L, 0);
   for (int j = 0; j < N; ++j) {
-    const LayerRec<T> rec = load_rec<T>(L, j);
+    const LayerRec<T> rec = nxt;
+    nxt = load_rec<T>(L, j + 1);
     const LayerK<T> K = layer_entries<T>(c2, k * rec.h, rec.ia2, rec.ib2, rec.rh, rec.mh);
     const T d = schur_layer<T>(S, K);
     neg ^= (d < T(0));
     acc += ::log(::fabs(double(d)));
   }
-  const LayerRec<T> hs = load_rec<T>(L, N);
+  const LayerRec<T> hs = nxt;
   T re, im;
   halfspace_det<T>(S, c2, hs.ia2, hs.ib2, hs.mh, &re, &im);
   acc += ::log(::hypot(double(re), double(im)));

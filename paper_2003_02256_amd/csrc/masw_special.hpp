@@ -134,24 +134,25 @@ __device__ __forceinline__ double fma_sc(double p, double x, double c) {
   return d;
 }
 
-// x * c0 + c1 as a product and a sum (with the constants in SGPRs, one VALU
-// instruction can read only one of them).
+// x * c0 + c1 as one v_fma_f64.  With both constants in SGPRs (one VALU
+// instruction can read only one SGPR pair) c1 is first copied to a VGPR
+// pair by one v_mov_b64, so the two placements round alike.
 template <Coef P>
-__device__ __forceinline__ double mul_add_ss(double x, double c0, double c1) {
-  double m, d;
+__device__ __forceinline__ double fma_cc(double x, double c0, double c1) {
+  double d;
   if constexpr (P == Coef::Vgpr) {
-    asm("v_mul_f64 %0, %1, %2" : "=v"(m) : "v"(x), "v"(c0));
-    asm("v_add_f64 %0, %1, %2" : "=v"(d) : "v"(m), "v"(c1));
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(x), "v"(c0), "v"(c1));
   } else {
-    asm("v_mul_f64 %0, %1, %2" : "=v"(m) : "v"(x), "s"(c0));
-    asm("v_add_f64 %0, %1, %2" : "=v"(d) : "v"(m), "s"(c1));
+    double v1;
+    asm("v_mov_b64 %0, %1" : "=v"(v1) : "s"(c1));
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(x), "s"(c0), "v"(v1));
   }
   return d;
 }
 
 // Horner's rule for the polynomial C[0] z^(D-1) + ... + C[D-1] (highest
-// degree first).  The first step is a product and a sum; each later
-// coefficient is materialised one step ahead of the FMA that reads it.
+// degree first), one FMA per step; each coefficient after the first two is
+// materialised one step ahead of the FMA that reads it.
 template <const double* C, int J, int D, Coef P>
 __device__ __forceinline__ double horner_k(double p, double z, double cj) {
   if constexpr (J + 1 == D) {
@@ -167,7 +168,7 @@ __device__ __forceinline__ double poly_k(double z) {
   const double c0 = kconst<__builtin_bit_cast(uint64_t, C[0]), P>();
   const double c1 = kconst<__builtin_bit_cast(uint64_t, C[1]), P>();
   const double c2 = kconst<__builtin_bit_cast(uint64_t, C[2]), P>();
-  return horner_k<C, 2, D, P>(mul_add_ss<P>(z, c0, c1), z, c2);
+  return horner_k<C, 2, D, P>(fma_cc<P>(z, c0, c1), z, c2);
 }
 
 __device__ __forceinline__ double rcp(double d) {
