@@ -179,24 +179,39 @@ class DeviceJob:
 
 
 def time_path(job, ctx, prec, steps, warmup):
-    """Wall time per job over `steps` back-to-back jobs on the library's stream,
-    and the mean sweep-kernel and job device times of exactly those launches
-    (HIP events the library records around every launch)."""
+    """Two timed passes of `steps` back-to-back jobs on the library's stream,
+    after `warmup` jobs.  The first runs with the library's default timing
+    (the GPU's real-time counter, read by the kernels; no host event): its
+    wall time per job is the path's rate.  In the second the library records
+    HIP events around every launch (masw_opts.timing_events), each costing
+    some 5 us of host time: the mean sweep-kernel and job device times of
+    exactly those launches give the roofline.  Returns (wall, sweep_ms,
+    total_ms, stats of the last job, details)."""
     torch, M = job.torch, job.M
+
+    def timed(events):
+        M.masw_set_opts(ctx, timing_events=events)
+        M.masw_get_timing(ctx, reset=True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            job.run(ctx, prec)
+        torch.cuda.synchronize()
+        w = (time.perf_counter() - t0) / steps
+        tm = M.masw_get_timing(ctx, reset=True)
+        if tm["launches"] != steps:
+            raise RuntimeError(f"timed {tm['launches']} launches, expected {steps}")
+        return w, tm["sweep_ms_sum"] / steps, tm["total_ms_sum"] / steps
+
     for _ in range(warmup):
         job.run(ctx, prec)
     torch.cuda.synchronize()
-    M.masw_get_timing(ctx, reset=True)         # drop the warm-up launches
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        job.run(ctx, prec)
-    torch.cuda.synchronize()
-    wall = (time.perf_counter() - t0) / steps
-    tm = M.masw_get_timing(ctx, reset=True)
-    if tm["launches"] != steps:
-        raise RuntimeError(f"timed {tm['launches']} launches, expected {steps}")
+    wall, sweep_c, total_c = timed(0)
+    wall_e, sweep_e, total_e = timed(1)
+    M.masw_set_opts(ctx)                       # default options again
     stats = M.masw_get_stats(ctx)              # counters of the last job
-    return wall, tm["sweep_ms_sum"] / steps, tm["total_ms_sum"] / steps, stats
+    details = {"ms_per_step_with_events": wall_e * 1e3, "sweep_ms_counter": sweep_c,
+               "device_ms_per_step_counter": total_c}
+    return wall, sweep_e, total_e, stats, details
 
 
 # ------------------------------------------------------------------ serving --
@@ -628,14 +643,14 @@ def measure_curves(M, torch, wl, steps: int, warmup: int, inertia: bool = True) 
     first_call_ms = (time.perf_counter() - t0) * 1e3
 
     log(f"{wl.name}: timing the FP64 path")
-    wall64, sweep64, total64, st64 = time_path(job, ctx, M.MASW_PREC_FP64, steps, warmup)
+    wall64, sweep64, total64, st64, x64 = time_path(job, ctx, M.MASW_PREC_FP64, steps, warmup)
     r64 = job.results(M.MASW_PREC_FP64)
     log(f"{wl.name}: timing the split path")
-    wall32, sweep32, total32, st32 = time_path(job, ctx, M.MASW_PREC_SPLIT, steps, warmup)
+    wall32, sweep32, total32, st32, _ = time_path(job, ctx, M.MASW_PREC_SPLIT, steps, warmup)
     r32 = job.results(M.MASW_PREC_SPLIT)
     if inertia:
         log(f"{wl.name}: timing the inertia-count search")
-        wall_i, sweep_i, total_i, st_i = time_path(job, ctx, "inertia", steps, warmup)
+        wall_i, sweep_i, total_i, st_i, _ = time_path(job, ctx, "inertia", steps, warmup)
         st_i["cus"] = torch.cuda.get_device_properties(0).multi_processor_count
         r_i = job.results("inertia")
     graph = graph_replay(M, torch, job, ctx, steps, warmup, r64) if job.single and wl.n_lambda_total <= 1024 else None
@@ -673,6 +688,11 @@ def measure_curves(M, torch, wl, steps: int, warmup: int, inertia: bool = True) 
         "algorithmic_evals": algorithmic64,
         "first_call_ms": first_call_ms,
         "device_ms_per_step": total64,
+        "timing": {"ms_per_step_with_events": x64["ms_per_step_with_events"],
+                   "device_ms_per_step_counter": x64["device_ms_per_step_counter"],
+                   "sweep_ms_counter": x64["sweep_ms_counter"],
+                   "note": "ms_per_step: the library's default timing (GPU real-time counter); "
+                           "device times and roofline: a second pass with HIP events per launch"},
         "split": {
             "value": useful / wall32, "unit": "det evals/s", "ms_per_step": wall32 * 1e3,
             "dtype": "f32 sweep + f64 re-check/refine", "speedup_vs_fp64": wall64 / wall32,

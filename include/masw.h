@@ -175,7 +175,7 @@ typedef struct {
     int32_t waves_per_item; /* wavefronts that cooperated on one wavelength    */
     int32_t workgroups;     /* persistent workgroups launched                  */
     float sweep_ms;         /* device time of the sweep/re-check/refine kernel,
-                               from HIP events on the launch stream            */
+                               from the GPU's real-time counter (masw_timing)  */
     float total_ms;         /* device time of staging + ordering + sweep       */
     int32_t shared_items;   /* wavelengths run as shared sweeps, which workgroups
                                that run out of queued work join                */
@@ -216,7 +216,11 @@ typedef struct {
                                  (0 = 8; -1 = no shared sweeps)               */
     int32_t first_item_priority; /* 0 = each workgroup's first (deepest) item
                                  runs at wave issue priority 2; -1 = off      */
-    int32_t reserved;         /* must be 0                                    */
+    int32_t timing_events;    /* 1 = time each call with HIP events around its
+                                 kernels (the launches' exact bounds, as a
+                                 profiler sees them; each event costs some
+                                 5 us of host time); 0 = from the GPU's
+                                 real-time counter (masw_get_timing)          */
 } masw_opts;
 
 /* Set the options of ctx (NULL = defaults).  They apply to later calls; a
@@ -468,9 +472,12 @@ int masw_classify_picks(masw_ctx *ctx, const double *c_test, int32_t n_c,
 int masw_get_stats(masw_ctx *ctx, masw_stats *out);
 
 /* Device time of the masw_dispersion_curve / masw_dispersion_batch calls
- * made on ctx since the timing was last reset, from HIP events recorded on
- * each call's stream (no synchronisation between calls is needed to time
- * them).  Waits for those calls to finish.  With reset != 0 the sums start
+ * made on ctx since the timing was last reset (calls with n_lambda > 0), from
+ * the GPU's constant-rate real-time counter, which each call's kernels read
+ * at the start of its first kernel, the start of its sweep and the end of
+ * the sweep's last workgroup (no host event and no synchronisation between
+ * calls is needed to time them; the dispatch latency before a kernel's
+ * first workgroup starts is not counted).  Waits for those calls to finish.  With reset != 0 the sums start
  * again from zero after being returned.  Calls on other contexts, sign maps
  * and served requests are not counted. */
 typedef struct {

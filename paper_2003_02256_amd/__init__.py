@@ -96,10 +96,10 @@ class masw_stats(ctypes.Structure):
 class masw_opts(ctypes.Structure):
     _fields_ = [("refine_rel_tol", ctypes.c_double), ("noise_threshold", ctypes.c_double),
                 ("waves_per_item", ctypes.c_int32), ("shared_window", ctypes.c_int32),
-                ("first_item_priority", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("first_item_priority", ctypes.c_int32), ("timing_events", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class masw_timing(ctypes.Structure):
@@ -368,9 +368,10 @@ def masw_misfit(ctx, lambda_off, C_t, C_e, flags: int, stream, misfit) -> int:
 
 
 def masw_set_opts(ctx, refine_rel_tol=0.0, noise_threshold=0.0, waves_per_item=0, shared_window=0,
-                  first_item_priority=0) -> int:
+                  first_item_priority=0, timing_events=0) -> int:
     """Options of ctx (zero = default; see masw_opts in include/masw.h)."""
-    o = masw_opts(refine_rel_tol, noise_threshold, waves_per_item, shared_window, first_item_priority, 0)
+    o = masw_opts(refine_rel_tol, noise_threshold, waves_per_item, shared_window, first_item_priority,
+                  timing_events)
     return _check(library().masw_set_opts(ctx, ctypes.byref(o)), "masw_set_opts")
 
 

@@ -121,18 +121,29 @@ struct masw_ctx {
   masw_stats last = {};
   bool stats_pending = false;
   masw::Counters* counters = nullptr;  // arena offset 0
-  // HIP events of the last kTimingSlots synchronous calls (start, sweep
-  // start, sweep end), so that back-to-back calls can be timed without a
-  // synchronisation per call; a slot is resolved into the running sums when
-  // it is reused or when the timing is read.
+  // Timing of the last kTimingSlots synchronous calls: each call's kernels
+  // write the GPU's real-time counter into its slot of tring (device memory,
+  // kTimingSlots x kStampWords; see stamp_start), so that back-to-back calls
+  // are timed with no host event and no synchronisation per call.  The
+  // pending slots are read back together (one copy after the stream has
+  // drained) when the ring comes round to a pending slot, or when the
+  // timing or the stats are read.
+  // With timing_events (masw_opts) a slot's call records HIP events instead
+  // (start, sweep start, sweep end; the fused launch has no sweep start).
   struct TimingSlot {
-    hipEvent_t ev[3] = {};
     bool pending = false;
-    bool fused = false;  // a fused launch: no staging, no ev[1]
+    bool events = false;
+    bool fused = false;
+    hipEvent_t ev[3] = {};
     float sweep_ms = 0.f, total_ms = 0.f;
   };
-  static constexpr int kTimingSlots = 64;
+  static constexpr int kTimingSlots = 256;
+  static constexpr int kStampWords = 4;  // start, sweep start, end, unused
   TimingSlot tslot[kTimingSlots];
+  unsigned long long* tring = nullptr;                  // device
+  unsigned long long tring_host[kTimingSlots * kStampWords] = {};
+  int rtc_khz = 0;  // real-time counter rate (hipDeviceAttributeWallClockRate)
+  bool timing_events = false;  // masw_opts::timing_events (slot events created on first use)
   int tslot_next = 0;
   int tslot_last = -1;
   masw_timing timing = {};

@@ -79,6 +79,7 @@ __global__ __launch_bounds__(64 * kInertiaWaves) __attribute__((amdgpu_waves_per
 void MASW_INERTIA_KERNEL(SweepArgs a, int chunk) {
   __shared__ unsigned long long s_cnt[kInertiaWaves][7];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  stamp_start(a.tstamp, 1);
   Tally t;
   if (chunk <= 1) {
     const int W = gridDim.x * kInertiaWaves;
@@ -129,6 +130,7 @@ void MASW_INERTIA_KERNEL(SweepArgs a, int chunk) {
       atomicAdd(dst[threadIdx.x], sum);
     }
   }
+  stamp_end(a.tstamp);
 }
 
 }  // namespace

@@ -140,6 +140,8 @@ struct SweepArgs {
   const double* f_lambda;
   const double* f_c;
   int32_t f_n_c;
+  // Launch timing (null: not timed): see stamp_start / stamp_end.
+  unsigned long long* tstamp;
 };
 constexpr int kFusedG = 8;              // wavefronts per workgroup of a fused launch
 constexpr int kFusedMaxLayers = 64;     // layers of a model that a fused launch stages in LDS
@@ -184,7 +186,28 @@ struct PrepArgs {
   uint32_t* grid_flags;  // [ceil(n_c / kPrepThreads)] 1 where a block of the grid failed its checks
   int32_t* model_left;   // fused misfit: [n_models] set to each model's wavelength count (else null)
   double* misfit;        // fused misfit: [n_models], NaN written here for a model with no wavelength
+  unsigned long long* tstamp;  // launch timing of the job (null: not timed): its start
 };
+
+// Launch timing from the GPU's constant-rate real-time counter
+// (s_memrealtime, the device's wall-clock rate), without host events: a
+// timed job's slot holds [0] the start of its first kernel, [1] the start
+// of its sweep (or inertia) kernel and [2] the end of that kernel's last
+// workgroup.  Workgroup 0 of a launch is dispatched first, so its start
+// stands for the launch's; the end is the largest of every workgroup's end
+// (an atomic maximum, which needs no reset between uses of a slot since the
+// counter only grows).
+// (With j >= 0 the same reading goes to slot words i and j.)
+__device__ __forceinline__ void stamp_start(unsigned long long* ts, int i, int j = -1) {
+  if (ts && blockIdx.x == 0 && threadIdx.x == 0) {
+    const unsigned long long t = __builtin_amdgcn_s_memrealtime();
+    ts[i] = t;
+    if (j >= 0) ts[j] = t;
+  }
+}
+__device__ __forceinline__ void stamp_end(unsigned long long* ts) {
+  if (ts && threadIdx.x == 0) atomicMax(ts + 2, (unsigned long long)__builtin_amdgcn_s_memrealtime());
+}
 
 // Where one item's search stands.  The batch kernels keep it in registers;
 // the serving tick kernel keeps it in HBM between ticks.

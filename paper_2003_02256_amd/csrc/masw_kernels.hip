@@ -135,6 +135,7 @@ __device__ void build_model(const PrepArgs& a, int m, int single_N, int single_W
 __global__ __launch_bounds__(kPrepThreads) void prep_front_kernel(PrepArgs a, CoopInitArgs ci, int nb_grid,
                                                                   int nb_models, int nb_clear, int single_N,
                                                                   int single_W) {
+  stamp_start(a.tstamp, 0);
   const int b = blockIdx.x;
   if (b < nb_grid) {
     const int i = b * kPrepThreads + int(threadIdx.x);
@@ -278,6 +279,7 @@ constexpr int kSmallGrid = 16 * kLamBlock;
 
 __global__ __launch_bounds__(kLamBlock) void prep_small_kernel(PrepArgs a, CoopInitArgs ci, int single_N,
                                                                int single_W) {
+  stamp_start(a.tstamp, 0);
   __shared__ LambdaShared ls;
   const int t = threadIdx.x;
   int bad = 0;

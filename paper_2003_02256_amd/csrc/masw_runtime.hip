@@ -196,19 +196,43 @@ int pick_waves_per_item(masw_ctx* ctx, int mode, int64_t n_items, int* blocks) {
 }
 
 // Waits for a timed call's last event and adds its durations to the sums.
-hipError_t resolve_timing(masw_ctx* ctx, masw_ctx::TimingSlot& T) {
-  hipError_t e = hipEventSynchronize(T.ev[2]);
-  if (e == hipSuccess) e = hipEventElapsedTime(&T.total_ms, T.ev[0], T.ev[2]);
-  if (e == hipSuccess && !T.fused) e = hipEventElapsedTime(&T.sweep_ms, T.ev[1], T.ev[2]);
-  if (e != hipSuccess) return e;
-  if (T.fused) T.sweep_ms = T.total_ms;  // one launch: the sweep with its staging
-  T.pending = false;
+// Resolves every pending timing slot into the running sums, oldest first:
+// a slot timed by the real-time counter from one read-back of the ring
+// (their calls ran on last_stream, or on a stream that claim_arena has since
+// drained), a slot timed by events from its events.
+hipError_t resolve_timing(masw_ctx* ctx) {
+  bool stamps = false;
+  for (const auto& T : ctx->tslot) stamps = stamps || (T.pending && !T.events);
+  if (stamps) {
+    hipError_t e = hipMemcpyAsync(ctx->tring_host, ctx->tring, sizeof(ctx->tring_host), hipMemcpyDeviceToHost,
+                                  ctx->last_stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->last_stream);
+    if (e != hipSuccess) return e;
+  }
+  const double per_ms = double(ctx->rtc_khz);  // counter ticks per millisecond
   masw_timing& t = ctx->timing;
-  t.sweep_ms_min = t.launches ? std::min(t.sweep_ms_min, T.sweep_ms) : T.sweep_ms;
-  t.sweep_ms_max = t.launches ? std::max(t.sweep_ms_max, T.sweep_ms) : T.sweep_ms;
-  t.sweep_ms_sum += T.sweep_ms;
-  t.total_ms_sum += T.total_ms;
-  ++t.launches;
+  for (int k = 0; k < masw_ctx::kTimingSlots; ++k) {
+    const int i = (ctx->tslot_next + k) % masw_ctx::kTimingSlots;
+    masw_ctx::TimingSlot& T = ctx->tslot[i];
+    if (!T.pending) continue;
+    if (T.events) {
+      hipError_t e = hipEventSynchronize(T.ev[2]);
+      if (e == hipSuccess) e = hipEventElapsedTime(&T.total_ms, T.ev[0], T.ev[2]);
+      if (e == hipSuccess && !T.fused) e = hipEventElapsedTime(&T.sweep_ms, T.ev[1], T.ev[2]);
+      if (e != hipSuccess) return e;
+      if (T.fused) T.sweep_ms = T.total_ms;  // one launch: the sweep with its staging
+    } else {
+      const unsigned long long* w = ctx->tring_host + size_t(i) * masw_ctx::kStampWords;
+      T.total_ms = w[2] > w[0] ? float(double(w[2] - w[0]) / per_ms) : 0.f;
+      T.sweep_ms = w[2] > w[1] ? float(double(w[2] - w[1]) / per_ms) : 0.f;
+    }
+    T.pending = false;
+    t.sweep_ms_min = t.launches ? std::min(t.sweep_ms_min, T.sweep_ms) : T.sweep_ms;
+    t.sweep_ms_max = t.launches ? std::max(t.sweep_ms_max, T.sweep_ms) : T.sweep_ms;
+    t.sweep_ms_sum += T.sweep_ms;
+    t.total_ms_sum += T.total_ms;
+    ++t.launches;
+  }
   return hipSuccess;
 }
 
@@ -372,14 +396,21 @@ int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t fl
     sw.f_n_c = in.n_c;
   }
 
+  // timed (a slot of the stamp ring) unless no-alloc or without a sweep
   masw_ctx::TimingSlot* T = nullptr;
   const int ts = ctx->tslot_next;
-  if (!ws.noalloc) {
+  if (!ws.noalloc && in.n_lam > 0) {
     T = &ctx->tslot[ts];
-    if (T->pending) MASW_HIP(resolve_timing(ctx, *T));
+    if (T->pending) MASW_HIP(resolve_timing(ctx));
     ctx->tslot_next = (ts + 1) % masw_ctx::kTimingSlots;
+    T->events = ctx->timing_events;
     T->fused = fused;
-    MASW_HIP(hipEventRecord(T->ev[0], s));
+    if (T->events) {
+      MASW_HIP(hipEventRecord(T->ev[0], s));
+    } else {
+      p.tstamp = ctx->tring + size_t(ts) * masw_ctx::kStampWords;
+      sw.tstamp = p.tstamp;
+    }
   }
   if (!fused) MASW_HIP(launch_prep(p, ci, in.single_N, in.single_W, s));
 
@@ -411,12 +442,12 @@ int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t fl
     sw.model_left = p.model_left;
     sw.lambda_off = p.lambda_off;
   }
-  if (T && !fused) MASW_HIP(hipEventRecord(T->ev[1], s));
+  if (T && T->events && !fused) MASW_HIP(hipEventRecord(T->ev[1], s));
   if (fused)
     MASW_HIP(launch_fused(mode, blocks, s, sw));
   else if (in.n_lam > 0)
     MASW_HIP(inertia ? launch_inertia(sw, ctx->cus, s, &blocks) : launch_sweep(mode, G, blocks, s, sw));
-  if (T) MASW_HIP(hipEventRecord(T->ev[2], s));
+  if (T && T->events) MASW_HIP(hipEventRecord(T->ev[2], s));
   if (in.misfit && inertia)
     MASW_HIP(launch_misfit(in.n_models, p.lambda_off, sw.out_ct, c_e_dev, misfit_dev, s));
   // optional diagnostic after the timed sweep: the FP64 noise band of each
@@ -425,8 +456,8 @@ int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t fl
     MASW_HIP(launch_noise_check(p.models, p.layers64, p.c64, p.lam_k, p.lam_model, sw.out_idx, sw.out_status,
                                 in.n_lam, ctx->noise_threshold, s));
   if (ws.noalloc) return MASW_OK;
-  T->pending = true;
-  ctx->tslot_last = ts;
+  if (T) T->pending = true;
+  ctx->tslot_last = T ? ts : -1;
   ctx->last = masw_stats{};
   ctx->last.n_lambda = uint64_t(in.n_lam);
   ctx->last.waves_per_item = fused ? kFusedG : G;
@@ -500,9 +531,7 @@ int masw_create(int device, size_t hbm_budget_bytes, masw_ctx** out) {
   ctx->device = device;
   auto cleanup = [&](int code, const std::string& msg) {
     if (ctx->arena) (void)hipFree(ctx->arena);
-    for (auto& t : ctx->tslot)
-      for (auto& e : t.ev)
-        if (e) (void)hipEventDestroy(e);
+    if (ctx->tring) (void)hipFree(ctx->tring);
     for (auto& e : ctx->cls_ev)
       if (e) (void)hipEventDestroy(e);
     delete ctx;
@@ -513,13 +542,15 @@ int masw_create(int device, size_t hbm_budget_bytes, masw_ctx** out) {
     return cleanup(MASW_EDEVICE, "cannot look up the no-alloc scratch array on this device");
   if (hipDeviceGetAttribute(&ctx->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
     return cleanup(MASW_EDEVICE, "cannot query compute units");
-  // The timing events only time launches (outputs reach the host through
-  // their own copies and synchronisations): a device-scope release spares
-  // each of them a system-scope cache writeback between the kernels.
-  for (auto& t : ctx->tslot)
-    for (auto& e : t.ev)
-      if (hipEventCreateWithFlags(&e, hipEventReleaseToDevice) != hipSuccess)
-        return cleanup(MASW_EDEVICE, "hipEventCreate failed");
+  if (hipDeviceGetAttribute(&ctx->rtc_khz, hipDeviceAttributeWallClockRate, device) != hipSuccess ||
+      ctx->rtc_khz <= 0)
+    return cleanup(MASW_EDEVICE, "cannot query the real-time counter rate");
+  if (hipMalloc(&ctx->tring, sizeof(ctx->tring_host)) != hipSuccess ||
+      hipMemset(ctx->tring, 0, sizeof(ctx->tring_host)) != hipSuccess)
+    return cleanup(MASW_ENOMEM, "cannot allocate the timing slots");
+  // The classification's events only time its launch (outputs reach the
+  // host through their own copies and synchronisations): a device-scope
+  // release spares each of them a system-scope cache writeback.
   for (auto& e : ctx->cls_ev)
     if (hipEventCreateWithFlags(&e, hipEventReleaseToDevice) != hipSuccess)
       return cleanup(MASW_EDEVICE, "hipEventCreate failed");
@@ -561,6 +592,7 @@ void masw_destroy(masw_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   if (ctx->last_valid) (void)hipStreamSynchronize(ctx->last_stream);
   if (ctx->arena) (void)hipFree(ctx->arena);
+  if (ctx->tring) (void)hipFree(ctx->tring);
   for (auto& t : ctx->tslot)
     for (auto& e : t.ev)
       if (e) (void)hipEventDestroy(e);
@@ -990,9 +1022,18 @@ int masw_set_opts(masw_ctx* ctx, const masw_opts* opts) {
     return fail(MASW_EINVAL, "opts: shared_window must be -1 or in [0, 1024]");
   if (!(o.first_item_priority == 0 || o.first_item_priority == -1))
     return fail(MASW_EINVAL, "opts: first_item_priority must be 0 or -1");
-  if (o.reserved != 0) return fail(MASW_EINVAL, "opts: reserved must be 0");
+  if (!(o.timing_events == 0 || o.timing_events == 1)) return fail(MASW_EINVAL, "opts: timing_events must be 0 or 1");
   if (!ctx) return fail(MASW_EINVAL, "ctx: null context");
   std::lock_guard<std::mutex> lock(ctx->mu);
+  if (o.timing_events && !ctx->tslot[0].ev[0]) {
+    // the slots' events, on first use (device-scope release: they only time
+    // launches, so they need no system-scope cache writeback)
+    MASW_HIP(hipSetDevice(ctx->device));
+    for (auto& t : ctx->tslot)
+      for (auto& e : t.ev)
+        if (!e) MASW_HIP(hipEventCreateWithFlags(&e, hipEventReleaseToDevice));
+  }
+  ctx->timing_events = o.timing_events == 1;
   ctx->refine_rel = tol;
   ctx->noise_threshold = thr;
   ctx->forced_waves = g;
@@ -1011,6 +1052,7 @@ int masw_get_opts(masw_ctx* ctx, masw_opts* out) {
   o.waves_per_item = ctx->forced_waves;
   o.shared_window = ctx->shared_sweeps ? ctx->shared_window : -1;
   o.first_item_priority = ctx->first_item_priority ? 0 : -1;
+  o.timing_events = ctx->timing_events ? 1 : 0;
   *out = o;
   return MASW_OK;
 }
@@ -1064,7 +1106,7 @@ int masw_get_stats(masw_ctx* ctx, masw_stats* out) {
     }
     if (ctx->tslot_last >= 0) {
       masw_ctx::TimingSlot& T = ctx->tslot[ctx->tslot_last];
-      if (T.pending) MASW_HIP(resolve_timing(ctx, T));
+      if (T.pending) MASW_HIP(resolve_timing(ctx));
       ctx->last.sweep_ms = T.sweep_ms;
       ctx->last.total_ms = T.total_ms;
     }
@@ -1078,11 +1120,7 @@ int masw_get_timing(masw_ctx* ctx, int reset, masw_timing* out) {
   if (!ctx || !out) return fail(MASW_EINVAL, "null argument");
   std::lock_guard<std::mutex> lock(ctx->mu);
   MASW_HIP(hipSetDevice(ctx->device));
-  // resolve in call order: the oldest pending slot follows the newest one
-  for (int k = 0; k < masw_ctx::kTimingSlots; ++k) {
-    masw_ctx::TimingSlot& T = ctx->tslot[(ctx->tslot_next + k) % masw_ctx::kTimingSlots];
-    if (T.pending) MASW_HIP(resolve_timing(ctx, T));
-  }
+  MASW_HIP(resolve_timing(ctx));
   *out = ctx->timing;
   if (reset) ctx->timing = masw_timing{};
   return MASW_OK;

@@ -735,6 +735,7 @@ void sweep_kernel(SweepArgs a) {
   __shared__ double s_mis[MISFIT ? 256 : 1];  // fused misfit reduction
   WorkCount wc;
   constexpr int P = 64 * G;
+  stamp_start(a.tstamp, 1);
   // Queue positions below gridDim.x (the launch has at most one workgroup
   // per item) are taken by workgroup index, the rest from the atomic queue:
   // a launch with no more items than workgroups makes no claim at all.
@@ -780,6 +781,7 @@ void sweep_kernel(SweepArgs a) {
   __builtin_amdgcn_s_setprio(0);
   if (a.n_coop > 0) join_sweeps<MODE, G>(a, sh, wc);
   flush_counts(a.counters, a.wg_counts, wc);
+  stamp_end(a.tstamp);
 }
 
 
@@ -799,6 +801,7 @@ __global__ __launch_bounds__(64 * kFusedG) void fused_sweep_kernel(SweepArgs a) 
   const int N = a.fused_N, n_c = a.f_n_c, tid = threadIdx.x;
   LayerRec64* L64 = reinterpret_cast<LayerRec64*>(fused_lds);
   LayerRec32* L32 = reinterpret_cast<LayerRec32*>(fused_lds + sizeof(LayerRec64) * size_t(N + 1));
+  stamp_start(a.tstamp, 0, 1);  // the job is this one launch
   if (tid == 0) s_below = 0;
   // the model: checks and records (build_model's)
   const double be_hs = a.f_beta[N];
@@ -871,6 +874,7 @@ __global__ __launch_bounds__(64 * kFusedG) void fused_sweep_kernel(SweepArgs a) 
     run_item<MODE, G>(r, st, 0x7fffffff, sh, wc, o, kNoCoop, a.counters);
   }
   flush_counts(a.counters, a.wg_counts, wc);
+  stamp_end(a.tstamp);
 }
 
 // Dynamic LDS of a fused launch: the model's FP64 and FP32 records.

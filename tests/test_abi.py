@@ -216,7 +216,7 @@ def test_opts_validate_on_host(lib):
                         (dict(noise_threshold=2.0), "noise_threshold"), (dict(noise_threshold=-1.0), "noise_threshold"),
                         (dict(waves_per_item=3), "waves_per_item"), (dict(shared_window=2000), "shared_window"),
                         (dict(shared_window=-2), "shared_window"), (dict(first_item_priority=1), "first_item_priority"),
-                        (dict(), "ctx")):
+                        (dict(timing_events=2), "timing_events"), (dict(), "ctx")):
         with pytest.raises(M.MaswError) as e:
             M.masw_set_opts(None, **kwargs)
         assert e.value.code == M.MASW_EINVAL and msg in str(e.value), (kwargs, str(e.value))

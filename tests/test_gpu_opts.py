@@ -22,11 +22,11 @@ def ctx(gpu):
 
 def test_defaults_and_round_trip(ctx):
     assert M.masw_get_opts(ctx.ctx) == {"refine_rel_tol": 1e-9, "noise_threshold": 1e-2, "waves_per_item": 0,
-                                         "shared_window": 8, "first_item_priority": 0}
+                                         "shared_window": 8, "first_item_priority": 0, "timing_events": 0}
     M.masw_set_opts(ctx.ctx, refine_rel_tol=1e-12, noise_threshold=0.5, waves_per_item=4, shared_window=-1,
-                    first_item_priority=-1)
+                    first_item_priority=-1, timing_events=1)
     assert M.masw_get_opts(ctx.ctx) == {"refine_rel_tol": 1e-12, "noise_threshold": 0.5, "waves_per_item": 4,
-                                         "shared_window": -1, "first_item_priority": -1}
+                                         "shared_window": -1, "first_item_priority": -1, "timing_events": 1}
     M.masw_set_opts(ctx.ctx)                      # defaults again
     assert M.masw_get_opts(ctx.ctx)["refine_rel_tol"] == 1e-9
 
@@ -47,7 +47,7 @@ def test_schedule_options_leave_results_unchanged(ctx):
     m, lam, c = wl.models[0], wl.lambdas[0][::10], wl.c_test
     base = ctx.curve(c, lam, m, prec=M.MASW_PREC_FP64)
     for kw in (dict(waves_per_item=2), dict(waves_per_item=16), dict(shared_window=-1),
-               dict(shared_window=1, first_item_priority=-1)):
+               dict(shared_window=1, first_item_priority=-1), dict(timing_events=1)):
         M.masw_set_opts(ctx.ctx, **kw)
         got = ctx.curve(c, lam, m, prec=M.MASW_PREC_FP64)
         for a, b in zip(base, got):

@@ -442,11 +442,32 @@ def test_shared_sweeps_one_wavefront_per_item(torch_dev):
             np.testing.assert_array_equal(x, y)
 
 
-def test_timing_of_back_to_back_calls(torch_dev, ctx):
-    # calls issued without synchronising in between are each timed by the
-    # library's events; outputs of the last call are those of a single call
-    wl = WL.two_layer_case()
-    m, lam, c = wl.models[0], wl.lambdas[0], wl.c_test
+@pytest.mark.parametrize("events", [0, 1])
+@pytest.mark.parametrize("case", ["fused", "staged"])
+def test_timing_of_back_to_back_calls(torch_dev, ctx, case, events):
+    # calls issued without synchronising in between are each timed, from the
+    # GPU's real-time counter or from HIP events (masw_opts.timing_events),
+    # through more calls than the library has timing slots; outputs of the
+    # last call are those of a single call.  The two-layer curve runs as one
+    # fused launch (sweep time = job time); a 20-wavelength slice of the
+    # fine-scale curve is staged before its sweep (job time > sweep time).
+    if case == "fused":
+        wl = WL.two_layer_case()
+        m, lam, c = wl.models[0], wl.lambdas[0], wl.c_test
+        n = 300
+    else:
+        wl = WL.fine_scale_case()
+        m, lam, c = wl.models[0], wl.lambdas[0][::50], wl.c_test
+        n = 270
+    M.masw_set_opts(ctx.ctx, timing_events=events)
+    try:
+        _timing_run(torch_dev, ctx, case, c, lam, m, n, events)
+    finally:
+        M.masw_set_opts(ctx.ctx)  # the module's context keeps its default options
+
+
+def _timing_run(torch_dev, ctx, case, c, lam, m, n, events):
+    assert M.masw_get_opts(ctx.ctx)["timing_events"] == events
     want = dev_curve(torch_dev, ctx, c, lam, m, M.MASW_PREC_FP64)
     torch, dev = torch_dev
     t = lambda x: torch.as_tensor(np.ascontiguousarray(x, np.float64), device=dev)
@@ -455,13 +476,18 @@ def test_timing_of_back_to_back_calls(torch_dev, ctx):
     out = (torch.empty(W, dtype=torch.float64, device=dev), torch.empty(W, dtype=torch.int32, device=dev),
            torch.empty(W, dtype=torch.int32, device=dev), torch.empty(W, dtype=torch.float64, device=dev))
     M.masw_get_timing(ctx.ctx, reset=True)
-    n = 100  # more than the library's 64 event slots
     for _ in range(n):
         M.masw_dispersion_curve(ctx.ctx, *args, M.MASW_PREC_FP64, 0, None, *out)
+    st = M.masw_get_stats(ctx.ctx)
     tm = M.masw_get_timing(ctx.ctx, reset=True)
     assert tm["launches"] == n
-    assert 0.0 < tm["sweep_ms_min"] <= tm["sweep_ms_max"]
+    assert 0.0 < tm["sweep_ms_min"] <= tm["sweep_ms_max"] < 1e3
     assert tm["sweep_ms_min"] * n <= tm["sweep_ms_sum"] + 1e-9 <= tm["total_ms_sum"] + 1e-6
+    assert 0.0 < st["sweep_ms"] <= st["total_ms"]
+    if case == "staged":
+        assert st["fused_staging"] == 0 and tm["total_ms_sum"] > tm["sweep_ms_sum"]
+    else:
+        assert st["fused_staging"] == 1 and abs(tm["total_ms_sum"] - tm["sweep_ms_sum"]) <= 1e-6 * n
     assert M.masw_get_timing(ctx.ctx)["launches"] == 0
     torch.cuda.synchronize()
     for x, y in zip(want, (o.cpu().numpy() for o in out)):
