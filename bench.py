@@ -85,14 +85,14 @@ def classify_flops(evals: int, layers: int, steps: int) -> float:
 # classification), the workload and the
 # launch, so a changed kernel reports null until it is measured again.
 MEASURED_TRAFFIC = {
-    ("e60705128af84d5c", "fine_scale_N20_1000lam_115001c", "sweep_kernel<FP64,G=8>"):
-        4939.56 * 1024 * 2.000 + 2579.36 * 1024 * 1.000,
-    ("e60705128af84d5c", "batch_4096models_19001c", "sweep_kernel<FP64,G=1>"):
-        267717.09 * 1024 * 2.000 + 147027.62 * 1024 * 1.000,
-    ("17b17b04f332626b", "fine_scale_N20_1000lam_115001c", "inertia_lone_kernel"):
-        889.90 * 1024 * 2.000 + 46.875 * 1024 * 1.000,
-    ("17b17b04f332626b", "batch_4096models_19001c", "inertia_kernel"):
-        49503.25 * 1024 * 2.000 + 1010303.53 * 1024 * 1.000,
+    ("4e502a09f3d5959a", "fine_scale_N20_1000lam_115001c", "sweep_kernel<FP64,G=8>"):
+        4890.39 * 1024 * 2.000 + 2585.17 * 1024 * 1.000,
+    ("4e502a09f3d5959a", "batch_4096models_19001c", "sweep_kernel<FP64,G=1>"):
+        267238.81 * 1024 * 2.000 + 147567.77 * 1024 * 1.000,
+    ("31a58e2a8353c3d3", "fine_scale_N20_1000lam_115001c", "inertia_lone_kernel"):
+        902.00 * 1024 * 2.000 + 50.80 * 1024 * 1.000,
+    ("31a58e2a8353c3d3", "batch_4096models_19001c", "inertia_kernel"):
+        55078.56 * 1024 * 2.000 + 1205151.92 * 1024 * 1.000,
     ("ef681d38c885d05d", "classify_batch_4096models_19001c", "classify_kernel"):
         14642.625 * 1024 * 2.000 + 21872.34 * 1024 * 1.000,
 }
