@@ -699,8 +699,11 @@ def measure_curves(M, torch, wl, steps: int, warmup: int, inertia: bool = True) 
             "curves_per_s": n_curves / wall32, "wavelengths_per_s": wl.n_lambda_total / wall32,
             "sweep_evals": st32["sweep_evals"], "check_evals": st32["check_evals"],
             "refine_evals": st32["refine_evals"], "sweep_kernel_ms": sweep32,
-            "kernel": ("fused_sweep_kernel<split>" if st32.get("fused_staging")
+            "kernel": (("fused_sweep_kernel<FP64>" if st32.get("fused_staging")
+                        else f"sweep_kernel<FP64,G={st32['waves_per_item']}>") if st32.get("split_as_fp64")
+                       else "fused_sweep_kernel<split>" if st32.get("fused_staging")
                        else f"sweep_kernel<split,G={st32['waves_per_item']}>"),
+            "split_as_fp64": bool(st32.get("split_as_fp64")),
             "achieved_tflops_fp64_counted": achieved32,
             "idx_mismatch_vs_fp64": int(np.sum((idx64 != idx32))),
             "root_rel_err_vs_fp64_max": float(root_rel.max()) if root_rel.size else None,

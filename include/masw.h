@@ -89,8 +89,13 @@ enum {
  *                  grid at or above the half-space's S velocity is walked in
  *                  FP64, and the refinement is FP64.  So idx is Algorithm 1's
  *                  FP64 pick, as with MASW_PREC_FP64, outside the FP64 noise
- *                  band.                                                      */
+ *                  band.  A curve or batch call whose grid has fewer than
+ *                  MASW_SPLIT_MIN_GRID points runs as MASW_PREC_FP64 (two
+ *                  rounds of a small launch's sweep cover such a grid, so
+ *                  the FP32 sweep saves none of them, and its FP64 re-check
+ *                  window would add one); masw_stats.split_as_fp64 says so. */
 enum { MASW_PREC_FP64 = 0, MASW_PREC_SPLIT = 1 };
+#define MASW_SPLIT_MIN_GRID 1025
 /* A plain integer, not the enum type, so that any value a caller passes is
  * well defined on both sides of the ABI; others are rejected (MASW_EINVAL). */
 typedef int32_t masw_precision;
@@ -198,7 +203,9 @@ typedef struct {
     int32_t fused_staging;    /* 1: a small single-curve launch that staged its
                                  model, grid and wavelengths inside the sweep
                                  kernel (one launch; sweep_ms = total_ms)      */
-    int32_t reserved;         /* 0                                             */
+    int32_t split_as_fp64;    /* 1: a MASW_PREC_SPLIT call on a grid of at most
+                                 MASW_SPLIT_MIN_GRID - 1 points, run as the
+                                 FP64 walk (see MASW_PREC_SPLIT)              */
 } masw_stats;
 
 /* Options of a context.  A zero field keeps its default, so a

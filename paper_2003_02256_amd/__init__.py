@@ -87,10 +87,10 @@ class masw_stats(ctypes.Structure):
                 ("classify_layers", ctypes.c_uint64), ("classify_steps", ctypes.c_uint64),
                 ("inertia_evals", ctypes.c_uint64), ("inertia_entries", ctypes.c_uint64),
                 ("inertia_pivots", ctypes.c_uint64), ("fused_staging", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("split_as_fp64", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class masw_opts(ctypes.Structure):

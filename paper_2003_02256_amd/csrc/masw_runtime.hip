@@ -349,7 +349,10 @@ int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t fl
   if (!b.ok()) return fail(MASW_ENOMEM, "workspace exceeds the HBM budget");
 
   const bool inertia = (flags & MASW_SEARCH_INERTIA) != 0;
-  const int mode = prec == MASW_PREC_SPLIT ? 1 : 0;
+  // a split call on a grid that two rounds of a small launch cover runs as
+  // the FP64 walk (include/masw.h, MASW_PREC_SPLIT)
+  const bool split_as_fp64 = prec == MASW_PREC_SPLIT && int64_t(in.n_c) < int64_t(MASW_SPLIT_MIN_GRID);
+  const int mode = (prec == MASW_PREC_SPLIT && !split_as_fp64) ? 1 : 0;
   int blocks = 1;
   const int G = inertia ? 1 : pick_waves_per_item(ctx, mode, in.n_lam, &blocks);
 
@@ -463,6 +466,7 @@ int run_curves(masw_ctx* ctx, const Inputs& in, masw_precision prec, uint32_t fl
   ctx->last.waves_per_item = fused ? kFusedG : G;
   ctx->last_fused = fused;
   ctx->last.fused_staging = fused ? 1 : 0;
+  ctx->last.split_as_fp64 = split_as_fp64 ? 1 : 0;
   ctx->last.workgroups = in.n_lam > 0 ? blocks : 0;
   ctx->wg_counts = sw.wg_counts;
   ctx->wg_rows = in.n_lam > 0 ? blocks : 0;

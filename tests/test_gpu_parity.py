@@ -220,6 +220,27 @@ def test_device_side_validation_marks_invalid(torch_dev, ctx):
     assert st[3] == M.MASW_STATUS_INVALID and np.all(np.delete(st, 3) == 0)
 
 
+def test_split_on_short_grids_runs_the_fp64_walk(torch_dev, ctx):
+    # a split call on a grid of fewer than MASW_SPLIT_MIN_GRID points runs as
+    # the FP64 walk (bitwise its outputs) and says so; from that size on it
+    # sweeps in FP32, with the same picks
+    wl = WL.two_layer_case()
+    m, lam = wl.models[0], wl.lambdas[0]
+    for n, as_fp64 in ((801, 1), (1024, 1), (1025, 0), (1601, 0)):
+        c = WL.uniform_grid(50.0, 400.0 / (n - 1), n)
+        want = dev_curve(torch_dev, ctx, c, lam, m, M.MASW_PREC_FP64)
+        assert M.masw_get_stats(ctx.ctx)["split_as_fp64"] == 0
+        got = dev_curve(torch_dev, ctx, c, lam, m, M.MASW_PREC_SPLIT)
+        st = M.masw_get_stats(ctx.ctx)
+        assert st["split_as_fp64"] == as_fp64, n
+        if as_fp64:
+            for x, y in zip(got, want):
+                np.testing.assert_array_equal(x, y, err_msg=f"n_c {n}")
+        else:
+            np.testing.assert_array_equal(got[1], want[1], err_msg=f"n_c {n}")
+            assert st["check_evals"] > 0
+
+
 def test_fused_small_launches_equal_staged_launches(torch_dev, ctx):
     # Small single-curve launches stage the model, grid and wavelengths inside
     # the sweep kernel (one launch); with MASW_FUSED_SMALL=0 a context stages
