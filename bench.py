@@ -85,8 +85,8 @@ def classify_flops(evals: int, layers: int, steps: int) -> float:
 # classification), the workload and the
 # launch, so a changed kernel reports null until it is measured again.
 MEASURED_TRAFFIC = {
-    ("4e502a09f3d5959a", "fine_scale_N20_1000lam_115001c", "sweep_kernel<FP64,G=8>"):
-        4890.39 * 1024 * 2.000 + 2585.17 * 1024 * 1.000,
+    ("4e502a09f3d5959a", "fine_scale_N20_1000lam_115001c", "sweep_kernel<FP64,G=4>"):
+        8170.61 * 1024 * 2.000 + 4899.36 * 1024 * 1.000,
     ("4e502a09f3d5959a", "batch_4096models_19001c", "sweep_kernel<FP64,G=1>"):
         267238.81 * 1024 * 2.000 + 147567.77 * 1024 * 1.000,
     ("31a58e2a8353c3d3", "fine_scale_N20_1000lam_115001c", "inertia_lone_kernel"):
